@@ -1,0 +1,174 @@
+"""Seeded synthetic THC-CCSD inputs (orbital energies, Cholesky vectors, collocation factors).
+
+This module holds no arithmetic of the method itself: it only turns (seed, stream, index)
+into numbers with the shapes and value distributions of the workloads, so that the CPU
+oracle and the GPU library can be fed identical inputs.  Nothing here imports either side.
+
+Generator: a counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA 2014).  For a key k
+derived from (seed, stream), draw i is the SplitMix64 output function applied to the
+state k + (i+1)*0x9E3779B97F4A7C15.  Uniforms take the top 53 bits, normals come from the
+Box-Muller transform of two consecutive uniforms (cosine branch only).
+
+Value distributions (paper Sec. II, Eq. 1 ordering N_o < N_v < N_CD ~ N_THC ~ N_aux):
+  eps_o ~ U[-1.5, -0.3] Eh, eps_v ~ U[0.1, 5.0] Eh, each sorted ascending;
+  L^K_pq = gamma * N(0,1) * exp(-K/decay), symmetric in pq (upper triangle drawn, mirrored);
+  X_o, X_v ~ N(0,1)/sqrt(N_P) (amplitude collocation, the y factors of Eq. 22-23);
+  x_o, x_v ~ N(0,1)/sqrt(N_Q) (ovov ERI collocation, the x factors of Eq. 17).
+gamma is one global scale fixed so that gamma^2 * lambda_max(L_ov L_ov^T) = 0.2 * Delta_min,
+Delta_min = 2 (min eps_v - max eps_o); without it the unit-variance vectors give amplitudes
+of order 10 and no coupled-cluster iteration converges.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+STREAM_EPS_O, STREAM_EPS_V, STREAM_L, STREAM_XO_AMP, STREAM_XV_AMP, STREAM_XO_ERI, STREAM_XV_ERI = range(7)
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on a uint64 array (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def _key(seed: int, stream: int) -> np.uint64:
+    with np.errstate(over="ignore"):
+        s = _mix(np.array([stream], dtype=np.uint64) + _GOLDEN)
+        k = _mix(np.array([seed], dtype=np.uint64) * _GOLDEN ^ s)
+    return k[0]
+
+
+def bits(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
+    """Raw 64-bit draws for counter values idx (any integer array)."""
+    k = _key(seed, stream)
+    idx = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix(k + (idx + np.uint64(1)) * _GOLDEN)
+
+
+def uniform(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
+    """Uniforms in the open interval (0, 1) from the top 53 bits."""
+    b = bits(seed, stream, idx) >> np.uint64(11)
+    return (b.astype(np.float64) + 0.5) * (1.0 / 9007199254740992.0)
+
+
+def normal(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
+    """Standard normals; normal i consumes uniforms 2i and 2i+1 (Box-Muller, cosine branch)."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    u1 = uniform(seed, stream, idx * np.uint64(2))
+    u2 = uniform(seed, stream, idx * np.uint64(2) + np.uint64(1))
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+@dataclass(frozen=True)
+class Config:
+    """Sizes of one synthetic system: occupied o, virtual v, Cholesky rank nL,
+    amplitude THC rank nP, ERI THC grid nQ; Cholesky decay length; seed."""
+    name: str
+    o: int
+    v: int
+    nL: int
+    nP: int
+    nQ: int
+    decay: float = 30.0
+    seed: int = 1000
+    gamma: float | None = None  # None: the lambda_max rule above
+
+    @property
+    def n(self) -> int:
+        return self.o + self.v
+
+
+# The workloads: tiny oracle scale, the plain FP64 GPU scale, the mixed-precision scale,
+# the ~2500-basis-function single-GPU scale, and two extra parity sizes.
+CONFIGS = {
+    "tiny": Config("tiny", 10, 40, 150, 120, 300, 30.0, 1000),
+    "fp64": Config("fp64", 50, 450, 1500, 1000, 2500, 150.0, 1001),
+    "mixed": Config("mixed", 200, 1800, 6000, 4000, 10000, 600.0, 1002),
+    "paper": Config("paper", 350, 2150, 10000, 7000, 17500, 1000.0, 1003),
+    # parity-only sizes: several kernel tiles with ragged tails, oracle still fast
+    "small": Config("small", 6, 22, 70, 50, 110, 30.0, 1010),
+    "medium": Config("medium", 14, 66, 210, 170, 420, 30.0, 1011),
+}
+
+
+def learned_config(s: int) -> Config:
+    """System s (0..255) of the learned-guess set: o in [30, 80], v = 9o, nL = 30o,
+    nP = 20o, nQ = 50o; seed 2000 + s."""
+    o = 30 + int(bits(7, 0, np.array([s]))[0] % np.uint64(51))
+    return Config(f"learn{s}", o, 9 * o, 30 * o, 20 * o, 50 * o, 30.0, 2000 + s)
+
+
+def orbital_energies(cfg: Config) -> np.ndarray:
+    eo = -1.5 + 1.2 * uniform(cfg.seed, STREAM_EPS_O, np.arange(cfg.o))
+    ev = 0.1 + 4.9 * uniform(cfg.seed, STREAM_EPS_V, np.arange(cfg.v))
+    return np.concatenate([np.sort(eo), np.sort(ev)])
+
+
+def cholesky_unscaled(cfg: Config, dtype=np.float64) -> np.ndarray:
+    """L^K_pq / gamma as an (nL, n, n) array, symmetric in (p, q)."""
+    n = cfg.n
+    iu, ju = np.triu_indices(n)
+    flat = (iu * n + ju).astype(np.uint64)
+    out = np.empty((cfg.nL, n, n), dtype=dtype)
+    for K in range(cfg.nL):
+        vals = normal(cfg.seed, STREAM_L, np.uint64(K * n * n) + flat) * np.exp(-K / cfg.decay)
+        m = out[K]
+        m[iu, ju] = vals
+        m[ju, iu] = vals
+    return out
+
+
+def _lambda_max_ov(Lov: np.ndarray, iters: int = 200) -> float:
+    """Largest eigenvalue of the (ov x ov) Gram sum_K L^K (L^K)^T through the small
+    (nL x nL) Gram, by power iteration from a fixed start (deterministic)."""
+    M = Lov.reshape(Lov.shape[0], -1)
+    G = M @ M.T
+    x = np.ones(G.shape[0]) / np.sqrt(G.shape[0])
+    lam = 0.0
+    for _ in range(iters):
+        y = G @ x
+        lam = float(np.linalg.norm(y))
+        x = y / lam
+    return lam
+
+
+def make_system(cfg: Config) -> dict:
+    """All inputs of one system as FP64 numpy arrays:
+    eps (n), L (nL, n, n), Xo (o, nP), Xv (v, nP), xo (o, nQ), xv (v, nQ), gamma."""
+    o, v = cfg.o, cfg.v
+    eps = orbital_energies(cfg)
+    L = cholesky_unscaled(cfg)
+    if cfg.gamma is None:
+        dmin = 2.0 * (eps[o] - eps[o - 1])
+        lam = _lambda_max_ov(L[:, :o, o:])
+        gamma = float(np.sqrt(0.2 * dmin / lam))
+    else:
+        gamma = float(cfg.gamma)
+    L *= gamma
+    Xo = normal(cfg.seed, STREAM_XO_AMP, np.arange(o * cfg.nP)).reshape(o, cfg.nP) / np.sqrt(cfg.nP)
+    Xv = normal(cfg.seed, STREAM_XV_AMP, np.arange(v * cfg.nP)).reshape(v, cfg.nP) / np.sqrt(cfg.nP)
+    xo = normal(cfg.seed, STREAM_XO_ERI, np.arange(o * cfg.nQ)).reshape(o, cfg.nQ) / np.sqrt(cfg.nQ)
+    xv = normal(cfg.seed, STREAM_XV_ERI, np.arange(v * cfg.nQ)).reshape(v, cfg.nQ) / np.sqrt(cfg.nQ)
+    return dict(eps=eps, L=L, Xo=Xo, Xv=Xv, xo=xo, xv=xv, gamma=gamma, cfg=cfg)
+
+
+def complete_basis(o: int, v: int):
+    """Indicator collocation spanning the whole ov pair space: X_o[i, (i'a')] = delta_ii',
+    X_v[a, (i'a')] = delta_aa' (column index i'*v + a').  With it the Khatri-Rao product of
+    the factors is the identity on ov, so every projection is exact."""
+    Xo = np.zeros((o, o * v))
+    Xv = np.zeros((v, o * v))
+    for i in range(o):
+        for a in range(v):
+            Xo[i, i * v + a] = 1.0
+            Xv[a, i * v + a] = 1.0
+    return Xo, Xv
