@@ -1,0 +1,138 @@
+/*
+ * thc.h -- C ABI of the MI355X (gfx950) THC-CCSD hot path.
+ *
+ * Method: tensor-hypercontracted rank-reduced CCSD (Hohenstein, Fales, Parrish, Martinez,
+ * "Rank-reduced coupled-cluster III", arXiv:2111.11473).  The doubles amplitudes are
+ *   t_ij^ab = sum_WX y_i^W y_a^W Z^WX y_j^X y_b^X                         (paper Eq. 22-23)
+ * and the unknown core Z solves the projected CCSD doubles equations
+ *   sigma^WX = sum_ijab y_i^W y_a^W <Phi_ij^ab| e^-T H e^T |0> y_j^X y_b^X = 0   (Eq. 6),
+ * together with the usual singles equations, with the T1-transformed Hamiltonian (Eq. 24-27),
+ * Cholesky integrals (pq|rs) = sum_A L_pq^A L_rs^A and the least-squares THC form of (ia|jb)
+ * (Eq. 17-20) in the quadratic terms.
+ *
+ * Conventions
+ *  - Every array argument is a DEVICE pointer (memory on the GPU the context was created on),
+ *    row-major, FP64, owned by the caller; the library copies what it keeps.  Scalars returned
+ *    through pointers (energies, norms, iteration counts) are HOST pointers.
+ *  - Sizes: o occupied, v virtual, n = o + v orbitals, nL Cholesky vectors, nP amplitude THC
+ *    rank, nQ ERI THC grid points.
+ *  - All work is issued on the stream given to thc_create (a hipStream_t, e.g. torch's current
+ *    stream); functions that return host scalars synchronize that stream.
+ *  - Return value: THC_OK (0) or a negative error code; thc_last_error() gives a message.
+ *    No C++ exception crosses the ABI.  One context must not be used by two threads at once.
+ */
+#ifndef THC_H
+#define THC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define THC_OK 0
+#define THC_EINVAL (-1)     /* bad argument or option */
+#define THC_ENOMEM (-2)     /* device allocation failed */
+#define THC_EDEVICE (-3)    /* HIP runtime error */
+#define THC_ESINGULAR (-4)  /* metric S or ERI-grid Gram matrix not positive definite */
+#define THC_ENUMERIC (-5)   /* NaN/Inf in a residual or energy */
+#define THC_ENOTCONV (-6)   /* iteration limit reached */
+#define THC_ESTATE (-7)     /* call out of order (e.g. residual before build_factors) */
+
+/* Residual term groups (bit mask for thc_residual_terms), named by the paper's equations. */
+#define THC_TERM_EQ28 (1u << 0)   /* pp/hh/mixed ladders, Alg. 1 */
+#define THC_TERM_EQ29 (1u << 1)   /* bare integrals + Coulomb rings, Alg. 2 */
+#define THC_TERM_EQ31 (1u << 2)   /* remaining linear terms, Alg. 3 */
+#define THC_TERM_EQ32 (1u << 3)   /* T2^2 ladder + exchange (Eq. 32 + 33), Alg. 6 */
+#define THC_TERM_EQ35 (1u << 4)   /* T2^2 rings (Eq. 35-37), Alg. 7 */
+#define THC_TERM_EQ41 (1u << 5)   /* Fock + xi intermediates, Alg. 8-9 */
+#define THC_TERM_EQ38 (1u << 6)   /* singles, Alg. 8 */
+#define THC_TERM_EQ42 (1u << 7)   /* singles Fock terms, Alg. 10 */
+#define THC_TERM_ALL 0xffu
+
+typedef struct thc_ctx thc_ctx;
+
+typedef struct thc_options {
+  int64_t o, v, nL, nP, nQ; /* problem sizes (all >= 1) */
+  int32_t singles;          /* 1: CCSD (T1-dressed), 0: CCD (t1 fixed at zero) */
+  int32_t diis_max;         /* DIIS subspace size; 0 disables DIIS (<= 16) */
+  double tol_energy;        /* |dE| convergence threshold (Eh), e.g. 1e-8 */
+  int64_t a_block;          /* Cholesky vectors per fused-pass block; 0 = automatic */
+  int64_t i_chunk;          /* ERI grid points per H-kernel pass; 0 = automatic */
+  int64_t x_block;          /* amplitude ranks per H block (multiple of 64); 0 = automatic */
+  int64_t x_chunk;          /* amplitude ranks per Alg. 7 exchange chunk; 0 = automatic */
+  int32_t precision;        /* 0 = FP64 throughout (the only value accepted) */
+  int32_t reserved;
+} thc_options;
+
+/* Creates a context bound to the current HIP device and to `stream` (hipStream_t; NULL = the
+ * default stream).  Allocates nothing on the device yet.  *out receives the context. */
+int thc_create(const thc_options* opt, void* stream, thc_ctx** out);
+
+/* Set-up (paper Eq. 9-14, 17-20; Alg. 6 line 2): copies the integrals and factors, forms the
+ * Gram matrices o = Xo^T Xo, v = Xv^T Xv and the metric S = o (Hadamard) v, fits the ERI core
+ * z = xi^T xi by least squares against the ovov Cholesky block, forms B_ia^I, solves the
+ * generalized eigenproblem of the projected Fock operator (E w = e S w, the working basis with
+ * exact denominators e_P + e_Q) and the least-squares fit of the MP2 amplitudes,
+ * Z0 = S^-1 B^T t_MP2 B S^-1, which becomes the current state (t1 = 0).
+ *   L   [nL][n][n]  Cholesky vectors in the MO basis, symmetric in (p, q), occupied first
+ *   eps [n]         orbital energies (the Fock matrix is diag(eps))
+ *   X   [o*nP + v*nP + o*nQ + v*nQ]  Xo[o][nP] | Xv[v][nP] | xo[o][nQ] | xv[v][nQ]
+ *   Z   [nP][nP]    out: the MP2-guess core (may be NULL)
+ * Allocates the device working memory (all of it; nothing is allocated later). */
+int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const double* X, double* Z);
+
+/* Residual of a state (pure: the context state is not changed).
+ *   Z      [nP][nP] amplitude core (symmetric), raw collocation basis
+ *   t1     [o][v]   singles (NULL = zero; ignored in CCD mode)
+ *   sigma  [nP][nP] out: projected doubles residual sigma^WX (Eq. 6)
+ *   sigma1 [o][v]   out: singles residual (may be NULL)
+ *   norms  host [2] out: ||W^T sigma W||_F in the orthonormal working basis and ||sigma1||_F
+ *                   (may be NULL; if given the call synchronizes the stream) */
+int thc_residual(thc_ctx* ctx, const double* Z, const double* t1, double* sigma, double* sigma1, double* norms);
+
+/* As thc_residual, restricted to the term groups in `mask` (THC_TERM_*). */
+int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t mask, double* sigma,
+                       double* sigma1);
+
+/* Jacobi + DIIS iterations from the current state: each iteration evaluates the residual and
+ * the energy of the current amplitudes, stops when the residual norm (orthonormal basis) is
+ * below tol and |dE| < tol_energy, else updates T^ -= sigma^/(e_P + e_Q),
+ * t1 -= sigma1/(eps_a - eps_i) and extrapolates with DIIS.  *iters (host, may be NULL): number
+ * of residual evaluations; *rnorm (host, may be NULL): last residual norm.
+ * Returns THC_ENOTCONV when maxit is reached, THC_ENUMERIC on NaN/Inf. */
+int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm);
+
+/* Correlation energy of the current state (host scalar), the usual CCSD expression
+ * sum (t_ij^ab + t_i^a t_j^b)(2(ia|jb) - (ib|ja)) with Cholesky integrals. */
+int thc_energy(thc_ctx* ctx, double* e_corr);
+
+/* Current state in the raw basis: Z [nP][nP], t1 [o][v] (device; either may be NULL). */
+int thc_get_state(thc_ctx* ctx, double* Z, double* t1);
+/* Replaces the state (t1 may be NULL = zero); clears the DIIS history. */
+int thc_set_state(thc_ctx* ctx, const double* Z, const double* t1);
+
+/* Device working memory held by the context (bytes), valid after thc_build_factors. */
+int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes);
+
+/* Kernel timing with HIP events on the context stream.  thc_profile(ctx, 1) starts recording
+ * (and clears earlier records); thc_profile_get synchronizes and returns, for the kernel
+ * class `name` ("h_kernel", "gemm", "misc", or "residual" for whole residual evaluations),
+ * the summed duration in milliseconds and the number of launches recorded. */
+int thc_profile(thc_ctx* ctx, int enable);
+int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
+
+/* The library's FP64 MFMA GEMM (exposed for testing): C = alpha op(A) op(B) + beta C,
+ * row-major, op = transpose when trans* != 0, batched with element strides sA, sB, sC. */
+int thc_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+              int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C,
+              int64_t ldc, int64_t sC, int64_t batch, void* stream);
+
+const char* thc_last_error(const thc_ctx* ctx);
+void thc_destroy(thc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THC_H */

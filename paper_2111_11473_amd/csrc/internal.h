@@ -1,0 +1,71 @@
+// Internal declarations of the THC-CCSD HIP library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hostla.h"
+
+namespace thc {
+
+// Row-major batched GEMM descriptor:
+//   C[b](m, n) = alpha * sum_k opA(m, k) opB(k, n) * hmul(m, n) + beta * C[b](m, n)
+// opA(m, k) = transA ? A[k*lda + m] : A[m*lda + k], scaled by kscaleA[k*ksA + b*sksA] if given;
+// opB(k, n) = transB ? B[n*ldb + k] : B[k*ldb + n], scaled by kscaleB[k*ksB + b*sksB] if given.
+// hmul (optional) multiplies the product elementwise: hmul[m*ldh + n + b*sH].
+// ksplit > 1 splits K into ksplit slices; slice s writes to C + s*sSplit (the caller reduces).
+struct Gemm {
+  int64_t M = 0, N = 0, K = 0;
+  bool transA = false, transB = false;
+  const double* A = nullptr; int64_t lda = 0, sA = 0;
+  const double* B = nullptr; int64_t ldb = 0, sB = 0;
+  double* C = nullptr; int64_t ldc = 0, sC = 0;
+  double alpha = 1.0, beta = 0.0;
+  const double* kscaleA = nullptr; int64_t ksA = 1, sksA = 0;
+  const double* kscaleB = nullptr; int64_t ksB = 1, sksB = 0;
+  const double* hmul = nullptr; int64_t ldh = 0, sH = 0;
+  int64_t batch = 1;
+  int ksplit = 1; int64_t sSplit = 0;
+};
+
+hipError_t gemm_f64(const Gemm& g, hipStream_t s);
+
+// Elementwise / reduction kernels (kernels_misc.hip).
+hipError_t k_form_C(int64_t P, int64_t nb, const double* Bvv, const double* Boo, const double* Go,
+                    const double* Gv, double* Ccat, double* C3, hipStream_t s);
+hipError_t k_colsum_rowscaled(int64_t nb, int64_t rows, int64_t P, const double* Y, const double* W,
+                              int64_t sW, double* out, int64_t ldo, hipStream_t s);
+hipError_t k_hadamard_energy(int64_t P, int64_t nb, const double* T, const double* MT, double* F,
+                             double* epart, hipStream_t s);
+hipError_t k_batch_sum(int64_t nb, int64_t len, const double* X, double alpha, double* out, hipStream_t s);
+hipError_t k_wsum(int64_t nb, int64_t len, const double* w, const double* X, int64_t sX, double alpha,
+                  double* out, hipStream_t s);
+hipError_t k_copy2d(int64_t batch, int64_t rows, int64_t cols, const double* src, int64_t lds, int64_t sbs,
+                    double* dst, int64_t ldd, int64_t sbd, bool transpose, hipStream_t s);
+hipError_t k_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+hipError_t k_hadamard(int64_t n, const double* x, const double* y, double alpha, double beta, double* out,
+                      hipStream_t s);
+hipError_t k_sym_add(int64_t P, const double* Q, double alpha, double* out, hipStream_t s);
+hipError_t k_dot_cols(int64_t P, int64_t nb, const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                      double* out, hipStream_t s);
+hipError_t k_diag(int64_t P, const double* X, int64_t ldx, double* d, hipStream_t s);
+hipError_t k_trace_sq(int64_t nb, int64_t o, const double* K, double* out, hipStream_t s);
+hipError_t k_diag_eri(int64_t P, int64_t Q, int64_t o, const double* xo, const double* Rx, double* Cx,
+                      hipStream_t s);
+hipError_t k_dot(int64_t n, const double* x, const double* y, double* out, hipStream_t s);
+hipError_t k_sum(int64_t n, const double* x, double* out, hipStream_t s);
+hipError_t k_jacobi(int64_t P, int64_t o, int64_t v, const double* sh, const double* e, const double* s1,
+                    const double* eps, double* Th, double* t1, double* dT, double* dt1, hipStream_t s);
+hipError_t k_lincomb(int64_t n, int m, const double* coef, const double* const* vecs, double* out, hipStream_t s);
+hipError_t k_kr(int64_t o, int64_t v, int64_t P, const double* Yo, const double* Yv, double* B, hipStream_t s);
+hipError_t k_mp2_denom(int64_t rows0, int64_t rows, int64_t ov, int64_t v, const double* eps, int64_t o,
+                       double* X, hipStream_t s);
+hipError_t k_fill(int64_t n, double val, double* x, hipStream_t s);
+hipError_t k_set_diag(int64_t n, const double* d, double* X, int64_t ld, hipStream_t s);
+
+// VALU kernel for H^XYZ += sum_I (E^XY F^XZ + E^XZ F^XY) G^YZ (kernels_h.hip).
+hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t nI, const double* E, const double* F, const double* G,
+                        double* H, hipStream_t s);
+
+}  // namespace thc

@@ -1,0 +1,1050 @@
+// C ABI and host orchestration of the THC-CCSD hot path on one MI355X.
+//
+// The residual is evaluated as the paper's Algorithms 1-3 and 8 fused into one pass over
+// blocks of Cholesky vectors, Algorithm 6 (quartic T2^2 terms, H-kernel), Algorithm 7 (T2^2
+// rings), Algorithms 9-10 and the projection onto the working basis.  Every contraction is
+// a launch of the library's FP64 MFMA GEMM or of one of its elementwise kernels; the host
+// only sequences launches on one stream and reads back scalars.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/thc.h"
+#include "internal.h"
+
+using namespace thc;
+
+namespace {
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+
+struct Buf {
+  double* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct thc_ctx {
+  thc_options opt{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  bool built = false;
+
+  int64_t o = 0, v = 0, n = 0, nL = 0, P = 0, Q = 0, Pp = 0, ov = 0;
+  int64_t nb = 0, KS = 1, Xb = 0, Ic = 0, Xc = 0;
+
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+
+  // factors (device)
+  double *Loo = nullptr, *Lov = nullptr, *Lvv = nullptr, *eps = nullptr;
+  double *Yo = nullptr, *Yv = nullptr, *xo = nullptr, *xv = nullptr;
+  double *Go = nullptr, *Gv = nullptr, *S = nullptr, *z = nullptr, *Bq = nullptr, *Bkr = nullptr;
+  double *W = nullptr, *e = nullptr;
+  // state
+  double *Th = nullptr, *t1 = nullptr, *Zs = nullptr;
+  // DIIS ring
+  double *dvec = nullptr, *derr = nullptr, *dT = nullptr, *dt1 = nullptr;
+  int diis_n = 0, diis_head = 0;
+  std::vector<double> diisB;  // host copy of the error inner products (diis_max^2)
+
+  // residual outputs
+  double *sig = nullptr, *sig1 = nullptr, *sigh = nullptr, *scal = nullptr;
+
+  // A-pass work
+  double *Lhoo = nullptr, *Lhvo = nullptr, *tmpoo = nullptr, *tmpooT = nullptr, *Pv = nullptr, *PvT = nullptr;
+  double *LovYv = nullptr, *Wv = nullptr, *Bvv = nullptr, *Woo = nullptr, *Boo = nullptr;
+  double *Ccat = nullptr, *Dcat = nullptr, *Wvo = nullptr, *Y1 = nullptr, *Gm = nullptr, *GY = nullptr;
+  double *TA = nullptr, *tmpov = nullptr;
+  double *sig28 = nullptr, *C3 = nullptr, *Abar = nullptr, *At = nullptr, *Hh = nullptr;
+  double *xioo = nullptr, *xivv = nullptr, *s38 = nullptr, *dvecA = nullptr, *trK = nullptr;
+  double *ej = nullptr, *ek = nullptr;
+  double *Fin = nullptr, *Fh = nullptr;  // n x n, blocks [oo | ov | vo | vv]
+  double *Jov = nullptr, *Jvo = nullptr;
+  // assembly
+  double *ST = nullptr, *Dt = nullptr, *K29 = nullptr, *Qm = nullptr, *ot = nullptr, *vt = nullptr, *E9 = nullptr;
+  double *tmpoP = nullptr, *tmpvP = nullptr, *Fxoo = nullptr, *Fxvv = nullptr, *Tf = nullptr, *fd = nullptr;
+  // Alg. 6
+  double *C6 = nullptr, *D6 = nullptr, *Ec = nullptr, *Fc = nullptr, *Gc = nullptr, *GYc = nullptr, *Hb = nullptr;
+  double *R1 = nullptr, *I6 = nullptr;
+  // Alg. 7
+  double *U7 = nullptr, *S7 = nullptr, *R7 = nullptr, *Rx = nullptr, *Sx = nullptr, *Cx = nullptr, *Dx = nullptr;
+  double *F7 = nullptr, *Gt = nullptr, *Gts = nullptr, *G7 = nullptr, *G7s = nullptr;
+
+  // profiling
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+};
+
+namespace {
+
+constexpr double C_D = 0.5;  // prefactor of the Eq. 35-37 ring contraction (closed-shell CCSD)
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess) {                                                          \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(_e);                  \
+      return THC_EDEVICE;                                                            \
+    }                                                                                \
+  } while (0)
+
+#define RCHK(expr)                 \
+  do {                             \
+    int _r = (expr);               \
+    if (_r != THC_OK) return _r;   \
+  } while (0)
+
+hipEvent_t next_event(thc_ctx* ctx) {
+  if (ctx->pool_used == ctx->pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    ctx->pool.push_back(ev);
+  }
+  return ctx->pool[ctx->pool_used++];
+}
+
+struct Scope {
+  thc_ctx* ctx;
+  hipEvent_t a = nullptr;
+  const char* name;
+  Scope(thc_ctx* c, const char* nm) : ctx(c), name(nm) {
+    if (ctx->prof) {
+      a = next_event(ctx);
+      if (a) (void)hipEventRecord(a, ctx->stream);
+    }
+  }
+  ~Scope() {
+    if (ctx->prof && a) {
+      hipEvent_t b = next_event(ctx);
+      if (b) {
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->recs.push_back({name, a, b});
+      }
+    }
+  }
+};
+
+int gemm(thc_ctx* ctx, const Gemm& g) {
+  Scope sc(ctx, "gemm");
+  HIPCHK(gemm_f64(g, ctx->stream));
+  return THC_OK;
+}
+
+// Plain (batched) GEMM helper.
+Gemm mk(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, bool tA, const double* B, int64_t ldb,
+        bool tB, double* C, int64_t ldc, double alpha = 1.0, double beta = 0.0) {
+  Gemm g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.transA = tA;
+  g.B = B; g.ldb = ldb; g.transB = tB;
+  g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta;
+  return g;
+}
+Gemm batched(Gemm g, int64_t batch, int64_t sA, int64_t sB, int64_t sC) {
+  g.batch = batch; g.sA = sA; g.sB = sB; g.sC = sC;
+  return g;
+}
+
+#define MISC(expr)                      \
+  do {                                  \
+    Scope _sc(ctx, "misc");             \
+    HIPCHK(expr);                       \
+  } while (0)
+
+int alloc(thc_ctx* ctx, double** p, size_t count) {
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  if (hipMalloc(&q, count * sizeof(double)) != hipSuccess) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "hipMalloc of %zu bytes failed (held: %zu bytes)", count * sizeof(double), ctx->bytes);
+    ctx->err = buf;
+    (void)hipGetLastError();
+    return THC_ENOMEM;
+  }
+  ctx->allocs.push_back(q);
+  ctx->bytes += count * sizeof(double);
+  *p = (double*)q;
+  return THC_OK;
+}
+
+int zero(thc_ctx* ctx, double* p, size_t count) {
+  MISC(k_fill((int64_t)count, 0.0, p, ctx->stream));
+  return THC_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Dense SPD solves on the device: blocked right-looking Cholesky (lower, in place) whose
+// 64 x 64 diagonal blocks are factored and inverted on the host; the panel and trailing
+// updates are GEMMs.  Linv receives the inverses of the diagonal blocks.
+constexpr int64_t CB = 64;
+
+int potrf(thc_ctx* ctx, double* A, int64_t n, double* Linv, double* tmp) {
+  std::vector<double> hb(CB * CB), hi(CB * CB);
+  for (int64_t k0 = 0; k0 < n; k0 += CB) {
+    const int64_t kb = std::min(CB, n - k0);
+    HIPCHK(hipMemcpy2DAsync(hb.data(), kb * sizeof(double), A + k0 * n + k0, n * sizeof(double), kb * sizeof(double), kb,
+                            hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (host_cholesky(kb, hb.data()) != 0) {
+      ctx->err = "matrix is not positive definite (Cholesky pivot <= 0)";
+      return THC_ESINGULAR;
+    }
+    host_tri_inverse_lower(kb, hb.data(), hi.data());
+    HIPCHK(hipMemcpy2DAsync(A + k0 * n + k0, n * sizeof(double), hb.data(), kb * sizeof(double), kb * sizeof(double), kb,
+                            hipMemcpyHostToDevice, ctx->stream));
+    double* Li = Linv + (k0 / CB) * CB * CB;
+    HIPCHK(hipMemcpyAsync(Li, hi.data(), kb * kb * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const int64_t r0 = k0 + kb, rn = n - r0;
+    if (rn <= 0) continue;
+    // panel: A[r0:, k0:k0+kb] <- A[r0:, k0:k0+kb] L_kk^-T
+    RCHK(gemm(ctx, mk(rn, kb, kb, A + r0 * n + k0, n, false, Li, kb, true, tmp, kb)));
+    MISC(k_copy2d(1, rn, kb, tmp, kb, 0, A + r0 * n + k0, n, 0, false, ctx->stream));
+    // trailing: A[r0:, r0:] -= panel panel^T
+    RCHK(gemm(ctx, mk(rn, rn, kb, A + r0 * n + k0, n, false, A + r0 * n + k0, n, true, A + r0 * n + r0, n, -1.0, 1.0)));
+  }
+  return THC_OK;
+}
+
+// Solves L X = B (forward) or L^T X = B (backward) for X (n x m, row-major, in place in B).
+int trsm(thc_ctx* ctx, const double* A, int64_t n, const double* Linv, double* B, int64_t m, bool backward,
+         double* tmp) {
+  const int64_t nblk = (n + CB - 1) / CB;
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t b = backward ? nblk - 1 - bi : bi;
+    const int64_t k0 = b * CB, kb = std::min(CB, n - k0);
+    const double* Li = Linv + b * CB * CB;
+    if (!backward) {
+      if (k0 > 0)  // B_k -= L[k, :k0] X[:k0]
+        RCHK(gemm(ctx, mk(kb, m, k0, A + k0 * n, n, false, B, m, false, B + k0 * m, m, -1.0, 1.0)));
+      RCHK(gemm(ctx, mk(kb, m, kb, Li, kb, false, B + k0 * m, m, false, tmp, m)));
+    } else {
+      const int64_t r0 = k0 + kb;
+      if (r0 < n)  // B_k -= L[r0:, k]^T X[r0:]
+        RCHK(gemm(ctx, mk(kb, m, n - r0, A + r0 * n + k0, n, true, B + r0 * m, m, false, B + k0 * m, m, -1.0, 1.0)));
+      RCHK(gemm(ctx, mk(kb, m, kb, Li, kb, true, B + k0 * m, m, false, tmp, m)));
+    }
+    MISC(k_copy2d(1, kb, m, tmp, m, 0, B + k0 * m, m, 0, false, ctx->stream));
+  }
+  return THC_OK;
+}
+
+int check_finite_host(thc_ctx* ctx, const double* x, size_t n, const char* what) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) {
+      ctx->err = std::string("non-finite value in ") + what;
+      return THC_ENUMERIC;
+    }
+  return THC_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Working-memory plan.
+int plan_and_alloc(thc_ctx* ctx) {
+  const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
+  const int64_t Pp = ctx->Pp = ((P + 63) / 64) * 64;
+  const thc_options& op = ctx->opt;
+  // fused-pass block: four nb x P^2 panels within ~4 GB
+  int64_t nb = op.a_block > 0 ? op.a_block : std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(4.0e9 / (32.0 * P * P))));
+  nb = std::min(nb, nL);
+  ctx->nb = nb;
+  const int64_t t64 = ((P + 63) / 64) * ((P + 63) / 64);
+  ctx->KS = std::max<int64_t>(1, std::min<int64_t>(16, (1024 + t64 - 1) / t64));
+  // H block over X: whole rank when it fits in ~40 GB
+  int64_t Xb = op.x_block;
+  if (Xb <= 0) {
+    const double hb = 40.0e9 / (8.0 * (double)Pp * Pp);
+    Xb = std::min<int64_t>(Pp, std::max<int64_t>(64, ((int64_t)hb / 64) * 64));
+  }
+  if (Xb % 64 != 0 || Xb > Pp) { ctx->err = "x_block must be a multiple of 64 and <= padded rank"; return THC_EINVAL; }
+  ctx->Xb = Xb;
+  int64_t Ic = op.i_chunk;
+  if (Ic <= 0) Ic = std::max<int64_t>(1, (int64_t)(8.0e9 / (8.0 * (2.0 * Xb * Pp + (double)Pp * Pp))));
+  ctx->Ic = std::min(Ic, Q);
+  int64_t Xc = op.x_chunk;
+  if (Xc <= 0) Xc = std::max<int64_t>(1, (int64_t)(2.0e9 / (8.0 * (double)Q * Q)));
+  ctx->Xc = std::min(Xc, P);
+  const int64_t PP = P * P;
+
+  struct A { double** p; size_t n; };
+  const int64_t dm = ctx->opt.diis_max;
+  std::vector<A> list = {
+      {&ctx->Loo, (size_t)(nL * o * o)}, {&ctx->Lov, (size_t)(nL * ov)}, {&ctx->Lvv, (size_t)(nL * v * v)},
+      {&ctx->eps, (size_t)n}, {&ctx->Yo, (size_t)(o * P)}, {&ctx->Yv, (size_t)(v * P)},
+      {&ctx->xo, (size_t)(o * Q)}, {&ctx->xv, (size_t)(v * Q)}, {&ctx->Go, (size_t)PP}, {&ctx->Gv, (size_t)PP},
+      {&ctx->S, (size_t)PP}, {&ctx->z, (size_t)(Q * Q)}, {&ctx->Bq, (size_t)(Q * ov)}, {&ctx->Bkr, (size_t)(ov * P)},
+      {&ctx->W, (size_t)PP}, {&ctx->e, (size_t)P},
+      {&ctx->Th, (size_t)PP}, {&ctx->t1, (size_t)ov}, {&ctx->Zs, (size_t)PP},
+      {&ctx->dvec, (size_t)(std::max<int64_t>(dm, 1) * (PP + ov))}, {&ctx->derr, (size_t)(std::max<int64_t>(dm, 1) * (PP + ov))},
+      {&ctx->dT, (size_t)(PP + ov)},
+      {&ctx->sig, (size_t)PP}, {&ctx->sig1, (size_t)ov}, {&ctx->sigh, (size_t)PP}, {&ctx->scal, 64},
+      // fused pass
+      {&ctx->Lhoo, (size_t)(nb * o * o)}, {&ctx->Lhvo, (size_t)(nb * v * o)}, {&ctx->tmpoo, (size_t)(nb * o * o)},
+      {&ctx->tmpooT, (size_t)(nb * o * o)}, {&ctx->Pv, (size_t)(nb * v * o)}, {&ctx->PvT, (size_t)(nb * v * o)},
+      {&ctx->LovYv, (size_t)(nb * o * P)}, {&ctx->Wv, (size_t)(nb * v * P)}, {&ctx->Bvv, (size_t)(nb * PP)},
+      {&ctx->Woo, (size_t)(nb * o * P)}, {&ctx->Boo, (size_t)(nb * PP)}, {&ctx->Ccat, (size_t)(nb * PP)},
+      {&ctx->Dcat, (size_t)(nb * PP)}, {&ctx->Wvo, (size_t)(nb * o * P)}, {&ctx->Y1, (size_t)(nb * o * P)},
+      {&ctx->Gm, (size_t)(nb * ov)}, {&ctx->GY, (size_t)(nb * o * P)}, {&ctx->TA, (size_t)(P * nb)},
+      {&ctx->tmpov, (size_t)(nb * std::max(std::max(ov, v * v), o * o))},
+      {&ctx->sig28, (size_t)(ctx->KS * PP)}, {&ctx->C3, (size_t)PP}, {&ctx->Abar, (size_t)(P * nL)},
+      {&ctx->At, (size_t)(P * nL)}, {&ctx->Hh, (size_t)(P * nL)}, {&ctx->xioo, (size_t)(o * o)},
+      {&ctx->xivv, (size_t)(v * v)}, {&ctx->s38, (size_t)ov}, {&ctx->dvecA, (size_t)nL}, {&ctx->trK, (size_t)nL},
+      {&ctx->ej, (size_t)nL}, {&ctx->ek, (size_t)(nL * 64)}, {&ctx->Fin, (size_t)(n * n)}, {&ctx->Fh, (size_t)(n * n)}, {&ctx->Jov, (size_t)ov}, {&ctx->Jvo, (size_t)ov},
+      // assembly
+      {&ctx->ST, (size_t)PP}, {&ctx->Dt, (size_t)(P * nL)}, {&ctx->K29, (size_t)(P * nL)}, {&ctx->Qm, (size_t)PP},
+      {&ctx->ot, (size_t)PP}, {&ctx->vt, (size_t)PP}, {&ctx->E9, (size_t)PP}, {&ctx->tmpoP, (size_t)(o * P)},
+      {&ctx->tmpvP, (size_t)(v * P)}, {&ctx->Fxoo, (size_t)(o * o)}, {&ctx->Fxvv, (size_t)(v * v)},
+      {&ctx->Tf, (size_t)P}, {&ctx->fd, (size_t)P},
+      // Alg. 6
+      {&ctx->C6, (size_t)(o * Xb * Pp)}, {&ctx->D6, (size_t)(v * Xb * Pp)}, {&ctx->Ec, (size_t)(ctx->Ic * Xb * Pp)},
+      {&ctx->Fc, (size_t)(ctx->Ic * Xb * Pp)}, {&ctx->Gc, (size_t)(ctx->Ic * Pp * Pp)}, {&ctx->GYc, (size_t)(ctx->Ic * o * P)},
+      {&ctx->Hb, (size_t)(Xb * Pp * Pp)}, {&ctx->R1, (size_t)(Xb * Pp * o)}, {&ctx->I6, (size_t)(Xb * ov)},
+      // Alg. 7
+      {&ctx->U7, (size_t)(P * o * P)}, {&ctx->S7, (size_t)(P * ov)}, {&ctx->R7, (size_t)(P * ov)},
+      {&ctx->Rx, (size_t)(P * o * Q)}, {&ctx->Sx, (size_t)(P * o * Q)}, {&ctx->Cx, (size_t)(P * Q)}, {&ctx->Dx, (size_t)(P * Q)},
+      {&ctx->F7, (size_t)(ctx->Xc * Q * Q)}, {&ctx->Gt, (size_t)(P * o * Q)}, {&ctx->Gts, (size_t)(P * o * Q)},
+      {&ctx->G7, (size_t)(P * ov)}, {&ctx->G7s, (size_t)(P * ov)},
+  };
+  for (auto& a : list) RCHK(alloc(ctx, a.p, a.n));
+  // zero-padded operands of the H-kernel: padding must stay zero
+  RCHK(zero(ctx, ctx->C6, o * Xb * Pp));
+  RCHK(zero(ctx, ctx->D6, v * Xb * Pp));
+  RCHK(zero(ctx, ctx->Gc, ctx->Ic * Pp * Pp));
+  RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
+  RCHK(zero(ctx, ctx->Ec, ctx->Ic * Xb * Pp));
+  RCHK(zero(ctx, ctx->Fc, ctx->Ic * Xb * Pp));
+  ctx->diisB.assign((size_t)std::max<int64_t>(dm, 1) * std::max<int64_t>(dm, 1), 0.0);
+  return THC_OK;
+}
+
+// Copies one scalar region of ctx->scal to the host.
+int read_scalars(thc_ctx* ctx, double* h, int count) {
+  HIPCHK(hipMemcpyAsync(h, ctx->scal, count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return THC_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// The residual (and the energy of the same amplitudes).  T: raw core (device, P x P);
+// t1: singles (device, may be null).  Results in ctx->sig (P x P), ctx->sig1 (o x v) and the
+// energy partial sums in ctx->scal[0..3] (E_J, E_K, singles: 2 sum d_A^2, sum tr K_A^2).
+int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask) {
+  Scope whole(ctx, "residual");
+  hipStream_t s = ctx->stream;
+  const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
+  const int64_t PP = P * P, Pp = ctx->Pp;
+  const bool sres = ctx->opt.singles != 0;    // singles residual wanted
+  const bool singles = sres && t1 != nullptr;  // T1 dressing needed (t1 given)
+  const double *Yo = ctx->Yo, *Yv = ctx->Yv, *xo = ctx->xo, *xv = ctx->xv;
+
+  RCHK(zero(ctx, ctx->sig, PP));
+  RCHK(zero(ctx, ctx->sig1, ov));
+  RCHK(zero(ctx, ctx->sig28, ctx->KS * PP));
+  RCHK(zero(ctx, ctx->C3, PP));
+  RCHK(zero(ctx, ctx->xioo, o * o));
+  RCHK(zero(ctx, ctx->xivv, v * v));
+  RCHK(zero(ctx, ctx->s38, ov));
+  RCHK(zero(ctx, ctx->Fin, n * n));
+  RCHK(zero(ctx, ctx->dvecA, nL));
+  RCHK(zero(ctx, ctx->trK, nL));
+
+  // ---------------- fused pass over blocks of Cholesky vectors (Alg. 1, 2, 3, 8) -------------
+  for (int64_t A0 = 0; A0 < nL; A0 += ctx->nb) {
+    const int64_t nb = std::min(ctx->nb, nL - A0);
+    const double* Loo = ctx->Loo + A0 * o * o;
+    const double* Lov = ctx->Lov + A0 * ov;
+    const double* Lvv = ctx->Lvv + A0 * v * v;
+    const double* Lhoo = Loo;  // dressed blocks (Eq. 27); the undressed ones in CCD mode
+    if (singles) {
+      // tmpoo[A] = Lov t1^T (o x o), also in the [i][A][k] layout for the Fock K-term
+      RCHK(gemm(ctx, batched(mk(o, o, v, Lov, v, false, t1, v, true, ctx->tmpoo, o), nb, ov, 0, o * o)));
+      RCHK(gemm(ctx, batched(mk(o, o, v, Lov, v, false, t1, v, true, ctx->tmpooT, nb * o), nb, ov, 0, o)));
+      MISC(k_copy2d(1, nb * o, o, Loo, o, 0, ctx->Lhoo, o, 0, false, s));
+      MISC(k_axpby(nb * o * o, 1.0, ctx->tmpoo, 1.0, ctx->Lhoo, s));
+      Lhoo = ctx->Lhoo;
+      MISC(k_trace_sq(nb, o, ctx->tmpoo, ctx->trK + A0, s));
+      // d_A = sum_ia t_ia L_ia^A
+      RCHK(gemm(ctx, mk(nb, 1, ov, Lov, ov, false, t1, 1, false, ctx->dvecA + A0, 1)));
+      // Pv[A] = Lvv t1^T (v x o), in [A][a][k] and [a][A][k] layouts
+      RCHK(gemm(ctx, batched(mk(v, o, v, Lvv, v, false, t1, v, true, ctx->Pv, o), nb, v * v, 0, v * o)));
+      RCHK(gemm(ctx, batched(mk(v, o, v, Lvv, v, false, t1, v, true, ctx->PvT, nb * o), nb, v * v, 0, o)));
+      // Lhvo[A] = Lov^T + Lvv t1^T - t1^T Lhoo
+      MISC(k_copy2d(nb, v, o, Lov, v, ov, ctx->Lhvo, o, v * o, true, s));
+      MISC(k_axpby(nb * v * o, 1.0, ctx->Pv, 1.0, ctx->Lhvo, s));
+      RCHK(gemm(ctx, batched(mk(v, o, o, t1, v, true, ctx->Lhoo, o, false, ctx->Lhvo, o, -1.0, 1.0), nb, 0, o * o, v * o)));
+      // Fock: inner += 2 sum_A d_A L^A - sum_A (L^A[:, vir] t1^T) L^A[occ, :]
+      MISC(k_wsum(nb, o * o, ctx->dvecA + A0, Loo, o * o, 2.0, ctx->Fin, s));  // oo block written densely below
+      // (the block layout of Fin: [oo | ov | vo | vv] stored contiguously)
+      MISC(k_wsum(nb, ov, ctx->dvecA + A0, Lov, ov, 2.0, ctx->Fin + o * o, s));
+      MISC(k_wsum(nb, v * v, ctx->dvecA + A0, Lvv, v * v, 2.0, ctx->Fin + o * o + 2 * ov, s));
+      RCHK(gemm(ctx, mk(o, o, nb * o, ctx->tmpooT, nb * o, false, Loo, o, false, ctx->Fin, o, -1.0, 1.0)));
+      RCHK(gemm(ctx, mk(o, v, nb * o, ctx->tmpooT, nb * o, false, Lov, v, false, ctx->Fin + o * o, v, -1.0, 1.0)));
+      RCHK(gemm(ctx, mk(v, o, nb * o, ctx->PvT, nb * o, false, Loo, o, false, ctx->Fin + o * o + ov, o, -1.0, 1.0)));
+      RCHK(gemm(ctx, mk(v, v, nb * o, ctx->PvT, nb * o, false, Lov, v, false, ctx->Fin + o * o + 2 * ov, v, -1.0, 1.0)));
+    }
+    // LovYv[A] = Lov Yv (o x P)
+    RCHK(gemm(ctx, batched(mk(o, P, v, Lov, v, false, Yv, P, false, ctx->LovYv, P), nb, ov, 0, o * P)));
+    // Wv[A] = L^vv Yv (v x P), dressed by - t1^T (Lov Yv)
+    RCHK(gemm(ctx, batched(mk(v, P, v, Lvv, v, false, Yv, P, false, ctx->Wv, P), nb, v * v, 0, v * P)));
+    if (singles)
+      RCHK(gemm(ctx, batched(mk(v, P, o, t1, v, true, ctx->LovYv, P, false, ctx->Wv, P, -1.0, 1.0), nb, 0, o * P, v * P)));
+    // Bvv[A] = Yv^T Wv[A];  Boo[A] = Yo^T (L^oo)^T Yo   (Alg. 1 lines 5-11)
+    RCHK(gemm(ctx, batched(mk(P, P, v, Yv, P, true, ctx->Wv, P, false, ctx->Bvv, P), nb, 0, v * P, PP)));
+    RCHK(gemm(ctx, batched(mk(o, P, o, Lhoo, o, true, Yo, P, false, ctx->Woo, P), nb, o * o, 0, o * P)));
+    RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->Woo, P, false, ctx->Boo, P), nb, 0, o * P, PP)));
+    // C^A = Go o Bvv - Gv o Boo ([X][A][Y]); C3 += Boo o Bvv  (Alg. 1 lines 8-13, Alg. 3 line 7)
+    MISC(k_form_C(P, nb, ctx->Bvv, ctx->Boo, ctx->Go, ctx->Gv, ctx->Ccat, ctx->C3, s));
+    if (mask & THC_TERM_EQ28) {
+      // D^A = C^A T; sigma += sum_A D^A (C^A)^T  (Alg. 1 lines 14-15), split over K
+      RCHK(gemm(ctx, batched(mk(P, P, P, ctx->Ccat, nb * P, false, T, P, false, ctx->Dcat, nb * P), nb, P, 0, P)));
+      Gemm g = mk(P, P, nb * P, ctx->Dcat, nb * P, false, ctx->Ccat, nb * P, true, ctx->sig28, P, 1.0, 1.0);
+      g.ksplit = (int)ctx->KS;
+      g.sSplit = PP;
+      RCHK(gemm(ctx, g));
+    }
+    // Abar^X_A = sum_ai y_a^X y_i^X L^_ai ; Atil^X_A = sum_ia y_i^X y_a^X L_ia  (Alg. 2 lines 5-6)
+    if (singles)
+      RCHK(gemm(ctx, batched(mk(o, P, v, ctx->Lhvo, o, true, Yv, P, false, ctx->Wvo, P), nb, v * o, 0, o * P)));
+    MISC(k_colsum_rowscaled(nb, o, P, Yo, singles ? ctx->Wvo : ctx->LovYv, o * P, ctx->Abar + A0, nL, s));
+    MISC(k_colsum_rowscaled(nb, o, P, Yo, ctx->LovYv, o * P, ctx->At + A0, nL, s));
+    // M^T[A] = (Lov Yv)^T Yo ; F = T o M^T ; exchange energy partials  (Alg. 2 lines 10-11)
+    RCHK(gemm(ctx, batched(mk(P, P, o, ctx->LovYv, P, true, Yo, P, false, ctx->Boo, P), nb, o * P, 0, PP)));
+    MISC(k_hadamard_energy(P, nb, T, ctx->Boo, ctx->Bvv, ctx->ek + A0 * 64, s));
+    // G[A] = Yo F Yv^T (o x v); H^X_A = sum_ia y_i^X y_a^X G_ia  (Alg. 2 lines 12-13)
+    RCHK(gemm(ctx, batched(mk(o, P, P, Yo, P, false, ctx->Bvv, P, false, ctx->Y1, P), nb, 0, PP, o * P)));
+    RCHK(gemm(ctx, batched(mk(o, v, P, ctx->Y1, P, false, Yv, P, true, ctx->Gm, v), nb, o * P, 0, ov)));
+    RCHK(gemm(ctx, batched(mk(o, P, v, ctx->Gm, v, false, Yv, P, false, ctx->GY, P), nb, ov, 0, o * P)));
+    MISC(k_colsum_rowscaled(nb, o, P, Yo, ctx->GY, o * P, ctx->Hh + A0, nL, s));
+    // TA = T Atil (P x nb); Coulomb energy partials Atil^T T Atil
+    RCHK(gemm(ctx, mk(P, nb, P, T, P, false, ctx->At + A0, nL, false, ctx->TA, nb)));
+    MISC(k_dot_cols(P, nb, ctx->At + A0, nL, ctx->TA, nb, ctx->ej + A0, s));
+    // D8[A] = 2 Yo diag(T Atil_A) Yv^T - G[A]  (Alg. 8 lines 8-9), in place of G
+    {
+      Gemm g = batched(mk(o, v, P, Yo, P, false, Yv, P, true, ctx->Gm, v, 2.0, -1.0), nb, 0, 0, ov);
+      g.kscaleA = ctx->TA; g.ksA = nb; g.sksA = 1;
+      RCHK(gemm(ctx, g));
+    }
+    // xi_oo += sum_A Lov D8^T ; xi_vv -= sum_A D8^T Lov  (Alg. 8 lines 10-11)
+    RCHK(gemm(ctx, batched(mk(o, o, v, Lov, v, false, ctx->Gm, v, true, ctx->tmpov, o), nb, ov, ov, o * o)));
+    MISC(k_batch_sum(nb, o * o, ctx->tmpov, 1.0, ctx->xioo, s));
+    RCHK(gemm(ctx, mk(v, v, nb * o, ctx->Gm, v, true, Lov, v, false, ctx->xivv, v, -1.0, 1.0)));
+    if (sres) {
+      // singles (Alg. 8 lines 12-13 with the dressing folded into xi afterwards):
+      // s38 += sum_A D8 Lvv - Loo D8
+      RCHK(gemm(ctx, batched(mk(o, v, v, ctx->Gm, v, false, Lvv, v, false, ctx->tmpov, v), nb, ov, v * v, ov)));
+      RCHK(gemm(ctx, batched(mk(o, v, o, Loo, o, false, ctx->Gm, v, false, ctx->tmpov, v, -1.0, 1.0), nb, o * o, ov, ov)));
+      MISC(k_batch_sum(nb, ov, ctx->tmpov, 1.0, ctx->s38, s));
+    }
+  }
+  // energy partial sums: scal[0] = sum_A Atil^T T Atil, scal[1] = exchange, scal[2] = sum d_A^2,
+  // scal[3] = sum tr(K_A^2)
+  MISC(k_sum(nL, ctx->ej, ctx->scal + 0, s));
+  MISC(k_sum(nL * 64, ctx->ek, ctx->scal + 1, s));
+  MISC(k_dot(nL, ctx->dvecA, ctx->dvecA, ctx->scal + 2, s));
+  MISC(k_sum(nL, ctx->trK, ctx->scal + 3, s));
+
+  // ---------------- Fock matrix, T1-transformed (Eq. 24-27) -----------------------------------
+  double* Foo = ctx->Fh;
+  double* Fov = ctx->Fh + o * o;
+  double* Fvo = ctx->Fh + o * o + ov;
+  double* Fvv = ctx->Fh + o * o + 2 * ov;
+  {
+    double* Ioo = ctx->Fin;
+    double* Iov = ctx->Fin + o * o;
+    double* Ivo = ctx->Fin + o * o + ov;
+    double* Ivv = ctx->Fin + o * o + 2 * ov;
+    MISC(k_set_diag(o, ctx->eps, Ioo, o, s));
+    MISC(k_set_diag(v, ctx->eps + o, Ivv, v, s));
+    if (singles) {
+      // J part of the vo block: (2 sum_A d_A L_ov^A)^T (L symmetric)
+      RCHK(zero(ctx, ctx->Jov, ov));
+      MISC(k_wsum(nL, ov, ctx->dvecA, ctx->Lov, ov, 2.0, ctx->Jov, s));
+      MISC(k_copy2d(1, v, o, ctx->Jov, v, 0, ctx->Jvo, o, 0, true, s));
+      MISC(k_axpby(v * o, 1.0, ctx->Jvo, 1.0, Ivo, s));
+      // F^ = (1 - tau) inner (1 + tau)
+      MISC(k_copy2d(1, o, v, Iov, v, 0, Fov, v, 0, false, s));
+      MISC(k_copy2d(1, o, o, Ioo, o, 0, Foo, o, 0, false, s));
+      RCHK(gemm(ctx, mk(o, o, v, Iov, v, false, t1, v, true, Foo, o, 1.0, 1.0)));
+      MISC(k_copy2d(1, v, v, Ivv, v, 0, Fvv, v, 0, false, s));
+      RCHK(gemm(ctx, mk(v, v, o, t1, v, true, Iov, v, false, Fvv, v, -1.0, 1.0)));
+      // Fvo = Ivo - t1^T Ioo + Fvv_part t1^T with Fvv_part = Ivv - t1^T Iov (= Fvv)
+      MISC(k_copy2d(1, v, o, Ivo, o, 0, Fvo, o, 0, false, s));
+      RCHK(gemm(ctx, mk(v, o, o, t1, v, true, Ioo, o, false, Fvo, o, -1.0, 1.0)));
+      RCHK(gemm(ctx, mk(v, o, v, Fvv, v, false, t1, v, true, Fvo, o, 1.0, 1.0)));
+    } else {
+      MISC(k_copy2d(1, 1, n * n, ctx->Fin, n * n, 0, ctx->Fh, n * n, 0, false, s));
+    }
+  }
+
+  // ---------------- assembly of the symmetric terms (Alg. 2, 3, 9) ----------------------------
+  RCHK(gemm(ctx, mk(P, P, P, ctx->S, P, false, T, P, false, ctx->ST, P)));
+  if (mask & THC_TERM_EQ28) MISC(k_batch_sum(ctx->KS, PP, ctx->sig28, 1.0, ctx->sig, s));
+  if (mask & THC_TERM_EQ29) {
+    // sigma += Abar K^T + K Abar^T, K = Abar/2 + 2 S T Atil - H
+    RCHK(gemm(ctx, mk(P, nL, P, ctx->ST, P, false, ctx->At, nL, false, ctx->K29, nL, 2.0, 0.0)));
+    MISC(k_axpby(P * nL, 0.5, ctx->Abar, 1.0, ctx->K29, s));
+    MISC(k_axpby(P * nL, -1.0, ctx->Hh, 1.0, ctx->K29, s));
+    RCHK(gemm(ctx, mk(P, P, nL, ctx->Abar, nL, false, ctx->K29, nL, true, ctx->Qm, P)));
+    MISC(k_sym_add(P, ctx->Qm, 1.0, ctx->sig, s));
+  }
+  if (mask & THC_TERM_EQ31) {
+    // sigma -= S T C3^T + C3 T S
+    RCHK(gemm(ctx, mk(P, P, P, ctx->ST, P, false, ctx->C3, P, true, ctx->Qm, P)));
+    MISC(k_sym_add(P, ctx->Qm, -1.0, ctx->sig, s));
+  }
+  if (mask & THC_TERM_EQ41) {
+    // Alg. 9: E = Go o vt - Gv o ot, vt = Yv^T (F^vv + xi_vv) Yv, ot = Yo^T (F^oo + xi_oo)^T Yo
+    MISC(k_copy2d(1, o, o, Foo, o, 0, ctx->Fxoo, o, 0, false, s));
+    MISC(k_axpby(o * o, 1.0, ctx->xioo, 1.0, ctx->Fxoo, s));
+    MISC(k_copy2d(1, v, v, Fvv, v, 0, ctx->Fxvv, v, 0, false, s));
+    MISC(k_axpby(v * v, 1.0, ctx->xivv, 1.0, ctx->Fxvv, s));
+    RCHK(gemm(ctx, mk(o, P, o, ctx->Fxoo, o, true, Yo, P, false, ctx->tmpoP, P)));
+    RCHK(gemm(ctx, mk(P, P, o, Yo, P, true, ctx->tmpoP, P, false, ctx->ot, P)));
+    RCHK(gemm(ctx, mk(v, P, v, ctx->Fxvv, v, false, Yv, P, false, ctx->tmpvP, P)));
+    RCHK(gemm(ctx, mk(P, P, v, Yv, P, true, ctx->tmpvP, P, false, ctx->vt, P)));
+    MISC(k_hadamard(PP, ctx->Go, ctx->vt, 1.0, 0.0, ctx->E9, s));
+    MISC(k_hadamard(PP, ctx->Gv, ctx->ot, -1.0, 1.0, ctx->E9, s));
+    RCHK(gemm(ctx, mk(P, P, P, ctx->ST, P, false, ctx->E9, P, true, ctx->Qm, P)));
+    MISC(k_sym_add(P, ctx->Qm, 1.0, ctx->sig, s));
+  }
+
+  // ---------------- Alg. 6: quartic T2^2 ladder + exchange (Eq. 32 + 33) ----------------------
+  if (mask & THC_TERM_EQ32) {
+    const int64_t Xb = ctx->Xb;
+    for (int64_t X0 = 0; X0 < P; X0 += Xb) {
+      const int64_t xb = std::min(Xb, P - X0);
+      // C6[i][x][Y] = sum_W Gv[X][W] y_i^W T[W][Y];  D6[a][x][Y] = sum_W Go[X][W] y_a^W T[W][Y]
+      {
+        Gemm g = batched(mk(xb, P, P, ctx->Gv + X0 * P, P, false, T, P, false, ctx->C6, Pp), o, 0, 0, Xb * Pp);
+        g.kscaleA = Yo; g.ksA = 1; g.sksA = P;
+        RCHK(gemm(ctx, g));
+        Gemm h = batched(mk(xb, P, P, ctx->Go + X0 * P, P, false, T, P, false, ctx->D6, Pp), v, 0, 0, Xb * Pp);
+        h.kscaleA = Yv; h.ksA = 1; h.sksA = P;
+        RCHK(gemm(ctx, h));
+      }
+      for (int64_t I0 = 0; I0 < Q; I0 += ctx->Ic) {
+        const int64_t ic = std::min(ctx->Ic, Q - I0);
+        // E_I[x][Y] = sum_i x_i^I C6[i][x][Y];  F_I[x][Z] = sum_a x_a^I D6[a][x][Z]
+        RCHK(gemm(ctx, mk(ic, Xb * Pp, o, xo + I0, Q, true, ctx->C6, Xb * Pp, false, ctx->Ec, Xb * Pp)));
+        RCHK(gemm(ctx, mk(ic, Xb * Pp, v, xv + I0, Q, true, ctx->D6, Xb * Pp, false, ctx->Fc, Xb * Pp)));
+        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6 line 10)
+        RCHK(gemm(ctx, mk(ic * o, P, v, ctx->Bq + I0 * ov, v, false, Yv, P, false, ctx->GYc, P)));
+        RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, Pp), ic, 0, o * P, Pp * Pp)));
+        {
+          Scope sc(ctx, "h_kernel");
+          HIPCHK(h_accumulate(Pp, Xb, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, s));
+        }
+      }
+      // I^X_ia = sum_YZ y_i^Z y_a^Y H^XYZ ; sigma^XW += sum_ia y_i^W y_a^W I^X_ia  (lines 13-16)
+      RCHK(gemm(ctx, mk(xb * Pp, o, P, ctx->Hb, Pp, false, Yo, P, true, ctx->R1, o)));
+      RCHK(gemm(ctx, batched(mk(o, v, P, ctx->R1, o, true, Yv, P, true, ctx->I6, v), xb, Pp * o, 0, ov)));
+      RCHK(gemm(ctx, mk(xb, P, ov, ctx->I6, ov, false, ctx->Bkr, P, false, ctx->sig + X0 * P, P, 1.0, 1.0)));
+      RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
+    }
+  }
+
+  // ---------------- Alg. 7: T2^2 rings (Eq. 35-37) ------------------------------------------
+  if (mask & THC_TERM_EQ35) {
+    // S^X_ia = - sum_YZ y_i^Y y_a^Z Gv[X][Y] Go[X][Z] T[Y][Z]  (lines 5-8)
+    {
+      Gemm g = batched(mk(o, P, P, Yo, P, false, T, P, false, ctx->U7, P), P, 0, 0, o * P);
+      g.kscaleA = ctx->Gv; g.ksA = 1; g.sksA = P;
+      RCHK(gemm(ctx, g));
+      Gemm h = batched(mk(o, v, P, ctx->U7, P, false, Yv, P, true, ctx->S7, v, -1.0, 0.0), P, o * P, 0, ov);
+      h.kscaleB = ctx->Go; h.ksB = 1; h.sksB = P;
+      RCHK(gemm(ctx, h));
+    }
+    // R^X = 2 sum_Y y_i^Y y_a^Y (S T)[X][Y] + S^X  (lines 3-4, 7)
+    MISC(k_copy2d(1, 1, P * ov, ctx->S7, P * ov, 0, ctx->R7, P * ov, 0, false, s));
+    RCHK(gemm(ctx, mk(P, ov, P, ctx->ST, P, false, ctx->Bkr, P, true, ctx->R7, ov, 2.0, 1.0)));
+    // half-transformed: Rx[X][i][J] = sum_a R[X][i][a] x_a^J (and Sx)
+    RCHK(gemm(ctx, mk(P * o, Q, v, ctx->R7, v, false, xv, Q, false, ctx->Rx, Q)));
+    RCHK(gemm(ctx, mk(P * o, Q, v, ctx->S7, v, false, xv, Q, false, ctx->Sx, Q)));
+    // C^XI = sum_ia x_i^I x_a^I R^X_ia ; D = C z ; sigma += 2 c_D C D^T  (lines 9-10, 22)
+    MISC(k_diag_eri(P, Q, o, xo, ctx->Rx, ctx->Cx, s));
+    RCHK(gemm(ctx, mk(P, Q, Q, ctx->Cx, Q, false, ctx->z, Q, false, ctx->Dx, Q)));
+    RCHK(gemm(ctx, mk(P, P, Q, ctx->Cx, Q, false, ctx->Dx, Q, true, ctx->sig, P, 2.0 * C_D, 1.0)));
+    // exchange parts, chunked over X (lines 12-21)
+    for (int64_t X0 = 0; X0 < P; X0 += ctx->Xc) {
+      const int64_t xc = std::min(ctx->Xc, P - X0);
+      for (int pass = 0; pass < 2; ++pass) {
+        const double* src = pass == 0 ? ctx->Rx : ctx->Sx;
+        double* dst = pass == 0 ? ctx->Gt : ctx->Gts;
+        // F^IJ = z^IJ sum_i x_i^I Rx[X][i][J]
+        Gemm g = batched(mk(Q, Q, o, xo, Q, true, src + X0 * o * Q, Q, false, ctx->F7, Q), xc, 0, o * Q, Q * Q);
+        g.hmul = ctx->z; g.ldh = Q; g.sH = 0;
+        RCHK(gemm(ctx, g));
+        // Gt[X][i][I] = sum_J x_i^J F^IJ
+        RCHK(gemm(ctx, batched(mk(o, Q, Q, xo, Q, false, ctx->F7, Q, true, dst + X0 * o * Q, Q), xc, 0, Q * Q, o * Q)));
+      }
+    }
+    // G^X_ia = sum_I Gt[X][i][I] x_a^I ; sigma += c_D ( - G R^T + G~ S^T )
+    RCHK(gemm(ctx, mk(P * o, v, Q, ctx->Gt, Q, false, xv, Q, true, ctx->G7, v)));
+    RCHK(gemm(ctx, mk(P * o, v, Q, ctx->Gts, Q, false, xv, Q, true, ctx->G7s, v)));
+    RCHK(gemm(ctx, mk(P, P, ov, ctx->G7, ov, false, ctx->R7, ov, true, ctx->sig, P, -C_D, 1.0)));
+    RCHK(gemm(ctx, mk(P, P, ov, ctx->G7s, ov, false, ctx->S7, ov, true, ctx->sig, P, C_D, 1.0)));
+  }
+
+  // ---------------- singles residual (Alg. 8 lines 12-13, Alg. 10) ----------------------------
+  if (sres && (mask & THC_TERM_EQ38)) {
+    // s38 was accumulated with undressed Lvv/Loo; the dressing adds -xi_oo^T t1 + t1 xi_vv^T
+    MISC(k_axpby(ov, 1.0, ctx->s38, 1.0, ctx->sig1, s));
+    if (singles) {
+      RCHK(gemm(ctx, mk(o, v, o, ctx->xioo, o, true, t1, v, false, ctx->sig1, v, -1.0, 1.0)));
+      RCHK(gemm(ctx, mk(o, v, v, t1, v, false, ctx->xivv, v, true, ctx->sig1, v, 1.0, 1.0)));
+    }
+  }
+  if (singles) {  // with t1 = 0 the Fock matrix is diag(eps) and these terms vanish
+    if (mask & THC_TERM_EQ42) {
+      // F^_ai + 2 Yo diag(T f) Yv^T - Yo (T o Mf^T) Yv^T, Mf = Yo^T F^ov Yv, f = diag(Mf)
+      MISC(k_copy2d(1, o, v, Fvo, o, 0, ctx->tmpov, v, 0, true, s));
+      MISC(k_axpby(ov, 1.0, ctx->tmpov, 1.0, ctx->sig1, s));
+      RCHK(gemm(ctx, mk(o, P, v, Fov, v, false, Yv, P, false, ctx->tmpoP, P)));
+      RCHK(gemm(ctx, mk(P, P, o, ctx->tmpoP, P, true, Yo, P, false, ctx->Qm, P)));  // Mf^T
+      MISC(k_diag(P, ctx->Qm, P, ctx->fd, s));
+      RCHK(gemm(ctx, mk(P, 1, P, T, P, false, ctx->fd, 1, false, ctx->Tf, 1)));
+      MISC(k_hadamard(PP, T, ctx->Qm, 1.0, 0.0, ctx->E9, s));
+      RCHK(gemm(ctx, mk(o, P, P, Yo, P, false, ctx->E9, P, false, ctx->tmpoP, P)));
+      RCHK(gemm(ctx, mk(o, v, P, ctx->tmpoP, P, false, Yv, P, true, ctx->sig1, v, -1.0, 1.0)));
+      Gemm g = mk(o, v, P, Yo, P, false, Yv, P, true, ctx->sig1, v, 2.0, 1.0);
+      g.kscaleA = ctx->Tf; g.ksA = 1;
+      RCHK(gemm(ctx, g));
+    }
+  }
+  return THC_OK;
+}
+
+double energy_from_scalars(const double* h, bool singles) {
+  // E = 2 Atil^T T Atil - sum T o M o M^T  (+ singles: 2 sum d_A^2 - sum tr K_A^2)
+  double e = 2.0 * h[0] - h[1];
+  if (singles) e += 2.0 * h[2] - h[3];
+  return e;
+}
+
+// sigma^ = W^T sigma W (into ctx->sigh) and the norms of sigma^ and sigma1 into scal[8], scal[9].
+int project_basis(thc_ctx* ctx) {
+  const int64_t P = ctx->P;
+  RCHK(gemm(ctx, mk(P, P, P, ctx->sig, P, false, ctx->W, P, false, ctx->Qm, P)));
+  RCHK(gemm(ctx, mk(P, P, P, ctx->W, P, true, ctx->Qm, P, false, ctx->sigh, P)));
+  MISC(k_dot(P * P, ctx->sigh, ctx->sigh, ctx->scal + 8, ctx->stream));
+  MISC(k_dot(ctx->ov, ctx->sig1, ctx->sig1, ctx->scal + 9, ctx->stream));
+  return THC_OK;
+}
+
+// Z = W T^ W^T
+int raw_from_basis(thc_ctx* ctx, const double* Th, double* Z) {
+  const int64_t P = ctx->P;
+  RCHK(gemm(ctx, mk(P, P, P, Th, P, false, ctx->W, P, true, ctx->Qm, P)));
+  RCHK(gemm(ctx, mk(P, P, P, ctx->W, P, false, ctx->Qm, P, false, Z, P)));
+  return THC_OK;
+}
+
+// T^ = W^T S Z S W
+int basis_from_raw(thc_ctx* ctx, const double* Z, double* Th) {
+  const int64_t P = ctx->P;
+  RCHK(gemm(ctx, mk(P, P, P, ctx->S, P, false, ctx->W, P, false, ctx->Qm, P)));    // S W
+  RCHK(gemm(ctx, mk(P, P, P, Z, P, false, ctx->Qm, P, false, ctx->E9, P)));         // Z S W
+  RCHK(gemm(ctx, mk(P, P, P, ctx->Qm, P, true, ctx->E9, P, false, Th, P)));         // W^T S Z S W
+  return THC_OK;
+}
+
+int need_built(thc_ctx* ctx) {
+  if (!ctx->built) {
+    ctx->err = "thc_build_factors has not completed";
+    return THC_ESTATE;
+  }
+  return THC_OK;
+}
+
+}  // namespace
+
+// =========================================================================================
+extern "C" {
+
+int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
+  if (!opt || !out) return THC_EINVAL;
+  *out = nullptr;
+  if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
+      opt->diis_max > 16 || opt->precision != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
+      opt->x_chunk < 0)
+    return THC_EINVAL;
+  thc_ctx* ctx = new (std::nothrow) thc_ctx();
+  if (!ctx) return THC_ENOMEM;
+  ctx->opt = *opt;
+  ctx->stream = (hipStream_t)stream;
+  ctx->o = opt->o; ctx->v = opt->v; ctx->n = opt->o + opt->v; ctx->nL = opt->nL;
+  ctx->P = opt->nP; ctx->Q = opt->nQ; ctx->ov = opt->o * opt->v;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return THC_EDEVICE;
+  }
+  *out = ctx;
+  return THC_OK;
+}
+
+int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const double* X, double* Zout) {
+  if (!ctx) return THC_EINVAL;
+  if (!L || !eps || !X) { ctx->err = "null input"; return THC_EINVAL; }
+  if (ctx->built) { ctx->err = "factors already built for this context"; return THC_ESTATE; }
+  hipStream_t s = ctx->stream;
+  RCHK(plan_and_alloc(ctx));
+  const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
+  const int64_t PP = P * P;
+  // integrals and factors into the library layout
+  MISC(k_copy2d(nL, o, o, L, n, n * n, ctx->Loo, o, o * o, false, s));
+  MISC(k_copy2d(nL, o, v, L + o, n, n * n, ctx->Lov, v, ov, false, s));
+  MISC(k_copy2d(nL, v, v, L + o * n + o, n, n * n, ctx->Lvv, v, v * v, false, s));
+  HIPCHK(hipMemcpyAsync(ctx->eps, eps, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->Yo, X, o * P * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->Yv, X + o * P, v * P * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->xo, X + (o + v) * P, o * Q * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->xv, X + (o + v) * P + o * Q, v * Q * sizeof(double), hipMemcpyDeviceToDevice, s));
+
+  // Grams and metric (Eq. 10): S = (Xo^T Xo) o (Xv^T Xv); Khatri-Rao B[(ia)][X]
+  RCHK(gemm(ctx, mk(P, P, o, ctx->Yo, P, true, ctx->Yo, P, false, ctx->Go, P)));
+  RCHK(gemm(ctx, mk(P, P, v, ctx->Yv, P, true, ctx->Yv, P, false, ctx->Gv, P)));
+  MISC(k_hadamard(PP, ctx->Go, ctx->Gv, 1.0, 0.0, ctx->S, s));
+  MISC(k_kr(o, v, P, ctx->Yo, ctx->Yv, ctx->Bkr, s));
+
+  // scratch for the set-up: reuse big work buffers (sized >= what is needed below)
+  std::vector<void*> scratch;
+  auto salloc = [&](size_t cnt) -> double* {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(cnt, 1) * sizeof(double)) != hipSuccess) return nullptr;
+    scratch.push_back(q);
+    return (double*)q;
+  };
+  auto sfree = [&]() {
+    for (void* q : scratch) (void)hipFree(q);
+    scratch.clear();
+  };
+  int rc = THC_OK;
+  do {
+    // ---- ERI fit (Eq. 19-20): G_Q xi^T = M, M^IA = sum_ia x_i^I x_a^I L_ia^A, z = xi^T xi ----
+    const int64_t CBn = (std::max(Q, P) + CB - 1) / CB;
+    double* GQ = salloc(Q * Q);
+    double* tmpQ = salloc(Q * Q);
+    double* Linv = salloc(CBn * CB * CB);
+    double* Mq = salloc(Q * nL);
+    double* Tl = salloc(std::min<int64_t>(nL, 256) * o * Q);
+    double* tmpw = salloc(std::max(Q, P) * std::max<int64_t>(std::max(nL, P), CB));
+    double* tsolve = salloc(CB * std::max(std::max(nL, P), Q));  // panel / block-row scratch
+    if (!GQ || !tmpQ || !Linv || !Mq || !Tl || !tmpw || !tsolve) { ctx->err = "set-up allocation failed"; rc = THC_ENOMEM; break; }
+    rc = gemm(ctx, mk(Q, Q, o, ctx->xo, Q, true, ctx->xo, Q, false, GQ, Q)); if (rc) break;
+    rc = gemm(ctx, mk(Q, Q, v, ctx->xv, Q, true, ctx->xv, Q, false, tmpQ, Q)); if (rc) break;
+    MISC(k_hadamard(Q * Q, GQ, tmpQ, 1.0, 0.0, GQ, s));
+    // M^T[A][I] in chunks of A: Tl[A][i][I] = sum_a L_ia^A x_a^I, then the diagonal contraction with xo
+    for (int64_t A0 = 0; A0 < nL && rc == THC_OK; A0 += 256) {
+      const int64_t na = std::min<int64_t>(256, nL - A0);
+      rc = gemm(ctx, mk(na * o, Q, v, ctx->Lov + A0 * ov, v, false, ctx->xv, Q, false, Tl, Q));
+      if (rc) break;
+      MISC(k_diag_eri(na, Q, o, ctx->xo, Tl, tmpw + A0 * Q, s));  // tmpw holds M^T (nL x Q)
+    }
+    if (rc) break;
+    MISC(k_copy2d(1, Q, nL, tmpw, Q, 0, Mq, nL, 0, true, s));  // M (Q x nL)
+    rc = potrf(ctx, GQ, Q, Linv, tsolve); if (rc) break;
+    rc = trsm(ctx, GQ, Q, Linv, Mq, nL, false, tsolve); if (rc) break;
+    rc = trsm(ctx, GQ, Q, Linv, Mq, nL, true, tsolve); if (rc) break;   // Mq = xi^T (Q x nL)
+    rc = gemm(ctx, mk(Q, Q, nL, Mq, nL, false, Mq, nL, true, ctx->z, Q)); if (rc) break;
+    // B_ia^I = sum_J x_i^J x_a^J z^IJ  (Alg. 6 line 2), layout [I][i][a]
+    {
+      Gemm g = batched(mk(Q, v, Q, ctx->z, Q, false, ctx->xv, Q, true, ctx->Bq, ov), o, 0, 0, v);
+      g.kscaleB = ctx->xo; g.ksB = 1; g.sksB = Q;
+      rc = gemm(ctx, g); if (rc) break;
+    }
+
+    // ---- working basis: E_mat w = e S w, E_mat = Go o (Xv^T eps_v Xv) - (Xo^T eps_o Xo) o Gv ----
+    double* Sl = salloc(PP);
+    double* Em = salloc(PP);
+    double* tP = salloc(PP);
+    if (!Sl || !Em || !tP) { ctx->err = "set-up allocation failed"; rc = THC_ENOMEM; break; }
+    {
+      Gemm g = mk(P, P, v, ctx->Yv, P, true, ctx->Yv, P, false, Em, P);
+      g.kscaleA = ctx->eps + o; g.ksA = 1;
+      rc = gemm(ctx, g); if (rc) break;
+      MISC(k_hadamard(PP, ctx->Go, Em, 1.0, 0.0, Em, s));
+      Gemm h = mk(P, P, o, ctx->Yo, P, true, ctx->Yo, P, false, tP, P);
+      h.kscaleA = ctx->eps; h.ksA = 1;
+      rc = gemm(ctx, h); if (rc) break;
+      MISC(k_hadamard(PP, tP, ctx->Gv, -1.0, 1.0, Em, s));
+    }
+    MISC(k_copy2d(1, P, P, ctx->S, P, 0, Sl, P, 0, false, s));
+    rc = potrf(ctx, Sl, P, Linv, tsolve); if (rc) break;
+    // C = L^-1 E L^-T : Y = L^-1 E, C = L^-1 Y^T
+    rc = trsm(ctx, Sl, P, Linv, Em, P, false, tsolve); if (rc) break;
+    MISC(k_copy2d(1, P, P, Em, P, 0, tmpw, P, 0, true, s));
+    rc = trsm(ctx, Sl, P, Linv, tmpw, P, false, tsolve); if (rc) break;
+    std::vector<double> hC(PP), hw(P);
+    HIPCHK(hipMemcpyAsync(hC.data(), tmpw, PP * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < P; ++i)
+      for (int64_t j = 0; j < i; ++j) {
+        const double a = 0.5 * (hC[i * P + j] + hC[j * P + i]);
+        hC[i * P + j] = a;
+        hC[j * P + i] = a;
+      }
+    if (host_syev(P, hC.data(), hw.data()) != 0) { ctx->err = "eigensolver did not converge"; rc = THC_ENUMERIC; break; }
+    if (hw[0] <= 0.0) { ctx->err = "projected Fock operator is not positive"; rc = THC_ESINGULAR; break; }
+    HIPCHK(hipMemcpyAsync(ctx->W, hC.data(), PP * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->e, hw.data(), P * sizeof(double), hipMemcpyHostToDevice, s));
+    rc = trsm(ctx, Sl, P, Linv, ctx->W, P, true, tsolve); if (rc) break;   // W = L^-T V
+
+    // ---- MP2 guess: M = B^T t_MP2 B with t_MP2 = -(ia|jb)/Delta, T^0 = W^T M W ----
+    {
+      const int64_t rc0 = std::max<int64_t>(1, std::min<int64_t>(ov, (int64_t)(1.0e9 / (8.0 * ov))));
+      double* tb = salloc(rc0 * ov);
+      double* tB = salloc(rc0 * P);
+      if (!tb || !tB) { ctx->err = "set-up allocation failed"; rc = THC_ENOMEM; break; }
+      rc = zero(ctx, tP, PP); if (rc) break;
+      for (int64_t r0 = 0; r0 < ov && rc == THC_OK; r0 += rc0) {
+        const int64_t rr = std::min(rc0, ov - r0);
+        rc = gemm(ctx, mk(rr, ov, nL, ctx->Lov + r0, ov, true, ctx->Lov, ov, false, tb, ov)); if (rc) break;
+        MISC(k_mp2_denom(r0, rr, ov, v, ctx->eps, o, tb, s));
+        rc = gemm(ctx, mk(rr, P, ov, tb, ov, false, ctx->Bkr, P, false, tB, P)); if (rc) break;
+        rc = gemm(ctx, mk(P, P, rr, ctx->Bkr + r0 * P, P, true, tB, P, false, tP, P, 1.0, 1.0)); if (rc) break;
+      }
+      if (rc) break;
+      rc = gemm(ctx, mk(P, P, P, tP, P, false, ctx->W, P, false, Em, P)); if (rc) break;
+      rc = gemm(ctx, mk(P, P, P, ctx->W, P, true, Em, P, false, ctx->Th, P)); if (rc) break;
+    }
+    rc = zero(ctx, ctx->t1, ov); if (rc) break;
+    rc = raw_from_basis(ctx, ctx->Th, ctx->Zs); if (rc) break;
+    if (Zout) HIPCHK(hipMemcpyAsync(Zout, ctx->Zs, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } while (0);
+  sfree();
+  if (rc != THC_OK) return rc;
+  ctx->built = true;
+  ctx->diis_n = 0;
+  ctx->diis_head = 0;
+  return THC_OK;
+}
+
+int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t mask, double* sigma, double* sigma1) {
+  if (!ctx) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  if (!Z || !sigma) { ctx->err = "null argument"; return THC_EINVAL; }
+  RCHK(residual_impl(ctx, Z, ctx->opt.singles ? t1 : nullptr, mask));
+  HIPCHK(hipMemcpyAsync(sigma, ctx->sig, ctx->P * ctx->P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  if (sigma1) HIPCHK(hipMemcpyAsync(sigma1, ctx->sig1, ctx->ov * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  return THC_OK;
+}
+
+int thc_residual(thc_ctx* ctx, const double* Z, const double* t1, double* sigma, double* sigma1, double* norms) {
+  if (!ctx) return THC_EINVAL;
+  RCHK(thc_residual_terms(ctx, Z, t1, THC_TERM_ALL, sigma, sigma1));
+  if (norms) {
+    RCHK(project_basis(ctx));
+    double h[10];
+    HIPCHK(hipMemcpyAsync(h, ctx->scal, 10 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    norms[0] = std::sqrt(h[8]);
+    norms[1] = std::sqrt(h[9]);
+    RCHK(check_finite_host(ctx, norms, 2, "residual norms"));
+  }
+  return THC_OK;
+}
+
+int thc_energy(thc_ctx* ctx, double* e_corr) {
+  if (!ctx || !e_corr) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  RCHK(residual_impl(ctx, ctx->Zs, ctx->t1, 0u));
+  double h[4];
+  RCHK(read_scalars(ctx, h, 4));
+  *e_corr = energy_from_scalars(h, ctx->opt.singles != 0);
+  RCHK(check_finite_host(ctx, e_corr, 1, "energy"));
+  return THC_OK;
+}
+
+int thc_get_state(thc_ctx* ctx, double* Z, double* t1) {
+  if (!ctx) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  if (Z) HIPCHK(hipMemcpyAsync(Z, ctx->Zs, ctx->P * ctx->P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  if (t1) HIPCHK(hipMemcpyAsync(t1, ctx->t1, ctx->ov * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  return THC_OK;
+}
+
+int thc_set_state(thc_ctx* ctx, const double* Z, const double* t1) {
+  if (!ctx || !Z) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  HIPCHK(hipMemcpyAsync(ctx->Zs, Z, ctx->P * ctx->P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  if (t1 && ctx->opt.singles)
+    HIPCHK(hipMemcpyAsync(ctx->t1, t1, ctx->ov * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  else
+    RCHK(zero(ctx, ctx->t1, ctx->ov));
+  RCHK(basis_from_raw(ctx, ctx->Zs, ctx->Th));
+  ctx->diis_n = 0;
+  ctx->diis_head = 0;
+  return THC_OK;
+}
+
+int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) {
+  if (!ctx || maxit < 1 || !(tol >= 0.0)) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  hipStream_t s = ctx->stream;
+  const int64_t P = ctx->P, PP = P * P, ov = ctx->ov, len = PP + ov;
+  const bool singles = ctx->opt.singles != 0;
+  const int dm = ctx->opt.diis_max;
+  double E_old = 0.0;
+  bool have_old = false;
+  for (int it = 1; it <= maxit; ++it) {
+    RCHK(residual_impl(ctx, ctx->Zs, singles ? ctx->t1 : nullptr, THC_TERM_ALL));
+    RCHK(project_basis(ctx));
+    double h[10];
+    RCHK(read_scalars(ctx, h, 10));
+    const double E = energy_from_scalars(h, singles);
+    const double rn = std::sqrt(h[8] + h[9]);
+    if (!std::isfinite(E) || !std::isfinite(rn)) {
+      ctx->err = "residual or energy is not finite";
+      if (iters) *iters = it;
+      return THC_ENUMERIC;
+    }
+    if (iters) *iters = it;
+    if (rnorm) *rnorm = rn;
+    if (have_old && rn < tol && std::fabs(E - E_old) < ctx->opt.tol_energy) return THC_OK;
+    E_old = E;
+    have_old = true;
+    // Jacobi step in the working basis; (dT, dt1) is the DIIS error vector
+    double* dTp = ctx->dT;
+    double* dt1p = ctx->dT + PP;
+    MISC(k_jacobi(P, ctx->o, ctx->v, ctx->sigh, ctx->e, singles ? ctx->sig1 : nullptr, ctx->eps, ctx->Th, ctx->t1,
+                  dTp, dt1p, s));
+    if (dm > 0) {
+      const int slot = ctx->diis_head;
+      double* vs = ctx->dvec + (int64_t)slot * len;
+      double* es = ctx->derr + (int64_t)slot * len;
+      HIPCHK(hipMemcpyAsync(vs, ctx->Th, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(vs + PP, ctx->t1, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(es, ctx->dT, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+      ctx->diis_head = (slot + 1) % dm;
+      if (ctx->diis_n < dm) ctx->diis_n++;
+      const int m = ctx->diis_n;
+      // inner products of the new error with every stored error (device), B on the host
+      std::vector<int> slots(m);
+      for (int k = 0; k < m; ++k) slots[k] = (ctx->diis_head - m + k + 2 * dm) % dm;  // oldest first
+      for (int k = 0; k < m; ++k)
+        MISC(k_dot(len, ctx->derr + (int64_t)slots[k] * len, es, ctx->scal + 16 + k, s));
+      double bd[16];
+      HIPCHK(hipMemcpyAsync(bd, ctx->scal + 16, m * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int k = 0; k < m; ++k) {
+        ctx->diisB[(size_t)slots[k] * dm + slot] = bd[k];
+        ctx->diisB[(size_t)slot * dm + slots[k]] = bd[k];
+      }
+      if (m >= 2) {
+        // Pulay: [B -1; -1 0] [c; l] = [0; -1], solved by Gaussian elimination with pivoting
+        const int N = m + 1;
+        std::vector<double> A((size_t)N * N), b(N, 0.0);
+        for (int i = 0; i < m; ++i)
+          for (int j = 0; j < m; ++j) A[(size_t)i * N + j] = ctx->diisB[(size_t)slots[i] * dm + slots[j]];
+        for (int i = 0; i < m; ++i) { A[(size_t)i * N + m] = -1.0; A[(size_t)m * N + i] = -1.0; }
+        A[(size_t)m * N + m] = 0.0;
+        b[m] = -1.0;
+        bool ok = true;
+        for (int c = 0; c < N && ok; ++c) {
+          int piv = c;
+          for (int r = c + 1; r < N; ++r)
+            if (std::fabs(A[(size_t)r * N + c]) > std::fabs(A[(size_t)piv * N + c])) piv = r;
+          if (std::fabs(A[(size_t)piv * N + c]) < 1e-300) { ok = false; break; }
+          if (piv != c) {
+            for (int k = 0; k < N; ++k) std::swap(A[(size_t)c * N + k], A[(size_t)piv * N + k]);
+            std::swap(b[c], b[piv]);
+          }
+          for (int r = c + 1; r < N; ++r) {
+            const double f = A[(size_t)r * N + c] / A[(size_t)c * N + c];
+            for (int k = c; k < N; ++k) A[(size_t)r * N + k] -= f * A[(size_t)c * N + k];
+            b[r] -= f * b[c];
+          }
+        }
+        std::vector<double> x(N, 0.0);
+        if (ok) {
+          for (int r = N - 1; r >= 0; --r) {
+            double acc = b[r];
+            for (int k = r + 1; k < N; ++k) acc -= A[(size_t)r * N + k] * x[k];
+            x[r] = acc / A[(size_t)r * N + r];
+          }
+          for (int k = 0; k < m; ++k) ok = ok && std::isfinite(x[k]);
+        }
+        if (ok) {
+          std::vector<const double*> vecs(m);
+          for (int k = 0; k < m; ++k) vecs[k] = ctx->dvec + (int64_t)slots[k] * len;
+          // extrapolate into the first work vector, then split into Th / t1
+          MISC(k_lincomb(len, m, x.data(), vecs.data(), ctx->dT, s));
+          HIPCHK(hipMemcpyAsync(ctx->Th, ctx->dT, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
+          HIPCHK(hipMemcpyAsync(ctx->t1, ctx->dT + PP, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+      }
+    }
+    RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
+  }
+  ctx->err = "iteration limit reached";
+  return THC_ENOTCONV;
+}
+
+int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return THC_EINVAL;
+  *bytes = ctx->bytes;
+  return THC_OK;
+}
+
+int thc_profile(thc_ctx* ctx, int enable) {
+  if (!ctx) return THC_EINVAL;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return THC_EDEVICE;
+  ctx->prof = enable != 0;
+  ctx->recs.clear();
+  ctx->pool_used = 0;
+  return THC_OK;
+}
+
+int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* launches) {
+  if (!ctx || !name) return THC_EINVAL;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : ctx->recs) {
+    if (r.name != name) continue;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    tot += ms;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return THC_OK;
+}
+
+int thc_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+              int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC,
+              int64_t batch, void* stream) {
+  if (M < 0 || N < 0 || K < 0 || batch < 0) return THC_EINVAL;
+  Gemm g = batched(mk(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc, alpha, beta), batch, sA, sB, sC);
+  if (gemm_f64(g, (hipStream_t)stream) != hipSuccess) return THC_EDEVICE;
+  return THC_OK;
+}
+
+const char* thc_last_error(const thc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void thc_destroy(thc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  for (auto ev : ctx->pool) (void)hipEventDestroy(ev);
+  delete ctx;
+}
+
+}  // extern "C"

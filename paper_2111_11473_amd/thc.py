@@ -1,0 +1,210 @@
+"""ctypes binding of libthc.so (C ABI in include/thc.h).
+
+Argument marshalling only: tensors are passed as device pointers, the stream is torch's
+current HIP stream, and every computation runs in the library's kernels.  There is no CPU
+fallback: if the library is missing or the tensors are not on the GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libthc.so")
+
+THC_OK, THC_EINVAL, THC_ENOMEM, THC_EDEVICE, THC_ESINGULAR, THC_ENUMERIC, THC_ENOTCONV, THC_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+ERRNAMES = {0: "THC_OK", -1: "THC_EINVAL", -2: "THC_ENOMEM", -3: "THC_EDEVICE", -4: "THC_ESINGULAR",
+            -5: "THC_ENUMERIC", -6: "THC_ENOTCONV", -7: "THC_ESTATE"}
+
+TERM_EQ28, TERM_EQ29, TERM_EQ31, TERM_EQ32, TERM_EQ35, TERM_EQ41, TERM_EQ38, TERM_EQ42 = (1 << k for k in range(8))
+TERM_ALL = 0xFF
+TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TERM_EQ32, "eq35": TERM_EQ35,
+         "eq41": TERM_EQ41, "eq38": TERM_EQ38, "eq42": TERM_EQ42}
+
+# exported symbols (kept in sync with include/thc.h; checked by the tests)
+SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_energy",
+           "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_profile", "thc_profile_get", "thc_dgemm",
+           "thc_last_error", "thc_destroy"]
+
+
+class Options(C.Structure):
+    _fields_ = [("o", C.c_int64), ("v", C.c_int64), ("nL", C.c_int64), ("nP", C.c_int64), ("nQ", C.c_int64),
+                ("singles", C.c_int32), ("diis_max", C.c_int32), ("tol_energy", C.c_double),
+                ("a_block", C.c_int64), ("i_chunk", C.c_int64), ("x_block", C.c_int64), ("x_chunk", C.c_int64),
+                ("precision", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ThcError(RuntimeError):
+    def __init__(self, rc, msg):
+        super().__init__(f"{ERRNAMES.get(rc, rc)}: {msg}")
+        self.rc = rc
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libthc.so and declares the prototypes; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2111_11473_amd.build`")
+    lib = C.CDLL(path)
+    P, I64, D, VP = C.c_void_p, C.c_int64, C.c_double, C.c_void_p
+    lib.thc_create.argtypes = [C.POINTER(Options), VP, C.POINTER(VP)]
+    lib.thc_build_factors.argtypes = [VP, P, P, P, P]
+    lib.thc_residual.argtypes = [VP, P, P, P, P, C.POINTER(D)]
+    lib.thc_residual_terms.argtypes = [VP, P, P, C.c_uint32, P, P]
+    lib.thc_iterate.argtypes = [VP, D, C.c_int, C.POINTER(C.c_int), C.POINTER(D)]
+    lib.thc_energy.argtypes = [VP, C.POINTER(D)]
+    lib.thc_get_state.argtypes = [VP, P, P]
+    lib.thc_set_state.argtypes = [VP, P, P]
+    lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
+    lib.thc_profile.argtypes = [VP, C.c_int]
+    lib.thc_profile_get.argtypes = [VP, C.c_char_p, C.POINTER(D), C.POINTER(I64)]
+    lib.thc_dgemm.argtypes = [C.c_int, C.c_int, I64, I64, I64, D, P, I64, I64, P, I64, I64, D, P, I64, I64, I64, VP]
+    lib.thc_last_error.argtypes = [VP]
+    lib.thc_last_error.restype = C.c_char_p
+    lib.thc_destroy.argtypes = [VP]
+    lib.thc_destroy.restype = None
+    for name in SYMBOLS:
+        if name not in ("thc_last_error", "thc_destroy"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t, n=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def dgemm(A, B, C_out, transA=False, transB=False, alpha=1.0, beta=0.0):
+    """C = alpha op(A) op(B) + beta C on the library's MFMA kernel (2-D or batched 3-D tensors)."""
+    lib = load()
+    batched = A.dim() == 3
+    Am, Bm, Cm = (A, B, C_out) if batched else (A[None], B[None], C_out[None])
+    nb = Cm.shape[0]
+    M, N = Cm.shape[1], Cm.shape[2]
+    K = Am.shape[1] if transA else Am.shape[2]
+    sA = Am.stride(0) if Am.shape[0] > 1 else 0
+    sB = Bm.stride(0) if Bm.shape[0] > 1 else 0
+    rc = lib.thc_dgemm(int(transA), int(transB), M, N, K, alpha, _ptr(A, name="A"), Am.shape[2], sA, _ptr(B, name="B"),
+                       Bm.shape[2], sB, beta, _ptr(C_out, name="C"), N, Cm.stride(0), nb, _stream())
+    if rc != 0:
+        raise ThcError(rc, "thc_dgemm failed")
+    return C_out
+
+
+class THC:
+    """One THC-CCSD problem on the current GPU (all tensors float64, CUDA, contiguous)."""
+
+    def __init__(self, o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0,
+                 x_block=0, x_chunk=0):
+        self.lib = load()
+        self.o, self.v, self.nL, self.nP, self.nQ = o, v, nL, nP, nQ
+        self.singles = bool(singles)
+        opt = Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk, 0, 0)
+        h = C.c_void_p()
+        rc = self.lib.thc_create(C.byref(opt), _stream(), C.byref(h))
+        if rc != 0:
+            raise ThcError(rc, "thc_create failed")
+        self.ctx = h
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.thc_last_error(self.ctx)
+            raise ThcError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.thc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up -------------------------------------------------------------------------
+    def build_factors(self, L, eps, Xo, Xv, xo, xv):
+        """Uploads nothing itself: L, eps and the factors must already be GPU tensors.
+        Returns the MP2-guess core Z0 (nP x nP)."""
+        o, v, n = self.o, self.v, self.o + self.v
+        X = torch.cat([Xo.reshape(-1), Xv.reshape(-1), xo.reshape(-1), xv.reshape(-1)]).contiguous()
+        Z = torch.empty((self.nP, self.nP), dtype=torch.float64, device=L.device)
+        rc = self.lib.thc_build_factors(self.ctx, _ptr(L, self.nL * n * n, "L"), _ptr(eps, n, "eps"),
+                                        _ptr(X, o * self.nP + v * self.nP + (o + v) * self.nQ, "X"), _ptr(Z))
+        self._check(rc, "thc_build_factors")
+        return Z
+
+    # -- residual -----------------------------------------------------------------------
+    def residual(self, Z, t1=None, mask=TERM_ALL, norms=False):
+        sig = torch.empty((self.nP, self.nP), dtype=torch.float64, device=Z.device)
+        sig1 = torch.zeros((self.o, self.v), dtype=torch.float64, device=Z.device)
+        zp = _ptr(Z, self.nP ** 2, "Z")
+        tp = _ptr(t1, self.o * self.v, "t1")
+        if mask == TERM_ALL and norms:
+            nr = (C.c_double * 2)()
+            rc = self.lib.thc_residual(self.ctx, zp, tp, _ptr(sig), _ptr(sig1), nr)
+            self._check(rc, "thc_residual")
+            return sig, sig1, (nr[0], nr[1])
+        rc = self.lib.thc_residual_terms(self.ctx, zp, tp, C.c_uint32(mask), _ptr(sig), _ptr(sig1))
+        self._check(rc, "thc_residual_terms")
+        return sig, sig1
+
+    # -- solver -------------------------------------------------------------------------
+    def iterate(self, tol=1e-8, maxit=100, raise_on_notconv=True):
+        it = C.c_int(0)
+        rn = C.c_double(0.0)
+        rc = self.lib.thc_iterate(self.ctx, tol, maxit, C.byref(it), C.byref(rn))
+        if rc == THC_ENOTCONV and not raise_on_notconv:
+            return it.value, rn.value, False
+        self._check(rc, "thc_iterate")
+        return it.value, rn.value, True
+
+    def energy(self):
+        e = C.c_double(0.0)
+        self._check(self.lib.thc_energy(self.ctx, C.byref(e)), "thc_energy")
+        return e.value
+
+    def get_state(self):
+        Z = torch.empty((self.nP, self.nP), dtype=torch.float64, device="cuda")
+        t1 = torch.empty((self.o, self.v), dtype=torch.float64, device="cuda")
+        self._check(self.lib.thc_get_state(self.ctx, _ptr(Z), _ptr(t1)), "thc_get_state")
+        return Z, t1
+
+    def set_state(self, Z, t1=None):
+        self._check(self.lib.thc_set_state(self.ctx, _ptr(Z, self.nP ** 2, "Z"), _ptr(t1, self.o * self.v, "t1")),
+                    "thc_set_state")
+
+    def memory_bytes(self):
+        b = C.c_size_t(0)
+        self._check(self.lib.thc_memory_bytes(self.ctx, C.byref(b)), "thc_memory_bytes")
+        return b.value
+
+    # -- profiling ----------------------------------------------------------------------
+    def profile(self, enable=True):
+        self._check(self.lib.thc_profile(self.ctx, int(enable)), "thc_profile")
+
+    def profile_get(self, name):
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(self.lib.thc_profile_get(self.ctx, name.encode(), C.byref(ms), C.byref(n)), "thc_profile_get")
+        return ms.value, n.value

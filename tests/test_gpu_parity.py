@@ -1,0 +1,146 @@
+"""GPU parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 throughout, so the bar is agreement to rounding: every projected residual term to
+1e-10 relative (max-norm), energies to 1e-10 Eh, converged energies to 1e-9 Eh.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle import ccsd
+from paper_2111_11473_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL_TERM = 1e-10
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def thc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_11473_amd import thc as mod
+    mod.load()
+    return mod
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _make(thc, cfg, singles=True, **kw):
+    s = synth.make_system(cfg)
+    ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, singles=singles, **kw)
+    Z0 = ctx.build_factors(_dev(s["L"]), _dev(s["eps"]), _dev(s["Xo"]), _dev(s["Xv"]), _dev(s["xo"]), _dev(s["xv"]))
+    return s, ctx, _host(Z0)
+
+
+def _state(s, Z0, seed):
+    rng = np.random.default_rng(seed)
+    P = Z0.shape[0]
+    R = rng.standard_normal((P, P))
+    Z = Z0 + 0.3 * np.abs(Z0).max() * (R + R.T)
+    t1 = 0.02 * rng.standard_normal((s["Xo"].shape[0], s["Xv"].shape[0]))
+    return Z, t1
+
+
+@pytest.mark.parametrize("shape", [(1, 37, 53, 29, False, False), (3, 130, 70, 257, True, False),
+                                   (2, 65, 200, 17, False, True), (1, 300, 129, 64, True, True),
+                                   (4, 16, 16, 16, False, False)])
+def test_dgemm_matches_numpy(thc, shape):
+    nb, M, N, K, tA, tB = shape
+    _say("dgemm", shape)
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((nb, K, M) if tA else (nb, M, K))
+    B = rng.standard_normal((nb, N, K) if tB else (nb, K, N))
+    C0 = rng.standard_normal((nb, M, N))
+    Cd = _dev(C0.copy())
+    thc.dgemm(_dev(A), _dev(B), Cd, transA=tA, transB=tB, alpha=0.7, beta=-0.3)
+    ref = 0.7 * np.matmul(A.transpose(0, 2, 1) if tA else A, B.transpose(0, 2, 1) if tB else B) - 0.3 * C0
+    assert np.abs(_host(Cd) - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name", ["small", "tiny"])
+def test_mp2_guess_and_energy(thc, name):
+    cfg = synth.CONFIGS[name]
+    _say("build", name)
+    s, ctx, Z0 = _make(thc, cfg)
+    Zref = oracle.mp2_guess(s["eps"], s["L"], s["Xo"], s["Xv"])
+    assert np.abs(Z0 - Zref).max() < 1e-9 * np.abs(Zref).max()
+    e_gpu = ctx.energy()
+    e_ref = ccsd.energy(s["L"], np.zeros((cfg.o, cfg.v)), oracle.amplitudes(s["Xo"], s["Xv"], Z0))
+    assert abs(e_gpu - e_ref) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["small", "tiny", "medium"])
+def test_residual_terms_match_oracle(thc, name):
+    """Each term group of the projected residual (Alg. 1-10) against the dense oracle, at a
+    state with t1 != 0 (T1-dressed integrals exercised)."""
+    cfg = synth.CONFIGS[name]
+    _say("terms", name)
+    s, ctx, Z0 = _make(thc, cfg)
+    Z, t1 = _state(s, Z0, 3)
+    z, _ = oracle.eri_fit(s["L"], cfg.o, s["xo"], s["xv"])
+    V = oracle.eri_thc_dense(s["xo"], s["xv"], z)
+    ref, refs = oracle.thc_residual(s["eps"], s["L"], s["Xo"], s["Xv"], Z, t1, V, terms=True)
+    ref["eq32+33"] = ref.pop("eq32") + ref.pop("eq33")
+    Zd, t1d = _dev(Z), _dev(t1)
+    for key, mask in thc.TERMS.items():
+        _say("  term", key)
+        sig, sig1 = ctx.residual(Zd, t1d, mask=mask)
+        if key in ("eq38", "eq42"):
+            got, want = _host(sig1), refs[key]
+        else:
+            got, want = _host(sig), ref[key]
+        err = np.abs(got - want).max() / np.abs(want).max()
+        assert err < RTOL_TERM, (key, err)
+    sig, sig1, norms = ctx.residual(Zd, t1d, norms=True)
+    tot = sum(ref.values())
+    assert np.abs(_host(sig) - tot).max() < RTOL_TERM * np.abs(tot).max()
+    s1 = refs["eq38"] + refs["eq42"]
+    assert np.abs(_host(sig1) - s1).max() < RTOL_TERM * np.abs(s1).max()
+    e, W = oracle.pseudo_canonical(s["Xo"], s["Xv"], s["eps"])
+    assert abs(norms[0] - np.linalg.norm(W.T @ tot @ W)) < 1e-9 * norms[0]
+    ctx.set_state(Zd, t1d)
+    e_ref = ccsd.energy(s["L"], t1, oracle.amplitudes(s["Xo"], s["Xv"], Z))
+    assert abs(ctx.energy() - e_ref) < 1e-10 * max(1.0, abs(e_ref))
+
+
+@pytest.mark.parametrize("singles", [True, False])
+def test_converged_energy_matches_oracle(thc, singles):
+    cfg = synth.CONFIGS["tiny"]
+    _say("iterate tiny singles", singles)
+    s, ctx, Z0 = _make(thc, cfg, singles=singles, tol_energy=1e-11)
+    it, rn, ok = ctx.iterate(tol=1e-10, maxit=60)
+    assert ok
+    e_gpu = ctx.energy()
+    r = oracle.solve(s["eps"], s["L"], s["Xo"], s["Xv"], s["xo"], s["xv"], singles=singles, tol=1e-10, tol_e=1e-11,
+                     maxit=60)
+    assert r.converged
+    assert abs(e_gpu - r.energy) < 1e-9
+    assert abs(it - r.iterations) <= 2
+
+
+def test_small_blocks_and_chunks(thc):
+    """The same residual with tiny fused-pass blocks, ERI chunks, H blocks and Alg. 7 chunks
+    (several blocks with ragged tails in every loop)."""
+    cfg = synth.CONFIGS["medium"]
+    _say("blocking medium")
+    s, ctx, Z0 = _make(thc, cfg)
+    _, ctx2, _ = _make(thc, cfg, a_block=8, i_chunk=13, x_block=64, x_chunk=9)
+    Z, t1 = _state(s, Z0, 5)
+    a, a1 = ctx.residual(_dev(Z), _dev(t1))
+    b, b1 = ctx2.residual(_dev(Z), _dev(t1))
+    assert np.abs(_host(a) - _host(b)).max() < 1e-12 * np.abs(_host(a)).max()
+    assert np.abs(_host(a1) - _host(b1)).max() < 1e-12 * np.abs(_host(a1)).max()
