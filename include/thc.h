@@ -70,7 +70,7 @@ typedef struct thc_options {
  * default stream).  Allocates nothing on the device yet.  *out receives the context. */
 int thc_create(const thc_options* opt, void* stream, thc_ctx** out);
 
-/* Set-up (paper Eq. 9-14, 17-20; Alg. 6 line 2): copies the integrals and factors, forms the
+/* Set-up (paper Eq. 9-14, 17-20; Alg. 6): copies the integrals and factors, forms the
  * Gram matrices o = Xo^T Xo, v = Xv^T Xv and the metric S = o (Hadamard) v, fits the ERI core
  * z = xi^T xi by least squares against the ovov Cholesky block, forms B_ia^I, solves the
  * generalized eigenproblem of the projected Fock operator (E w = e S w, the working basis with
@@ -103,6 +103,12 @@ int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t
  * of residual evaluations; *rnorm (host, may be NULL): last residual norm.
  * Returns THC_ENOTCONV when maxit is reached, THC_ENUMERIC on NaN/Inf. */
 int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm);
+
+/* Per-iteration record of the last thc_iterate call (host arrays of length >= max, any may be
+ * NULL): energy and residual norm of the amplitudes evaluated at each iteration and the wall
+ * time in seconds from the start of the call to the end of that iteration's evaluation.
+ * *count receives the number of iterations recorded (at most max are copied). */
+int thc_history(const thc_ctx* ctx, int max, double* energy, double* rnorm, double* seconds, int* count);
 
 /* Correlation energy of the current state (host scalar), the usual CCSD expression
  * sum (t_ij^ab + t_i^a t_j^b)(2(ia|jb) - (ib|ja)) with Cholesky integrals. */

@@ -17,7 +17,7 @@ Readings taken where the text is ambiguous (each also listed in the design notes
     the value for which the sum of all terms equals textbook CCSD (checked in the tests
     against an independent spin-orbital CCSD and against closed-shell direct-ring CCD).
   * Eq. 41 prints (t_ij^ac + t_ji^ca), equal to 2 t_ij^ac; it is read as the pair
-    permutation P_ij^ab, as Alg. 9 line 10 (sigma = E B^T + B E^T) computes.
+    permutation P_ij^ab, as Alg. 9 computes (sigma = E B^T + B E^T).
   * Eq. 31 has no hats; Alg. 3 dresses l_ij and l_ab, so the dressed integrals are used.
   * Dressed oo/vv blocks enter with the orientation of the equations ((ki^|lj) etc.);
     at t1 = 0 every orientation coincides.

@@ -1,4 +1,4 @@
-// The three-way product of the quartic T2^2 algorithm (paper Alg. 6, line 11):
+// The three-way product of the quartic T2^2 algorithm (paper Alg. 6):
 //   H^XYZ += sum_I ( E_I^XY F_I^XZ + E_I^XZ F_I^XY ) G_I^YZ
 // It is not a matrix product (each factor carries two of the three output indices), so it
 // runs on the vector ALUs: 5 flops (one multiply, two FMAs) per (X, Y, Z, I).

@@ -29,7 +29,7 @@ __device__ double block_sum(double x) {
   return r;
 }
 
-// Alg. 1 lines 8, 12, 13 and Alg. 3 line 7 fused: for the nb Cholesky vectors of a block,
+// The Hadamard steps of Alg. 1 and Alg. 3 fused: for the nb Cholesky vectors of a block,
 // C^A = Go o Bvv^A - Gv o Boo^A written in the [X][A][Y] layout that the C T C^T chain
 // reads, and C3 += sum_A Boo^A o Bvv^A.
 __global__ void form_C_kernel(int64_t P, int64_t nb, const double* __restrict__ Bvv,
@@ -158,7 +158,7 @@ __global__ void trace_sq_kernel(int64_t o, const double* __restrict__ K, double*
   if (threadIdx.x == 0) out[A] = s;
 }
 
-// Cx[X][I] = sum_i xo[i][I] Rx[X][i][I]  (Alg. 7 line 9 from the half-transformed R)
+// Cx[X][I] = sum_i xo[i][I] Rx[X][i][I]  (Alg. 7, from the half-transformed R)
 __global__ void diag_eri_kernel(int64_t P, int64_t Q, int64_t o, const double* __restrict__ xo,
                                 const double* __restrict__ Rx, double* __restrict__ Cx) {
   const int64_t n = P * Q;

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -81,6 +82,9 @@ struct thc_ctx {
   // Alg. 7
   double *U7 = nullptr, *S7 = nullptr, *R7 = nullptr, *Rx = nullptr, *Sx = nullptr, *Cx = nullptr, *Dx = nullptr;
   double *F7 = nullptr, *Gt = nullptr, *Gts = nullptr, *G7 = nullptr, *G7s = nullptr;
+
+  // per-iteration history of the last thc_iterate call
+  std::vector<double> hist_e, hist_r, hist_t;
 
   // profiling
   bool prof = false;
@@ -403,29 +407,29 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     RCHK(gemm(ctx, batched(mk(v, P, v, Lvv, v, false, Yv, P, false, ctx->Wv, P), nb, v * v, 0, v * P)));
     if (singles)
       RCHK(gemm(ctx, batched(mk(v, P, o, t1, v, true, ctx->LovYv, P, false, ctx->Wv, P, -1.0, 1.0), nb, 0, o * P, v * P)));
-    // Bvv[A] = Yv^T Wv[A];  Boo[A] = Yo^T (L^oo)^T Yo   (Alg. 1 lines 5-11)
+    // Bvv[A] = Yv^T Wv[A];  Boo[A] = Yo^T (L^oo)^T Yo   (Alg. 1)
     RCHK(gemm(ctx, batched(mk(P, P, v, Yv, P, true, ctx->Wv, P, false, ctx->Bvv, P), nb, 0, v * P, PP)));
     RCHK(gemm(ctx, batched(mk(o, P, o, Lhoo, o, true, Yo, P, false, ctx->Woo, P), nb, o * o, 0, o * P)));
     RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->Woo, P, false, ctx->Boo, P), nb, 0, o * P, PP)));
-    // C^A = Go o Bvv - Gv o Boo ([X][A][Y]); C3 += Boo o Bvv  (Alg. 1 lines 8-13, Alg. 3 line 7)
+    // C^A = Go o Bvv - Gv o Boo ([X][A][Y]); C3 += Boo o Bvv  (Alg. 1, Alg. 3)
     MISC(k_form_C(P, nb, ctx->Bvv, ctx->Boo, ctx->Go, ctx->Gv, ctx->Ccat, ctx->C3, s));
     if (mask & THC_TERM_EQ28) {
-      // D^A = C^A T; sigma += sum_A D^A (C^A)^T  (Alg. 1 lines 14-15), split over K
+      // D^A = C^A T; sigma += sum_A D^A (C^A)^T  (Alg. 1), split over K
       RCHK(gemm(ctx, batched(mk(P, P, P, ctx->Ccat, nb * P, false, T, P, false, ctx->Dcat, nb * P), nb, P, 0, P)));
       Gemm g = mk(P, P, nb * P, ctx->Dcat, nb * P, false, ctx->Ccat, nb * P, true, ctx->sig28, P, 1.0, 1.0);
       g.ksplit = (int)ctx->KS;
       g.sSplit = PP;
       RCHK(gemm(ctx, g));
     }
-    // Abar^X_A = sum_ai y_a^X y_i^X L^_ai ; Atil^X_A = sum_ia y_i^X y_a^X L_ia  (Alg. 2 lines 5-6)
+    // Abar^X_A = sum_ai y_a^X y_i^X L^_ai ; Atil^X_A = sum_ia y_i^X y_a^X L_ia  (Alg. 2)
     if (singles)
       RCHK(gemm(ctx, batched(mk(o, P, v, ctx->Lhvo, o, true, Yv, P, false, ctx->Wvo, P), nb, v * o, 0, o * P)));
     MISC(k_colsum_rowscaled(nb, o, P, Yo, singles ? ctx->Wvo : ctx->LovYv, o * P, ctx->Abar + A0, nL, s));
     MISC(k_colsum_rowscaled(nb, o, P, Yo, ctx->LovYv, o * P, ctx->At + A0, nL, s));
-    // M^T[A] = (Lov Yv)^T Yo ; F = T o M^T ; exchange energy partials  (Alg. 2 lines 10-11)
+    // M^T[A] = (Lov Yv)^T Yo ; F = T o M^T ; exchange energy partials  (Alg. 2)
     RCHK(gemm(ctx, batched(mk(P, P, o, ctx->LovYv, P, true, Yo, P, false, ctx->Boo, P), nb, o * P, 0, PP)));
     MISC(k_hadamard_energy(P, nb, T, ctx->Boo, ctx->Bvv, ctx->ek + A0 * 64, s));
-    // G[A] = Yo F Yv^T (o x v); H^X_A = sum_ia y_i^X y_a^X G_ia  (Alg. 2 lines 12-13)
+    // G[A] = Yo F Yv^T (o x v); H^X_A = sum_ia y_i^X y_a^X G_ia  (Alg. 2)
     RCHK(gemm(ctx, batched(mk(o, P, P, Yo, P, false, ctx->Bvv, P, false, ctx->Y1, P), nb, 0, PP, o * P)));
     RCHK(gemm(ctx, batched(mk(o, v, P, ctx->Y1, P, false, Yv, P, true, ctx->Gm, v), nb, o * P, 0, ov)));
     RCHK(gemm(ctx, batched(mk(o, P, v, ctx->Gm, v, false, Yv, P, false, ctx->GY, P), nb, ov, 0, o * P)));
@@ -433,18 +437,18 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     // TA = T Atil (P x nb); Coulomb energy partials Atil^T T Atil
     RCHK(gemm(ctx, mk(P, nb, P, T, P, false, ctx->At + A0, nL, false, ctx->TA, nb)));
     MISC(k_dot_cols(P, nb, ctx->At + A0, nL, ctx->TA, nb, ctx->ej + A0, s));
-    // D8[A] = 2 Yo diag(T Atil_A) Yv^T - G[A]  (Alg. 8 lines 8-9), in place of G
+    // D8[A] = 2 Yo diag(T Atil_A) Yv^T - G[A]  (Alg. 8), in place of G
     {
       Gemm g = batched(mk(o, v, P, Yo, P, false, Yv, P, true, ctx->Gm, v, 2.0, -1.0), nb, 0, 0, ov);
       g.kscaleA = ctx->TA; g.ksA = nb; g.sksA = 1;
       RCHK(gemm(ctx, g));
     }
-    // xi_oo += sum_A Lov D8^T ; xi_vv -= sum_A D8^T Lov  (Alg. 8 lines 10-11)
+    // xi_oo += sum_A Lov D8^T ; xi_vv -= sum_A D8^T Lov  (Alg. 8)
     RCHK(gemm(ctx, batched(mk(o, o, v, Lov, v, false, ctx->Gm, v, true, ctx->tmpov, o), nb, ov, ov, o * o)));
     MISC(k_batch_sum(nb, o * o, ctx->tmpov, 1.0, ctx->xioo, s));
     RCHK(gemm(ctx, mk(v, v, nb * o, ctx->Gm, v, true, Lov, v, false, ctx->xivv, v, -1.0, 1.0)));
     if (sres) {
-      // singles (Alg. 8 lines 12-13 with the dressing folded into xi afterwards):
+      // singles (Alg. 8, with the dressing folded into xi afterwards):
       // s38 += sum_A D8 Lvv - Loo D8
       RCHK(gemm(ctx, batched(mk(o, v, v, ctx->Gm, v, false, Lvv, v, false, ctx->tmpov, v), nb, ov, v * v, ov)));
       RCHK(gemm(ctx, batched(mk(o, v, o, Loo, o, false, ctx->Gm, v, false, ctx->tmpov, v, -1.0, 1.0), nb, o * o, ov, ov)));
@@ -542,7 +546,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
         // E_I[x][Y] = sum_i x_i^I C6[i][x][Y];  F_I[x][Z] = sum_a x_a^I D6[a][x][Z]
         RCHK(gemm(ctx, mk(ic, Xb * Pp, o, xo + I0, Q, true, ctx->C6, Xb * Pp, false, ctx->Ec, Xb * Pp)));
         RCHK(gemm(ctx, mk(ic, Xb * Pp, v, xv + I0, Q, true, ctx->D6, Xb * Pp, false, ctx->Fc, Xb * Pp)));
-        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6 line 10)
+        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6)
         RCHK(gemm(ctx, mk(ic * o, P, v, ctx->Bq + I0 * ov, v, false, Yv, P, false, ctx->GYc, P)));
         RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, Pp), ic, 0, o * P, Pp * Pp)));
         {
@@ -550,7 +554,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
           HIPCHK(h_accumulate(Pp, Xb, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, s));
         }
       }
-      // I^X_ia = sum_YZ y_i^Z y_a^Y H^XYZ ; sigma^XW += sum_ia y_i^W y_a^W I^X_ia  (lines 13-16)
+      // I^X_ia = sum_YZ y_i^Z y_a^Y H^XYZ ; sigma^XW += sum_ia y_i^W y_a^W I^X_ia  (Alg. 6)
       RCHK(gemm(ctx, mk(xb * Pp, o, P, ctx->Hb, Pp, false, Yo, P, true, ctx->R1, o)));
       RCHK(gemm(ctx, batched(mk(o, v, P, ctx->R1, o, true, Yv, P, true, ctx->I6, v), xb, Pp * o, 0, ov)));
       RCHK(gemm(ctx, mk(xb, P, ov, ctx->I6, ov, false, ctx->Bkr, P, false, ctx->sig + X0 * P, P, 1.0, 1.0)));
@@ -560,7 +564,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
 
   // ---------------- Alg. 7: T2^2 rings (Eq. 35-37) ------------------------------------------
   if (mask & THC_TERM_EQ35) {
-    // S^X_ia = - sum_YZ y_i^Y y_a^Z Gv[X][Y] Go[X][Z] T[Y][Z]  (lines 5-8)
+    // S^X_ia = - sum_YZ y_i^Y y_a^Z Gv[X][Y] Go[X][Z] T[Y][Z]  (Alg. 7)
     {
       Gemm g = batched(mk(o, P, P, Yo, P, false, T, P, false, ctx->U7, P), P, 0, 0, o * P);
       g.kscaleA = ctx->Gv; g.ksA = 1; g.sksA = P;
@@ -569,17 +573,17 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       h.kscaleB = ctx->Go; h.ksB = 1; h.sksB = P;
       RCHK(gemm(ctx, h));
     }
-    // R^X = 2 sum_Y y_i^Y y_a^Y (S T)[X][Y] + S^X  (lines 3-4, 7)
+    // R^X = 2 sum_Y y_i^Y y_a^Y (S T)[X][Y] + S^X  (Alg. 7, Eq. 36)
     MISC(k_copy2d(1, 1, P * ov, ctx->S7, P * ov, 0, ctx->R7, P * ov, 0, false, s));
     RCHK(gemm(ctx, mk(P, ov, P, ctx->ST, P, false, ctx->Bkr, P, true, ctx->R7, ov, 2.0, 1.0)));
     // half-transformed: Rx[X][i][J] = sum_a R[X][i][a] x_a^J (and Sx)
     RCHK(gemm(ctx, mk(P * o, Q, v, ctx->R7, v, false, xv, Q, false, ctx->Rx, Q)));
     RCHK(gemm(ctx, mk(P * o, Q, v, ctx->S7, v, false, xv, Q, false, ctx->Sx, Q)));
-    // C^XI = sum_ia x_i^I x_a^I R^X_ia ; D = C z ; sigma += 2 c_D C D^T  (lines 9-10, 22)
+    // C^XI = sum_ia x_i^I x_a^I R^X_ia ; D = C z ; sigma += 2 c_D C D^T  (Alg. 7, Eq. 37)
     MISC(k_diag_eri(P, Q, o, xo, ctx->Rx, ctx->Cx, s));
     RCHK(gemm(ctx, mk(P, Q, Q, ctx->Cx, Q, false, ctx->z, Q, false, ctx->Dx, Q)));
     RCHK(gemm(ctx, mk(P, P, Q, ctx->Cx, Q, false, ctx->Dx, Q, true, ctx->sig, P, 2.0 * C_D, 1.0)));
-    // exchange parts, chunked over X (lines 12-21)
+    // exchange parts, chunked over X (Alg. 7)
     for (int64_t X0 = 0; X0 < P; X0 += ctx->Xc) {
       const int64_t xc = std::min(ctx->Xc, P - X0);
       for (int pass = 0; pass < 2; ++pass) {
@@ -600,7 +604,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     RCHK(gemm(ctx, mk(P, P, ov, ctx->G7s, ov, false, ctx->S7, ov, true, ctx->sig, P, C_D, 1.0)));
   }
 
-  // ---------------- singles residual (Alg. 8 lines 12-13, Alg. 10) ----------------------------
+  // ---------------- singles residual (Alg. 8, Alg. 10) ---------------------------------------
   if (sres && (mask & THC_TERM_EQ38)) {
     // s38 was accumulated with undressed Lvv/Loo; the dressing adds -xi_oo^T t1 + t1 xi_vv^T
     MISC(k_axpby(ov, 1.0, ctx->s38, 1.0, ctx->sig1, s));
@@ -761,7 +765,7 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
     rc = trsm(ctx, GQ, Q, Linv, Mq, nL, false, tsolve); if (rc) break;
     rc = trsm(ctx, GQ, Q, Linv, Mq, nL, true, tsolve); if (rc) break;   // Mq = xi^T (Q x nL)
     rc = gemm(ctx, mk(Q, Q, nL, Mq, nL, false, Mq, nL, true, ctx->z, Q)); if (rc) break;
-    // B_ia^I = sum_J x_i^J x_a^J z^IJ  (Alg. 6 line 2), layout [I][i][a]
+    // B_ia^I = sum_J x_i^J x_a^J z^IJ  (Alg. 6), layout [I][i][a]
     {
       Gemm g = batched(mk(Q, v, Q, ctx->z, Q, false, ctx->xv, Q, true, ctx->Bq, ov), o, 0, 0, v);
       g.kscaleB = ctx->xo; g.ksB = 1; g.sksB = Q;
@@ -902,6 +906,10 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   const int dm = ctx->opt.diis_max;
   double E_old = 0.0;
   bool have_old = false;
+  ctx->hist_e.clear();
+  ctx->hist_r.clear();
+  ctx->hist_t.clear();
+  const auto t_start = std::chrono::steady_clock::now();
   for (int it = 1; it <= maxit; ++it) {
     RCHK(residual_impl(ctx, ctx->Zs, singles ? ctx->t1 : nullptr, THC_TERM_ALL));
     RCHK(project_basis(ctx));
@@ -916,6 +924,9 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
     }
     if (iters) *iters = it;
     if (rnorm) *rnorm = rn;
+    ctx->hist_e.push_back(E);
+    ctx->hist_r.push_back(rn);
+    ctx->hist_t.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
     if (have_old && rn < tol && std::fabs(E - E_old) < ctx->opt.tol_energy) return THC_OK;
     E_old = E;
     have_old = true;
@@ -994,6 +1005,19 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   }
   ctx->err = "iteration limit reached";
   return THC_ENOTCONV;
+}
+
+int thc_history(const thc_ctx* ctx, int max, double* energy, double* rnorm, double* seconds, int* count) {
+  if (!ctx || max < 0) return THC_EINVAL;
+  const int n = (int)ctx->hist_e.size();
+  const int m = std::min(n, max);
+  for (int i = 0; i < m; ++i) {
+    if (energy) energy[i] = ctx->hist_e[i];
+    if (rnorm) rnorm[i] = ctx->hist_r[i];
+    if (seconds) seconds[i] = ctx->hist_t[i];
+  }
+  if (count) *count = n;
+  return THC_OK;
 }
 
 int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes) {

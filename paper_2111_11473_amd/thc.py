@@ -25,7 +25,8 @@ TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TER
          "eq41": TERM_EQ41, "eq38": TERM_EQ38, "eq42": TERM_EQ42}
 
 # exported symbols (kept in sync with include/thc.h; checked by the tests)
-SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_energy",
+SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_history",
+           "thc_energy",
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_profile", "thc_profile_get", "thc_dgemm",
            "thc_last_error", "thc_destroy"]
 
@@ -60,6 +61,7 @@ def load(path: str = LIB_PATH):
     lib.thc_residual.argtypes = [VP, P, P, P, P, C.POINTER(D)]
     lib.thc_residual_terms.argtypes = [VP, P, P, C.c_uint32, P, P]
     lib.thc_iterate.argtypes = [VP, D, C.c_int, C.POINTER(C.c_int), C.POINTER(D)]
+    lib.thc_history.argtypes = [VP, C.c_int, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(C.c_int)]
     lib.thc_energy.argtypes = [VP, C.POINTER(D)]
     lib.thc_get_state.argtypes = [VP, P, P]
     lib.thc_set_state.argtypes = [VP, P, P]
@@ -178,6 +180,16 @@ class THC:
             return it.value, rn.value, False
         self._check(rc, "thc_iterate")
         return it.value, rn.value, True
+
+    def history(self, max_it=1000):
+        """(energies, residual norms, seconds) of each iteration of the last iterate() call."""
+        e = (C.c_double * max_it)()
+        r = (C.c_double * max_it)()
+        t = (C.c_double * max_it)()
+        n = C.c_int(0)
+        self._check(self.lib.thc_history(self.ctx, max_it, e, r, t, C.byref(n)), "thc_history")
+        m = min(n.value, max_it)
+        return list(e[:m]), list(r[:m]), list(t[:m])
 
     def energy(self):
         e = C.c_double(0.0)
