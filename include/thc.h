@@ -61,10 +61,14 @@ typedef struct thc_options {
   int64_t a_block;          /* Cholesky vectors per fused-pass block; 0 = automatic */
   int64_t i_chunk;          /* ERI grid points per H-kernel pass; 0 = automatic */
   int64_t x_block;          /* amplitude ranks per H block (multiple of 64); 0 = automatic */
-  int64_t x_chunk;          /* amplitude ranks per Alg. 7 exchange chunk; 0 = automatic */
+  int64_t x_chunk;          /* amplitude ranks per Alg. 7 exchange chunk (two-GEMM form); 0 = automatic */
   int32_t precision;        /* 0 = FP64 throughout (the only value accepted) */
-  int32_t reserved;
+  int32_t flags;            /* THC_FLAG_* bits; 0 = defaults */
 } thc_options;
+
+/* Alg. 7 exchange contraction: by default fused on chip (no Q x Q intermediate) when o <= 128;
+ * this flag forces the two-GEMM form with its x_chunk-blocked Q x Q intermediate instead. */
+#define THC_FLAG_UNFUSED_EXCHANGE (1 << 0)
 
 /* Creates a context bound to the current HIP device and to `stream` (hipStream_t; NULL = the
  * default stream).  Allocates nothing on the device yet.  *out receives the context. */

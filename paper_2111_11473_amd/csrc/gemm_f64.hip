@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(const Gemm g, const int64_t 
         if (m < g.M && n < g.N) {
           double x = g.alpha * acc[i][j][r];
           if (H) x *= H[m * g.ldh + n];
-          double* c = C + m * g.ldc + n;
+          double* c = g.pair_rows ? C + ((m >> 1) * g.ldc + n) * 2 + (m & 1) : C + m * g.ldc + n;
           if (g.beta != 0.0) x += g.beta * *c;
           *c = x;
         }

@@ -27,6 +27,7 @@ struct Gemm {
   const double* hmul = nullptr; int64_t ldh = 0, sH = 0;
   int64_t batch = 1;
   int ksplit = 1; int64_t sSplit = 0;
+  bool pair_rows = false;  // C element (m, n) at C[((m / 2) ldc + n) 2 + m % 2]: rows interleaved in pairs
 };
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
@@ -49,6 +50,8 @@ hipError_t k_hadamard(int64_t n, const double* x, const double* y, double alpha,
 hipError_t k_sym_add(int64_t P, const double* Q, double alpha, double* out, hipStream_t s);
 hipError_t k_dot_cols(int64_t P, int64_t nb, const double* X, int64_t ldx, const double* Y, int64_t ldy,
                       double* out, hipStream_t s);
+// y = A x for an M x K row-major A (one workgroup per row)
+hipError_t k_gemv(int64_t M, int64_t K, const double* A, int64_t lda, const double* x, double* y, hipStream_t s);
 hipError_t k_diag(int64_t P, const double* X, int64_t ldx, double* d, hipStream_t s);
 hipError_t k_trace_sq(int64_t nb, int64_t o, const double* K, double* out, hipStream_t s);
 hipError_t k_diag_eri(int64_t P, int64_t Q, int64_t o, const double* xo, const double* Rx, double* Cx,
@@ -64,8 +67,16 @@ hipError_t k_mp2_denom(int64_t rows0, int64_t rows, int64_t ov, int64_t v, const
 hipError_t k_fill(int64_t n, double val, double* x, hipStream_t s);
 hipError_t k_set_diag(int64_t n, const double* d, double* X, int64_t ld, hipStream_t s);
 
+// Fused exchange contraction Gt^X = xo (z o (xo^T Rx^X))^T for X = 0..nx-1 (kernels_exch.hip);
+// xo [o][Q], z [Q][Q], Rx and Gt [nx][o][Q].  Supported for 1 <= o <= 128.
+bool exch_supported(int64_t o);
+hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx,
+                      double* Gt, hipStream_t s);
+
 // VALU kernel for H^XYZ += sum_I (E^XY F^XZ + E^XZ F^XY) G^YZ (kernels_h.hip).
+// E, F: [I][Pp][Xb]; G: [I][Pp][Pp]; H: [Pp][Pp][Xb]; tiles from h_tiles(Pp, Xb).
 hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t nI, const double* E, const double* F, const double* G,
-                        double* H, hipStream_t s);
+                        double* H, const uint32_t* tiles, int64_t ntiles, hipStream_t s);
+std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb);
 
 }  // namespace thc

@@ -1,0 +1,146 @@
+// Exchange contraction of the T2^2 ring algorithm (paper Alg. 7, Eq. 37 exchange part), fused:
+//   Gt^X[i][I] = sum_J xo[i][J] z[I][J] sum_k xo[k][I] Rx^X[k][J]
+// for every X of a block.  Written as two products it materialises the Q x Q matrix
+// F^X = z o (xo^T Rx^X) for each X; here F never leaves the chip.
+//
+// A workgroup (4 waves) owns one X and a tile of 64 I (16 per wave) and walks J in blocks of 16.
+// Per J block each wave forms the transposed block Ft[J][I] = sum_k Rx[k][J] xo[k][I] with FP64
+// MFMA (16x16x4, K = o), scales it by z[I][J] in registers, and feeds it directly as the B
+// operand of the second product Gt[i][I] += sum_J xo[i][J] Ft[J][I]: in the MFMA register
+// layout, output element r of a lane (row lane/16 + 4 r, column lane % 16) is exactly the lane's
+// B element of k-step r (row lane/16, column lane % 16 of rows 4 r .. 4 r + 3).  The o x 16
+// slices of Rx^X and xo and the 64 x 16 slice of z for the next J block are prefetched into
+// registers while the current one is used from LDS.
+// Layouts (row-major): xo [o][Q]; z [Q][Q]; Rx, Gt [X][o][Q].  Requires o <= 16 OB.
+#include "internal.h"
+
+namespace thc {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BI = 64, BJ = 16, NT = 256;
+
+template <int OB>
+__global__ __launch_bounds__(NT) void exch_kernel(int64_t o, int64_t Q, const double* __restrict__ xo,
+                                                  const double* __restrict__ z, const double* __restrict__ Rx,
+                                                  double* __restrict__ Gt) {
+  constexpr int OP = 16 * OB;             // padded o
+  constexpr int NRX = (OP * BJ) / NT;     // Rx / xo slice elements per thread
+  constexpr int NZ = (BI * BJ) / NT;      // z slice elements per thread
+  static_assert((OP * BJ) % NT == 0, "whole slices per thread");
+  __shared__ double rx_s[OP * BJ];        // [k][j]
+  __shared__ double xj_s[BJ * (OP + 1)];  // [j][i], padded row
+  __shared__ double z_s[BJ * BI];         // [j][I]
+
+  const int64_t X = blockIdx.y;
+  const int64_t I0 = (int64_t)blockIdx.x * BI;
+  const double* __restrict__ R = Rx + X * o * Q;
+  double* __restrict__ out = Gt + X * o * Q;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t Iw = I0 + 16 * w + lr;    // this lane's I (B operand column, output column)
+  const int S = (int)((o + 3) / 4);       // k-steps of the first product
+
+  // B operand of the first product: xo[4 s + lk][Iw], held for the whole J walk
+  double xb[4 * OB];
+#pragma unroll
+  for (int s = 0; s < 4 * OB; ++s) {
+    const int64_t k = 4 * s + lk;
+    xb[s] = (k < o && Iw < Q) ? xo[k * Q + Iw] : 0.0;
+  }
+
+  double prx[NRX], pxj[NRX], pz[NZ];
+  auto load = [&](int64_t J0) {
+#pragma unroll
+    for (int q = 0; q < NRX; ++q) {
+      const int e = t + NT * q;
+      const int64_t k = e / BJ, J = J0 + e % BJ;
+      const bool ok = k < o && J < Q;
+      prx[q] = ok ? R[k * Q + J] : 0.0;
+      pxj[q] = ok ? xo[k * Q + J] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) {
+      const int e = t + NT * q;
+      const int64_t I = I0 + e / BJ, J = J0 + e % BJ;
+      pz[q] = (I < Q && J < Q) ? z[I * Q + J] : 0.0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < NRX; ++q) {
+      const int e = t + NT * q;
+      rx_s[e] = prx[q];
+      xj_s[(e % BJ) * (OP + 1) + e / BJ] = pxj[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) {
+      const int e = t + NT * q;
+      z_s[(e % BJ) * BI + e / BJ] = pz[q];
+    }
+  };
+
+  d4 acc[OB];
+#pragma unroll
+  for (int b = 0; b < OB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  load(0);
+  for (int64_t J0 = 0; J0 < Q; J0 += BJ) {
+    store();
+    __syncthreads();
+    if (J0 + BJ < Q) load(J0 + BJ);
+    // Ft[J][I] for J in this block (rows), this wave's 16 I (columns)
+    d4 ft = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4 * OB; ++s)
+      if (s < S) ft = __builtin_amdgcn_mfma_f64_16x16x4f64(rx_s[(4 * s + lk) * BJ + lr], xb[s], ft, 0, 0, 0);
+    // scale by z[I][J]: element r is (J = lk + 4 r, I = 16 w + lr)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ft[r] *= z_s[(lk + 4 * r) * BI + 16 * w + lr];
+    // Gt[i][I] += sum_J xo[i][J] Ft[J][I]; k-step r uses ft[r] as its B element
+#pragma unroll
+    for (int b = 0; b < OB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xj_s[(4 * r + lk) * (OP + 1) + 16 * b + lr], ft[r], acc[b], 0, 0,
+                                                      0);
+    __syncthreads();
+  }
+
+  // output element r of block b: i = 16 b + lk + 4 r, I = Iw
+  if (Iw < Q) {
+#pragma unroll
+    for (int b = 0; b < OB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = 16 * b + lk + 4 * r;
+        if (i < o) out[i * Q + Iw] = acc[b][r];
+      }
+  }
+}
+
+template <int OB>
+hipError_t launch(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx, double* Gt,
+                  hipStream_t s) {
+  const int64_t ti = (Q + BI - 1) / BI;
+  if (ti > 2147483647LL || nx > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(exch_kernel<OB>, dim3((unsigned)ti, (unsigned)nx), dim3(NT), 0, s, o, Q, xo, z, Rx, Gt);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool exch_supported(int64_t o) { return o >= 1 && o <= 128; }
+
+hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx,
+                      double* Gt, hipStream_t s) {
+  if (nx <= 0 || Q <= 0) return hipSuccess;
+  if (o <= 16) return launch<1>(o, Q, nx, xo, z, Rx, Gt, s);
+  if (o <= 32) return launch<2>(o, Q, nx, xo, z, Rx, Gt, s);
+  if (o <= 64) return launch<4>(o, Q, nx, xo, z, Rx, Gt, s);
+  if (o <= 128) return launch<8>(o, Q, nx, xo, z, Rx, Gt, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace thc

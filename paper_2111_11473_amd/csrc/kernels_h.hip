@@ -1,33 +1,70 @@
 // The three-way product of the quartic T2^2 algorithm (paper Alg. 6):
 //   H^XYZ += sum_I ( E_I^XY F_I^XZ + E_I^XZ F_I^XY ) G_I^YZ
-// It is not a matrix product (each factor carries two of the three output indices), so it
-// runs on the vector ALUs: 5 flops (one multiply, two FMAs) per (X, Y, Z, I).
+// Each factor carries two of the three output indices, so this is not a matrix product; it
+// runs on the FP64 vector ALUs.
 //
-// Work decomposition.  A 256-thread workgroup (4 wave64s) owns an 8 x 32 x 64 (X, Y, Z) tile of
-// H held in registers for the whole I range: lane = Z, wave = 8 Y, and the 8 X are shared by the
-// workgroup, so each thread keeps 64 accumulators (8 X by 8 Y at its Z).  E_I^XZ, F_I^XZ and
-// G_I^YZ are per-lane coalesced buffer loads (a descriptor per operand row block in SGPRs, one
-// 32-bit lane offset in a VGPR, the row offset in an SGPR, so no 64-bit per-lane addresses);
-// E_I^XY and F_I^XY are wave-uniform and are read with scalar loads into SGPRs.
-// Tiles are grouped 4 (X) x 2 (Y) x 4 (Z) and each group of 32 tiles goes to one XCD
-// (workgroup id mod 8 selects the XCD), so the workgroups resident on an XCD at the same time
-// share their E, F and G slices through that XCD's L2.
-// Layouts (row-major, rank zero-padded to Pp, a multiple of 64; X restricted to a block of Xb
-// ranks, a multiple of 8): E, F: [I][Xb][Pp]; G: [I][Pp][Pp]; H: [Xb][Pp][Pp].
+// Symmetry.  The bracket t_I(X; Y, Z) = E^XY F^XZ + E^XZ F^XY is symmetric in Y <-> Z, so for
+// Y != Z one t serves both H^XYZ (times G^YZ) and H^XZY (times G^ZY): 7 flops and 4 VALU
+// instructions for two outputs instead of 10 flops and 6 instructions.
+//
+// Work decomposition.  Lanes run over X (64 per wave).  Y and Z are cut into blocks of 16; a
+// workgroup owns one X tile, one Y block and a BZ = 4 NWZ wide slice of one Z block with
+// Yb <= Zb.  For Yb < Zb it accumulates both H^XYZ and its mirror H^XZY; a diagonal block
+// (Yb == Zb) covers every ordered pair inside itself directly and keeps no mirror.  Wave
+// (wy, wz) holds an 8 (Y) x 4 (Z) patch: 32 accumulators plus 32 mirror accumulators per lane.
+//
+// Operand staging.  E and F are stored with pairs of rows interleaved ([Y/2][X][2]), so one
+// 16-byte LDS read gives a lane both rows of a pair at its X (16-byte reads have about twice the
+// LDS bandwidth of 8-byte ones).  Per I the workgroup's rows -- E^XY, F^XY for its 16 Y, E^XZ,
+// F^XZ for its Z slice (64 X each, 1 KB per row pair, contiguous in HBM) -- and its two G blocks
+// are copied by buffer loads straight into LDS, NS stages deep (NS - 1 values of I in flight),
+// and each wave waits only for its own copies of the next stage before the barrier.  The only
+// factor that is uniform across the lanes, G, is held 16 values to a VGPR pair (lane l holds
+// value l % 16) and broadcast into the FMA by the DPP row_newbcast source modifier, so the
+// inner loop has no scalar loads.
+// Tile order comes from a host-built table: runs of 64 tiles sharing an X tile, 4 Y blocks and
+// 8 Z blocks go to one XCD (workgroup b runs on XCD b % 8), so the workgroups resident on an XCD
+// share their operand rows through its L2.
+// Layouts (ranks zero-padded to Pp, a multiple of 64; X restricted to a block of Xb ranks, a
+// multiple of 64): E, F: [I][Pp/2][Xb][2] (E_I^XY at [I][Y/2][X][Y%2]); G: [I][Pp][Pp];
+// H: [Pp][Pp][Xb] (H^XYZ at [Y][Z][X]).
+#include <vector>
+
 #include "internal.h"
 
 namespace thc {
 namespace {
 
-constexpr int HX = 8, HYW = 8, HW = 4, HZ = 64;
-constexpr int TY = HYW * HW;                                   // 32 Y per workgroup
-constexpr int GX = 4, GY = 2, GZ = 4, GT = GX * GY * GZ;       // tiles per XCD group
-constexpr int RSRC_W3 = 0x00020000;                            // raw 32-bit buffer access
+constexpr int LANES = 64;                  // X per wave and per workgroup
+constexpr int BY = 16;                     // Y (and Z) block edge
+constexpr int WY = 8, WZ = 4;              // per-wave patch
+constexpr int RSRC_W3 = 0x00020000;        // raw 32-bit buffer access
+constexpr uint32_t EMPTY = 0x80000000u;
+
+template <int NWZ, int NS>
+struct Geo {
+  static constexpr int NW = (BY / WY) * NWZ;        // waves per workgroup
+  static constexpr int NTHREADS = NW * LANES;
+  static constexpr int BZ = WZ * NWZ;               // Z slice per workgroup
+  static constexpr int NZS = BY / BZ;               // Z slices per block
+  // stage layout in doubles: row pairs of 64 X (128 doubles = 1 KB each), then the G blocks
+  static constexpr int EY = 0, FY = (BY / 2) * 128, EZ = BY * 128, FZ = EZ + (BZ / 2) * 128;
+  static constexpr int GOFF = FZ + (BZ / 2) * 128;  // G^YZ [BY][BZ]
+  static constexpr int GMOFF = GOFF + BY * BZ;      // G^ZY [BZ][BY]
+  static constexpr int STAGE = GMOFF + BZ * BY;
+  static constexpr int CH_ROWS = BY + BZ;           // 1 KB DMA chunks of row pairs
+  static constexpr int CH_G = BY * BZ / 128;        // 1 KB chunks per G block
+  static constexpr int QROWS = CH_ROWS / NW;        // row-pair chunks issued by every wave
+  static_assert((BY / 2) % NW == 0 && (BZ / 2) % NW == 0, "each row region splits evenly over the waves");
+  static_assert(2 * CH_G <= NW && (BY * BZ) % 128 == 0, "one round of G chunks");
+  static_assert(NS >= 2 && NS * STAGE * 8 <= 160 * 1024, "stages must fit in LDS");
+};
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
-__device__ inline __amdgpu_buffer_rsrc_t rsrc(const double* base, int64_t ndoubles) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(ndoubles * 8), RSRC_W3);
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const double* base, int64_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(uint32_t)nbytes, RSRC_W3);
 }
 __device__ inline double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
@@ -35,83 +72,261 @@ __device__ inline double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned
 __device__ inline void bstore(double x, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
 }
+// 16 bytes per lane from a buffer straight into LDS at lds + 16 * lane (no VGPR destination)
+__device__ inline void bload_lds(__amdgpu_buffer_rsrc_t r, double* lds, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, soff, 0, 0);
+}
 
-__global__ __launch_bounds__(256) void h_kernel(int Pp, int Xb, int64_t nI, const double* __restrict__ E,
-                                                const double* __restrict__ F, const double* __restrict__ G,
-                                                double* __restrict__ H, int ntx, int nty, int ntz, int gx,
-                                                int gy) {
-  // XCD-contiguous numbering of the tiles (the grid is a multiple of 8; workgroup b runs on XCD b % 8)
-  const int nblk = gridDim.x, b = blockIdx.x;
-  const int tix = (b & 7) * (nblk >> 3) + (b >> 3);
-  const int gid = tix / GT, in = tix % GT;
-  const int tx = (gid % gx) * GX + in % GX;
-  const int ty = ((gid / gx) % gy) * GY + (in / GX) % GY;
-  const int tz = (gid / (gx * gy)) * GZ + in / (GX * GY);
-  if (tx >= ntx || ty >= nty || tz >= ntz) return;
+// Waits until at most n of this wave's vector-memory operations are outstanding (n is
+// wave-uniform), then joins the workgroup barrier.  Written as one block so that neither the
+// wait nor the barrier picks up the compiler's conservative vmcnt(0).
+template <int N>
+__device__ inline void wait_bar() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+// Wait for stage I + 1 with `later` further stages (0 <= later < 3) of Q or Q + 1 copies each
+// (extra: this wave also copies a G chunk) still allowed in flight, then the barrier.
+template <int Q>
+__device__ inline void wait_pipe(int later, bool extra) {
+  if (later >= 2) {
+    if (extra) wait_bar<2 * (Q + 1)>(); else wait_bar<2 * Q>();
+  } else if (later == 1) {
+    if (extra) wait_bar<Q + 1>(); else wait_bar<Q>();
+  } else {
+    wait_bar<0>();
+  }
+}
 
+// One row j of the wave patch (four Z): t_k = ey fz_k + ez_k fy, then acc_k += G^YZ t_k and
+// accm_k += G^ZY t_k with G broadcast from lane B + k of each row of 16 lanes (B = 4 (j % 4)).
+// The instruction order keeps every DPP read at least two wait states after the VALU write of
+// t_k, as the hardware requires (inline assembly is invisible to the compiler's hazard pass).
+template <int B>
+__device__ inline void h_row(double (&acc)[WZ], double (&accm)[WZ], double ey, double fy, const double (&ez)[WZ],
+                             const double (&fz)[WZ], double g, double gm) {
+  double t0, t1, t2, t3;
+  asm("v_mul_f64 %[t0], %[ey], %[f0]\n\t"
+      "v_mul_f64 %[t1], %[ey], %[f1]\n\t"
+      "v_mul_f64 %[t2], %[ey], %[f2]\n\t"
+      "v_mul_f64 %[t3], %[ey], %[f3]\n\t"
+      "v_fma_f64 %[t0], %[e0], %[fy], %[t0]\n\t"
+      "v_fma_f64 %[t1], %[e1], %[fy], %[t1]\n\t"
+      "v_fma_f64 %[t2], %[e2], %[fy], %[t2]\n\t"
+      "v_fma_f64 %[t3], %[e3], %[fy], %[t3]\n\t"
+      "v_fmac_f64_dpp %[a0], %[g], %[t0] row_newbcast:%[b0]\n\t"
+      "v_fmac_f64_dpp %[m0], %[gm], %[t0] row_newbcast:%[b0]\n\t"
+      "v_fmac_f64_dpp %[a1], %[g], %[t1] row_newbcast:%[b1]\n\t"
+      "v_fmac_f64_dpp %[m1], %[gm], %[t1] row_newbcast:%[b1]\n\t"
+      "v_fmac_f64_dpp %[a2], %[g], %[t2] row_newbcast:%[b2]\n\t"
+      "v_fmac_f64_dpp %[m2], %[gm], %[t2] row_newbcast:%[b2]\n\t"
+      "v_fmac_f64_dpp %[a3], %[g], %[t3] row_newbcast:%[b3]\n\t"
+      "v_fmac_f64_dpp %[m3], %[gm], %[t3] row_newbcast:%[b3]"
+      : [a0] "+v"(acc[0]), [a1] "+v"(acc[1]), [a2] "+v"(acc[2]), [a3] "+v"(acc[3]), [m0] "+v"(accm[0]),
+        [m1] "+v"(accm[1]), [m2] "+v"(accm[2]), [m3] "+v"(accm[3]), [t0] "=&v"(t0), [t1] "=&v"(t1),
+        [t2] "=&v"(t2), [t3] "=&v"(t3)
+      : [ey] "v"(ey), [fy] "v"(fy), [e0] "v"(ez[0]), [e1] "v"(ez[1]), [e2] "v"(ez[2]), [e3] "v"(ez[3]),
+        [f0] "v"(fz[0]), [f1] "v"(fz[1]), [f2] "v"(fz[2]), [f3] "v"(fz[3]), [g] "v"(g), [gm] "v"(gm),
+        [b0] "n"(B), [b1] "n"(B + 1), [b2] "n"(B + 2), [b3] "n"(B + 3));
+}
+static_assert(WZ == 4 && WY == 8, "h_row covers four Z; a patch is eight rows");
+
+template <int NWZ, int NS>
+__global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int Xb, int64_t nI,
+                                                                   const double* __restrict__ E,
+                                                                   const double* __restrict__ F,
+                                                                   const double* __restrict__ G,
+                                                                   double* __restrict__ H,
+                                                                   const uint32_t* __restrict__ tiles) {
+  using C = Geo<NWZ, NS>;
+  const uint32_t tile = tiles[blockIdx.x];
+  if (tile & EMPTY) return;  // whole workgroup, before any barrier
+  const int Yb = tile & 511, Zb = (tile >> 9) & 511, zs = (tile >> 18) & 3, xt = (tile >> 20) & 1023;
+  const bool mirror = Yb != Zb;
+  const int y0 = Yb * BY, z0 = Zb * BY + zs * C::BZ, X0 = xt * LANES;
+
+  __shared__ double lds[NS * C::STAGE];
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int x0 = tx * HX, y0 = ty * TY + wave * HYW, z0 = tz * HZ;
-  const int64_t PP = (int64_t)Pp * Pp;    // per-I stride of G
-  const int64_t XP = (int64_t)Xb * Pp;    // per-I stride of E and F
-
-  // H tile rows: (x0 + xi, y0 + yi, z0 + lane), relative to the tile origin
-  const double* Hb = H + ((int64_t)x0 * Pp + y0) * Pp + z0;
-  const __amdgpu_buffer_rsrc_t rh = rsrc(Hb, ((int64_t)(HX - 1) * Pp + HYW) * Pp);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ly0 = (w % (BY / WY)) * WY, lz0 = (w / (BY / WY)) * WZ;
+  const unsigned xrow = (unsigned)Xb * 8u;  // bytes per (Y) row of H
   const unsigned lo = (unsigned)lane * 8u;
-  const unsigned rowb = (unsigned)Pp * 8u;  // bytes per rank row
-  double acc[HX][HYW];
-#pragma unroll
-  for (int xi = 0; xi < HX; ++xi)
-#pragma unroll
-    for (int yi = 0; yi < HYW; ++yi) acc[xi][yi] = bload(rh, lo, (unsigned)(xi * Pp + yi) * rowb);
 
-  const double* EI = E + (int64_t)x0 * Pp;
-  const double* FI = F + (int64_t)x0 * Pp;
-  const double* GI = G + (int64_t)y0 * Pp;
-  const unsigned zo = (unsigned)(z0 + lane) * 8u;
-  for (int64_t I = 0; I < nI; ++I, EI += XP, FI += XP, GI += PP) {
-    const __amdgpu_buffer_rsrc_t re = rsrc(EI, (int64_t)HX * Pp);
-    const __amdgpu_buffer_rsrc_t rf = rsrc(FI, (int64_t)HX * Pp);
-    const __amdgpu_buffer_rsrc_t rg = rsrc(GI, (int64_t)HYW * Pp);
-    double ez[HX], fz[HX], gz[HYW];
+  // A diagonal block has no mirror: its G^ZY slots stay zero (the DMA never writes them), so the
+  // mirror FMAs add nothing and the broadcast sources always come from LDS.
+  if (!mirror)
+    for (int i = threadIdx.x; i < C::BZ * BY; i += C::NTHREADS)
 #pragma unroll
-    for (int xi = 0; xi < HX; ++xi) {
-      ez[xi] = bload(re, zo, (unsigned)xi * rowb);
-      fz[xi] = bload(rf, zo, (unsigned)xi * rowb);
-    }
+      for (int b = 0; b < NS; ++b) lds[b * C::STAGE + C::GMOFF + i] = 0.0;
+
+  // accumulators: acc[j][k] = H[y0+ly0+j][z0+lz0+k][X0+lane], accm[j][k] = H[z0+lz0+k][y0+ly0+j][X0+lane]
+  double acc[WY][WZ], accm[WY][WZ];
+  const double* Hw = H + ((int64_t)(y0 + ly0) * Pp + z0 + lz0) * Xb + X0;
+  const double* Hm = H + ((int64_t)(z0 + lz0) * Pp + y0 + ly0) * Xb + X0;
+  const int64_t hw_bytes = ((int64_t)(WY - 1) * Pp + WZ) * Xb * 8;
+  const int64_t hm_bytes = ((int64_t)(WZ - 1) * Pp + WY) * Xb * 8;
+  {
+    const __amdgpu_buffer_rsrc_t rh = rsrc(Hw, hw_bytes);
+    const __amdgpu_buffer_rsrc_t rm = rsrc(Hm, hm_bytes);
 #pragma unroll
-    for (int yi = 0; yi < HYW; ++yi) gz[yi] = bload(rg, zo, (unsigned)yi * rowb);
+    for (int j = 0; j < WY; ++j)
 #pragma unroll
-    for (int xi = 0; xi < HX; ++xi) {
-      const double* __restrict__ ex = EI + xi * Pp + y0;  // wave-uniform row segment
-      const double* __restrict__ fx = FI + xi * Pp + y0;
+      for (int k = 0; k < WZ; ++k) acc[j][k] = bload(rh, lo, (unsigned)(j * Pp + k) * xrow);
+    if (mirror) {
 #pragma unroll
-      for (int yi = 0; yi < HYW; ++yi) {
-        const double t = ex[yi] * fz[xi] + fx[yi] * ez[xi];
-        acc[xi][yi] += t * gz[yi];
-      }
+      for (int j = 0; j < WY; ++j)
+#pragma unroll
+        for (int k = 0; k < WZ; ++k) accm[j][k] = bload(rm, lo, (unsigned)(k * Pp + j) * xrow);
+    } else {
+#pragma unroll
+      for (int j = 0; j < WY; ++j)
+#pragma unroll
+        for (int k = 0; k < WZ; ++k) accm[j][k] = 0.0;
     }
   }
 
+  // DMA plan of one stage: chunk c (1 KB) lands at stage + 128 c; wave w issues chunks w + NW q.
+  // Row-pair chunks come first (E^Y pairs, F^Y pairs, E^Z pairs, F^Z pairs; the region of each
+  // round q is fixed at compile time), then one round of G chunks, c = CH_ROWS + w: G^YZ
+  // (CH_G chunks of 128 / BZ rows of BZ) and, off the diagonal, G^ZY (CH_G chunks of 8 rows of 16).
+  const unsigned voff_r = (unsigned)lane * 16u;
+  const bool g_yz = w < C::CH_G, g_zy = !g_yz && w < 2 * C::CH_G && mirror;
+  const int gs = g_yz ? w : w - C::CH_G;
+  const unsigned voff_g = g_yz ? ((unsigned)(lane / (C::BZ / 2)) * (unsigned)Pp + 2u * (lane % (C::BZ / 2))) * 8u
+                               : ((unsigned)(lane / (BY / 2)) * (unsigned)Pp + 2u * (lane % (BY / 2))) * 8u;
+  const unsigned so_g = g_yz ? ((unsigned)(y0 + gs * (128 / C::BZ)) * (unsigned)Pp + (unsigned)z0) * 8u
+                             : ((unsigned)(z0 + gs * (128 / BY)) * (unsigned)Pp + (unsigned)y0) * 8u;
+  const bool extra = g_yz || g_zy;  // this wave copies QROWS + extra chunks per stage
+  const int64_t PX = (int64_t)Pp * Xb, PP = (int64_t)Pp * Pp;
+  auto stage_in = [&](int64_t I, int buf) {
+    const __amdgpu_buffer_rsrc_t re = rsrc(E + I * PX, PX * 8);
+    const __amdgpu_buffer_rsrc_t rf = rsrc(F + I * PX, PX * 8);
+    double* sb = lds + buf * C::STAGE;
 #pragma unroll
-  for (int xi = 0; xi < HX; ++xi)
+    for (int q = 0; q < C::QROWS; ++q) {
+      constexpr int ey_end = BY / 2, fy_end = BY, ez_end = BY + C::BZ / 2;
+      const int c0 = C::NW * q;  // first chunk of round q: fixes its region
+      const int c = w + c0;
+      const bool isF = (c0 >= ey_end && c0 < fy_end) || c0 >= ez_end;
+      const int pair = c0 < ey_end ? y0 / 2 + c
+                       : c0 < fy_end ? y0 / 2 + c - ey_end
+                       : c0 < ez_end ? z0 / 2 + c - fy_end
+                                     : z0 / 2 + c - ez_end;
+      bload_lds(isF ? rf : re, sb + c * 128, voff_r, ((unsigned)pair * (unsigned)Xb + (unsigned)X0) * 16u);
+    }
+    if (extra) bload_lds(rsrc(G + I * PP, PP * 8), sb + (C::CH_ROWS + w) * 128, voff_g, so_g);
+  };
+
+  // broadcast-register sources: lane l holds G^YZ[ly0 + 4 r + m / 4][lz0 + m % 4], m = l % 16
+  const int m = lane & 15;
+  const int goff0 = C::GOFF + (ly0 + (m >> 2)) * C::BZ + lz0 + (m & 3);
+  const int gmoff0 = C::GMOFF + (lz0 + (m & 3)) * BY + ly0 + (m >> 2);
+
+  constexpr int D = NS - 1;  // stages in flight ahead of the one being consumed
+  static_assert(D <= 3, "wait_pipe allows at most two stages in flight behind the next one");
+  int64_t issued = 0;
+  for (; issued < D && issued < nI; ++issued) stage_in(issued, (int)issued);
+  wait_pipe<C::QROWS>((int)(issued > 0 ? issued - 1 : 0), extra);  // stage 0 has landed everywhere
+  int buf = 0;
+  for (int64_t I = 0; I < nI; ++I) {
+    if (I + D < nI) {
+      stage_in(I + D, buf == 0 ? D : buf - 1);  // (buf + D) % NS, the buffer consumed at I - 1
+      ++issued;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const double* __restrict__ st = lds + buf * C::STAGE;
+    d2 ey[WY / 2], fy[WY / 2], ez[WZ / 2], fz[WZ / 2];
+    double g[2], gm[2];
 #pragma unroll
-    for (int yi = 0; yi < HYW; ++yi) bstore(acc[xi][yi], rh, lo, (unsigned)(xi * Pp + yi) * rowb);
+    for (int p = 0; p < WZ / 2; ++p) {
+      ez[p] = *(const d2*)&st[C::EZ + (lz0 / 2 + p) * 128 + 2 * lane];
+      fz[p] = *(const d2*)&st[C::FZ + (lz0 / 2 + p) * 128 + 2 * lane];
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      g[r] = st[goff0 + 4 * r * C::BZ];
+      gm[r] = st[gmoff0 + 4 * r];
+    }
+#pragma unroll
+    for (int p = 0; p < WY / 2; ++p) {
+      ey[p] = *(const d2*)&st[C::EY + (ly0 / 2 + p) * 128 + 2 * lane];
+      fy[p] = *(const d2*)&st[C::FY + (ly0 / 2 + p) * 128 + 2 * lane];
+    }
+    const double ezs[WZ] = {ez[0].x, ez[0].y, ez[1].x, ez[1].y};
+    const double fzs[WZ] = {fz[0].x, fz[0].y, fz[1].x, fz[1].y};
+    h_row<0>(acc[0], accm[0], ey[0].x, fy[0].x, ezs, fzs, g[0], gm[0]);
+    h_row<4>(acc[1], accm[1], ey[0].y, fy[0].y, ezs, fzs, g[0], gm[0]);
+    h_row<8>(acc[2], accm[2], ey[1].x, fy[1].x, ezs, fzs, g[0], gm[0]);
+    h_row<12>(acc[3], accm[3], ey[1].y, fy[1].y, ezs, fzs, g[0], gm[0]);
+    h_row<0>(acc[4], accm[4], ey[2].x, fy[2].x, ezs, fzs, g[1], gm[1]);
+    h_row<4>(acc[5], accm[5], ey[2].y, fy[2].y, ezs, fzs, g[1], gm[1]);
+    h_row<8>(acc[6], accm[6], ey[3].x, fy[3].x, ezs, fzs, g[1], gm[1]);
+    h_row<12>(acc[7], accm[7], ey[3].y, fy[3].y, ezs, fzs, g[1], gm[1]);
+    __builtin_amdgcn_sched_barrier(0);
+    // stage I + 1 must have landed; the stages after it (issued - I - 2 of them) may be in flight
+    const int64_t later = issued - I - 2;
+    wait_pipe<C::QROWS>((int)(later > 0 ? later : 0), extra);
+    buf = (buf + 1 == NS) ? 0 : buf + 1;
+  }
+
+  {
+    const __amdgpu_buffer_rsrc_t rh = rsrc(Hw, hw_bytes);
+    const __amdgpu_buffer_rsrc_t rm = rsrc(Hm, hm_bytes);
+#pragma unroll
+    for (int j = 0; j < WY; ++j)
+#pragma unroll
+      for (int k = 0; k < WZ; ++k) bstore(acc[j][k], rh, lo, (unsigned)(j * Pp + k) * xrow);
+    if (mirror) {
+#pragma unroll
+      for (int j = 0; j < WY; ++j)
+#pragma unroll
+        for (int k = 0; k < WZ; ++k) bstore(accm[j][k], rm, lo, (unsigned)(k * Pp + j) * xrow);
+    }
+  }
 }
+
+template <int NWZ>
+std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb) {
+  constexpr int NZS = BY / (WZ * NWZ);
+  const int64_t nB = Pp / BY, nX = Xb / LANES;
+  std::vector<uint32_t> lin;
+  for (int64_t xt = 0; xt < nX; ++xt)
+    for (int64_t gy = 0; gy < (nB + 3) / 4; ++gy)
+      for (int64_t gz = gy / 2; gz < (nB + 7) / 8; ++gz)
+        for (int64_t yb = gy * 4; yb < std::min(nB, gy * 4 + 4); ++yb)
+          for (int64_t zb = std::max(yb, gz * 8); zb < std::min(nB, gz * 8 + 8); ++zb)
+            for (int64_t s = 0; s < NZS; ++s) lin.push_back((uint32_t)(yb | (zb << 9) | (s << 18) | (xt << 20)));
+  const int64_t runs = ((int64_t)lin.size() + 63) / 64;
+  std::vector<uint32_t> out((size_t)(((runs + 7) / 8) * 512), EMPTY);
+  for (size_t e = 0; e < lin.size(); ++e) {
+    const int64_t c = (int64_t)e / 64, k = (int64_t)e % 64;
+    out[(size_t)((c / 8) * 512 + k * 8 + c % 8)] = lin[e];
+  }
+  return out;
+}
+
+template <int NWZ, int NS>
+hipError_t launch(int64_t Pp, int64_t Xb, int64_t nI, const double* E, const double* F, const double* G, double* H,
+                  const uint32_t* tiles, int64_t ntiles, hipStream_t s) {
+  if (Pp % 64 != 0 || Pp > 8192 || Xb % LANES != 0 || Xb > Pp || Xb <= 0 || ntiles <= 0 || ntiles > 2147483647LL ||
+      nI < 0)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((h_kernel<NWZ, NS>), dim3((unsigned)ntiles), dim3(Geo<NWZ, NS>::NTHREADS), 0, s, (int)Pp,
+                     (int)Xb, nI, E, F, G, H, tiles);
+  return hipGetLastError();
+}
+
+constexpr int H_NWZ = 2, H_NS = 3;  // 4 waves, 26 KB stages, three stages (two workgroups per CU)
 
 }  // namespace
 
+// Tile table: every (X tile, Y block Yb, Z block Zb >= Yb, Z slice) once, grouped into runs of
+// 64 tiles that share an X tile, 4 Y blocks and 8 Z blocks; run c is placed at workgroups
+// b = 512 (c / 8) + 8 k + (c % 8), k = 0..63, so that it runs on one XCD; unused slots are EMPTY.
+std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb) { return tiles_for<H_NWZ>(Pp, Xb); }
+
 hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t nI, const double* E, const double* F, const double* G,
-                        double* H, hipStream_t s) {
-  if (Pp % 64 != 0 || Pp > 8192 || Xb % HX != 0 || Xb > Pp || Xb <= 0) return hipErrorInvalidValue;
-  const int ntx = (int)(Xb / HX), nty = (int)(Pp / TY), ntz = (int)(Pp / HZ);
-  const int gx = (ntx + GX - 1) / GX, gy = (nty + GY - 1) / GY, gz = (ntz + GZ - 1) / GZ;
-  const int64_t nblk = (int64_t)gx * gy * gz * GT;  // a multiple of 8
-  if (nblk > 2147483647LL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(h_kernel, dim3((unsigned)nblk), dim3(256), 0, s, (int)Pp, (int)Xb, nI, E, F, G, H, ntx, nty,
-                     ntz, gx, gy);
-  return hipGetLastError();
+                        double* H, const uint32_t* tiles, int64_t ntiles, hipStream_t s) {
+  return launch<H_NWZ, H_NS>(Pp, Xb, nI, E, F, G, H, tiles, ntiles, s);
 }
 
 }  // namespace thc

@@ -141,6 +141,17 @@ __global__ void dot_cols_kernel(int64_t P, int64_t nb, const double* __restrict_
   if (threadIdx.x == 0) out[A] = s;
 }
 
+// y[m] = sum_k A[m][k] x[k]: one workgroup per row (the row is the long dimension)
+__global__ void gemv_kernel(int64_t K, const double* __restrict__ A, int64_t lda, const double* __restrict__ x,
+                            double* __restrict__ y) {
+  const int64_t m = blockIdx.x;
+  const double* a = A + m * lda;
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < K; k += blockDim.x) s += a[k] * x[k];
+  s = block_sum<TPB>(s);
+  if (threadIdx.x == 0) y[m] = s;
+}
+
 __global__ void diag_kernel(int64_t P, const double* __restrict__ X, int64_t ldx, double* __restrict__ d) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < P; e += (int64_t)gridDim.x * blockDim.x)
     d[e] = X[e * ldx + e];
@@ -292,6 +303,11 @@ hipError_t k_sym_add(int64_t P, const double* Q, double alpha, double* out, hipS
 hipError_t k_dot_cols(int64_t P, int64_t nb, const double* X, int64_t ldx, const double* Y, int64_t ldy,
                       double* out, hipStream_t s) {
   LAUNCH(dot_cols_kernel, dim3((unsigned)nb), dim3(TPB), P, nb, X, ldx, Y, ldy, out);
+}
+hipError_t k_gemv(int64_t M, int64_t K, const double* A, int64_t lda, const double* x, double* y, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  if (M > 2147483647LL) return hipErrorInvalidValue;
+  LAUNCH(gemv_kernel, dim3((unsigned)M), dim3(TPB), K, A, lda, x, y);
 }
 hipError_t k_diag(int64_t P, const double* X, int64_t ldx, double* d, hipStream_t s) {
   LAUNCH(diag_kernel, dim3(nblocks(P)), dim3(TPB), P, X, ldx, d);

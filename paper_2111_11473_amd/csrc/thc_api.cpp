@@ -78,6 +78,8 @@ struct thc_ctx {
   double *tmpoP = nullptr, *tmpvP = nullptr, *Fxoo = nullptr, *Fxvv = nullptr, *Tf = nullptr, *fd = nullptr;
   // Alg. 6
   double *C6 = nullptr, *D6 = nullptr, *Ec = nullptr, *Fc = nullptr, *Gc = nullptr, *GYc = nullptr, *Hb = nullptr;
+  uint32_t* htiles = nullptr;  // H-kernel tile table
+  int64_t nhtiles = 0;
   double *R1 = nullptr, *I6 = nullptr;
   // Alg. 7
   double *U7 = nullptr, *S7 = nullptr, *R7 = nullptr, *Rx = nullptr, *Sx = nullptr, *Cx = nullptr, *Dx = nullptr;
@@ -321,7 +323,7 @@ int plan_and_alloc(thc_ctx* ctx) {
       // Alg. 7
       {&ctx->U7, (size_t)(P * o * P)}, {&ctx->S7, (size_t)(P * ov)}, {&ctx->R7, (size_t)(P * ov)},
       {&ctx->Rx, (size_t)(P * o * Q)}, {&ctx->Sx, (size_t)(P * o * Q)}, {&ctx->Cx, (size_t)(P * Q)}, {&ctx->Dx, (size_t)(P * Q)},
-      {&ctx->F7, (size_t)(ctx->Xc * Q * Q)}, {&ctx->Gt, (size_t)(P * o * Q)}, {&ctx->Gts, (size_t)(P * o * Q)},
+      {&ctx->F7, (size_t)(exch_supported(o) && !(op.flags & THC_FLAG_UNFUSED_EXCHANGE) ? 1 : ctx->Xc * Q * Q)}, {&ctx->Gt, (size_t)(P * o * Q)}, {&ctx->Gts, (size_t)(P * o * Q)},
       {&ctx->G7, (size_t)(P * ov)}, {&ctx->G7s, (size_t)(P * ov)},
   };
   for (auto& a : list) RCHK(alloc(ctx, a.p, a.n));
@@ -332,6 +334,16 @@ int plan_and_alloc(thc_ctx* ctx) {
   RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
   RCHK(zero(ctx, ctx->Ec, ctx->Ic * Xb * Pp));
   RCHK(zero(ctx, ctx->Fc, ctx->Ic * Xb * Pp));
+  {
+    const std::vector<uint32_t> tiles = h_tiles(Pp, Xb);
+    double* tb = nullptr;
+    RCHK(alloc(ctx, &tb, (tiles.size() + 1) / 2));
+    ctx->htiles = reinterpret_cast<uint32_t*>(tb);
+    ctx->nhtiles = (int64_t)tiles.size();
+    HIPCHK(hipMemcpyAsync(ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   ctx->diisB.assign((size_t)std::max<int64_t>(dm, 1) * std::max<int64_t>(dm, 1), 0.0);
   return THC_OK;
 }
@@ -383,7 +395,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       Lhoo = ctx->Lhoo;
       MISC(k_trace_sq(nb, o, ctx->tmpoo, ctx->trK + A0, s));
       // d_A = sum_ia t_ia L_ia^A
-      RCHK(gemm(ctx, mk(nb, 1, ov, Lov, ov, false, t1, 1, false, ctx->dvecA + A0, 1)));
+      MISC(k_gemv(nb, ov, Lov, ov, t1, ctx->dvecA + A0, s));
       // Pv[A] = Lvv t1^T (v x o), in [A][a][k] and [a][A][k] layouts
       RCHK(gemm(ctx, batched(mk(v, o, v, Lvv, v, false, t1, v, true, ctx->Pv, o), nb, v * v, 0, v * o)));
       RCHK(gemm(ctx, batched(mk(v, o, v, Lvv, v, false, t1, v, true, ctx->PvT, nb * o), nb, v * v, 0, o)));
@@ -532,18 +544,19 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     const int64_t Xb = ctx->Xb;
     for (int64_t X0 = 0; X0 < P; X0 += Xb) {
       const int64_t xb = std::min(Xb, P - X0);
-      // C6[i][x][Y] = sum_W Gv[X][W] y_i^W T[W][Y];  D6[a][x][Y] = sum_W Go[X][W] y_a^W T[W][Y]
+      // C6[i][Y][x] = sum_W T[W][Y] y_i^W Gv[X][W];  D6[a][Y][x] = sum_W T[W][Y] y_a^W Go[X][W]
+      // stored [Y/2][x][Y%2] (X fastest, row pairs interleaved: the H-kernel's operand layout)
       {
-        Gemm g = batched(mk(xb, P, P, ctx->Gv + X0 * P, P, false, T, P, false, ctx->C6, Pp), o, 0, 0, Xb * Pp);
-        g.kscaleA = Yo; g.ksA = 1; g.sksA = P;
+        Gemm g = batched(mk(P, xb, P, T, P, true, ctx->Gv + X0 * P, P, true, ctx->C6, Xb), o, 0, 0, Xb * Pp);
+        g.kscaleA = Yo; g.ksA = 1; g.sksA = P; g.pair_rows = true;
         RCHK(gemm(ctx, g));
-        Gemm h = batched(mk(xb, P, P, ctx->Go + X0 * P, P, false, T, P, false, ctx->D6, Pp), v, 0, 0, Xb * Pp);
-        h.kscaleA = Yv; h.ksA = 1; h.sksA = P;
+        Gemm h = batched(mk(P, xb, P, T, P, true, ctx->Go + X0 * P, P, true, ctx->D6, Xb), v, 0, 0, Xb * Pp);
+        h.kscaleA = Yv; h.ksA = 1; h.sksA = P; h.pair_rows = true;
         RCHK(gemm(ctx, h));
       }
       for (int64_t I0 = 0; I0 < Q; I0 += ctx->Ic) {
         const int64_t ic = std::min(ctx->Ic, Q - I0);
-        // E_I[x][Y] = sum_i x_i^I C6[i][x][Y];  F_I[x][Z] = sum_a x_a^I D6[a][x][Z]
+        // E_I = sum_i x_i^I C6[i];  F_I = sum_a x_a^I D6[a]  (elementwise in the [Y/2][x][2] layout)
         RCHK(gemm(ctx, mk(ic, Xb * Pp, o, xo + I0, Q, true, ctx->C6, Xb * Pp, false, ctx->Ec, Xb * Pp)));
         RCHK(gemm(ctx, mk(ic, Xb * Pp, v, xv + I0, Q, true, ctx->D6, Xb * Pp, false, ctx->Fc, Xb * Pp)));
         // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6)
@@ -551,13 +564,14 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
         RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, Pp), ic, 0, o * P, Pp * Pp)));
         {
           Scope sc(ctx, "h_kernel");
-          HIPCHK(h_accumulate(Pp, Xb, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, s));
+          HIPCHK(h_accumulate(Pp, Xb, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles, ctx->nhtiles, s));
         }
       }
       // I^X_ia = sum_YZ y_i^Z y_a^Y H^XYZ ; sigma^XW += sum_ia y_i^W y_a^W I^X_ia  (Alg. 6)
-      RCHK(gemm(ctx, mk(xb * Pp, o, P, ctx->Hb, Pp, false, Yo, P, true, ctx->R1, o)));
-      RCHK(gemm(ctx, batched(mk(o, v, P, ctx->R1, o, true, Yv, P, true, ctx->I6, v), xb, Pp * o, 0, ov)));
-      RCHK(gemm(ctx, mk(xb, P, ov, ctx->I6, ov, false, ctx->Bkr, P, false, ctx->sig + X0 * P, P, 1.0, 1.0)));
+      // with H stored [Y][Z][x]: R1[Y][i][x] = sum_Z y_i^Z H[Y][Z][x], I6[i][a][x] = sum_Y y_a^Y R1[Y][i][x]
+      RCHK(gemm(ctx, batched(mk(o, xb, P, Yo, P, false, ctx->Hb, Xb, false, ctx->R1, Xb), P, 0, Pp * Xb, o * Xb)));
+      RCHK(gemm(ctx, batched(mk(v, xb, P, Yv, P, false, ctx->R1, o * Xb, false, ctx->I6, Xb), o, 0, Xb, v * Xb)));
+      RCHK(gemm(ctx, mk(xb, P, ov, ctx->I6, Xb, true, ctx->Bkr, P, false, ctx->sig + X0 * P, P, 1.0, 1.0)));
       RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
     }
   }
@@ -583,7 +597,12 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     MISC(k_diag_eri(P, Q, o, xo, ctx->Rx, ctx->Cx, s));
     RCHK(gemm(ctx, mk(P, Q, Q, ctx->Cx, Q, false, ctx->z, Q, false, ctx->Dx, Q)));
     RCHK(gemm(ctx, mk(P, P, Q, ctx->Cx, Q, false, ctx->Dx, Q, true, ctx->sig, P, 2.0 * C_D, 1.0)));
-    // exchange parts, chunked over X (Alg. 7)
+    // exchange parts (Alg. 7): fused on chip when o fits the kernel's tile, else two GEMMs per X chunk
+    if (exch_supported(o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE)) {
+      Scope sc(ctx, "exch");
+      HIPCHK(exch_fused(o, Q, P, xo, ctx->z, ctx->Rx, ctx->Gt, s));
+      HIPCHK(exch_fused(o, Q, P, xo, ctx->z, ctx->Sx, ctx->Gts, s));
+    } else
     for (int64_t X0 = 0; X0 < P; X0 += ctx->Xc) {
       const int64_t xc = std::min(ctx->Xc, P - X0);
       for (int pass = 0; pass < 2; ++pass) {
@@ -621,7 +640,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       RCHK(gemm(ctx, mk(o, P, v, Fov, v, false, Yv, P, false, ctx->tmpoP, P)));
       RCHK(gemm(ctx, mk(P, P, o, ctx->tmpoP, P, true, Yo, P, false, ctx->Qm, P)));  // Mf^T
       MISC(k_diag(P, ctx->Qm, P, ctx->fd, s));
-      RCHK(gemm(ctx, mk(P, 1, P, T, P, false, ctx->fd, 1, false, ctx->Tf, 1)));
+      MISC(k_gemv(P, P, T, P, ctx->fd, ctx->Tf, s));
       MISC(k_hadamard(PP, T, ctx->Qm, 1.0, 0.0, ctx->E9, s));
       RCHK(gemm(ctx, mk(o, P, P, Yo, P, false, ctx->E9, P, false, ctx->tmpoP, P)));
       RCHK(gemm(ctx, mk(o, v, P, ctx->tmpoP, P, false, Yv, P, true, ctx->sig1, v, -1.0, 1.0)));
@@ -684,7 +703,7 @@ int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
   if (!opt || !out) return THC_EINVAL;
   *out = nullptr;
   if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
-      opt->diis_max > 16 || opt->precision != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
+      opt->diis_max > 16 || opt->precision != 0 || (opt->flags & ~THC_FLAG_UNFUSED_EXCHANGE) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
       opt->x_chunk < 0)
     return THC_EINVAL;
   thc_ctx* ctx = new (std::nothrow) thc_ctx();

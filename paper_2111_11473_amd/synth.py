@@ -97,6 +97,9 @@ CONFIGS = {
     # parity-only sizes: several kernel tiles with ragged tails, oracle still fast
     "small": Config("small", 6, 22, 70, 50, 110, 30.0, 1010),
     "medium": Config("medium", 14, 66, 210, 170, 420, 30.0, 1011),
+    # wider occupied spaces: the fused exchange kernel's o <= 64 and o <= 128 instantiations
+    "occ40": Config("occ40", 40, 56, 200, 130, 300, 30.0, 1012),
+    "occ70": Config("occ70", 70, 30, 150, 120, 260, 30.0, 1013),
 }
 
 

@@ -21,6 +21,7 @@ ERRNAMES = {0: "THC_OK", -1: "THC_EINVAL", -2: "THC_ENOMEM", -3: "THC_EDEVICE", 
 
 TERM_EQ28, TERM_EQ29, TERM_EQ31, TERM_EQ32, TERM_EQ35, TERM_EQ41, TERM_EQ38, TERM_EQ42 = (1 << k for k in range(8))
 TERM_ALL = 0xFF
+FLAG_UNFUSED_EXCHANGE = 1 << 0
 TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TERM_EQ32, "eq35": TERM_EQ35,
          "eq41": TERM_EQ41, "eq38": TERM_EQ38, "eq42": TERM_EQ42}
 
@@ -35,7 +36,7 @@ class Options(C.Structure):
     _fields_ = [("o", C.c_int64), ("v", C.c_int64), ("nL", C.c_int64), ("nP", C.c_int64), ("nQ", C.c_int64),
                 ("singles", C.c_int32), ("diis_max", C.c_int32), ("tol_energy", C.c_double),
                 ("a_block", C.c_int64), ("i_chunk", C.c_int64), ("x_block", C.c_int64), ("x_chunk", C.c_int64),
-                ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("precision", C.c_int32), ("flags", C.c_int32)]
 
 
 class ThcError(RuntimeError):
@@ -117,11 +118,12 @@ class THC:
     """One THC-CCSD problem on the current GPU (all tensors float64, CUDA, contiguous)."""
 
     def __init__(self, o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0,
-                 x_block=0, x_chunk=0):
+                 x_block=0, x_chunk=0, flags=0):
         self.lib = load()
         self.o, self.v, self.nL, self.nP, self.nQ = o, v, nL, nP, nQ
         self.singles = bool(singles)
-        opt = Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk, 0, 0)
+        opt = Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk, 0,
+                      flags)
         h = C.c_void_p()
         rc = self.lib.thc_create(C.byref(opt), _stream(), C.byref(h))
         if rc != 0:

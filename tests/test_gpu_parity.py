@@ -83,7 +83,7 @@ def test_mp2_guess_and_energy(thc, name):
     assert abs(e_gpu - e_ref) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["small", "tiny", "medium"])
+@pytest.mark.parametrize("name", ["small", "tiny", "medium", "occ40", "occ70"])
 def test_residual_terms_match_oracle(thc, name):
     """Each term group of the projected residual (Alg. 1-10) against the dense oracle, at a
     state with t1 != 0 (T1-dressed integrals exercised)."""
@@ -133,12 +133,13 @@ def test_converged_energy_matches_oracle(thc, singles):
 
 
 def test_small_blocks_and_chunks(thc):
-    """The same residual with tiny fused-pass blocks, ERI chunks, H blocks and Alg. 7 chunks
-    (several blocks with ragged tails in every loop)."""
+    """The same residual with tiny fused-pass blocks, ERI chunks, H blocks and the two-GEMM
+    Alg. 7 exchange in small X chunks (several blocks with ragged tails in every loop) against
+    the default plan (fused exchange)."""
     cfg = synth.CONFIGS["medium"]
     _say("blocking medium")
     s, ctx, Z0 = _make(thc, cfg)
-    _, ctx2, _ = _make(thc, cfg, a_block=8, i_chunk=13, x_block=64, x_chunk=9)
+    _, ctx2, _ = _make(thc, cfg, a_block=8, i_chunk=13, x_block=64, x_chunk=9, flags=thc.FLAG_UNFUSED_EXCHANGE)
     Z, t1 = _state(s, Z0, 5)
     a, a1 = ctx.residual(_dev(Z), _dev(t1))
     b, b1 = ctx2.residual(_dev(Z), _dev(t1))
