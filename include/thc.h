@@ -142,6 +142,62 @@ int thc_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double al
 const char* thc_last_error(const thc_ctx* ctx);
 void thc_destroy(thc_ctx* ctx);
 
+/* ---- Learned starting guess -------------------------------------------------------------------
+ * Not part of the paper: a small network proposes, per rank index P of the pseudo-canonical
+ * working basis (E_mat w = e S w), a diagonal scaling c_P of the MP2 guess and a shift delta_P of
+ * the Jacobi denominators.  The plain MP2 guess with delta = 0 stays the fallback.  All arrays
+ * are device pointers unless stated otherwise. */
+#define THC_GUESS_FEATURES 10
+
+/* phi[nP][10] (FP32) from the current state T^ (after thc_build_factors: the MP2 guess):
+ * [T^_PP, e_P, T^_PP e_P, eps_HOMO, eps_LUMO, mean eps_occ, mean eps_vir, nP / o,
+ *  ||T^||_F / sqrt(nP), sum_Q |T^_PQ|]. */
+int thc_guess_features(thc_ctx* ctx, float* phi);
+
+/* pred[nP][ld] (FP32): column 0 is c_P, column 1 (if ld >= 2) is delta_P.  Sets
+ * T^ <- diag(1 + c) T^ diag(1 + c) (and Z accordingly), and, if ld >= 2, the Jacobi denominators
+ * D_PQ = max(e_P + e_Q + delta_P + delta_Q, (e_P + e_Q) / 2) for later thc_iterate calls.
+ * Clears the DIIS history. */
+int thc_guess_apply(thc_ctx* ctx, const float* pred, int64_t ld);
+
+/* delta[nP] (FP64) as above, or NULL for the plain denominators e_P + e_Q.  Clears DIIS. */
+int thc_set_shift(thc_ctx* ctx, const double* delta);
+
+/* The current state in the working basis, T^[nP][nP], and (if sigma_hat is not NULL) the
+ * projected residual of that state in the working basis, sigma^ = W^T sigma W.  Either may be NULL. */
+int thc_working(thc_ctx* ctx, double* Th, double* sigma_hat);
+
+/* Training targets of one converged system (all [nP][nP] in the working basis): Th0 the guess,
+ * Tstar the converged state, sig0 the projected residual at the guess.  Writes c[nP], the
+ * least-squares diagonal scaling of Th0 onto Tstar (Gauss-Newton), and delta[nP], the
+ * least-squares secant fit -sig0 = (e_P + e_Q + delta_P + delta_Q)(Tstar - Th0).  Host FP64.
+ * THC_ESINGULAR if a normal matrix is not positive definite. */
+int thc_guess_targets(thc_ctx* ctx, const double* Th0, const double* Tstar, const double* sig0, double* c,
+                      double* delta);
+
+/* The network: n_in -> width -> width -> n_out, SiLU hidden activations, inputs standardized by
+ * (x - mu_in) / sd_in and outputs produced as y_n sd_out + mu_out.  FP32 parameters in one flat
+ * vector [W1 (n_in x width, row-major), b1, W2 (width x width), b2, W3 (width x n_out), b3],
+ * Glorot-uniform initial weights from `seed`, zero biases.  Bound to `stream` (hipStream_t). */
+typedef struct thc_mlp thc_mlp;
+int thc_mlp_create(int64_t n_in, int64_t width, int64_t n_out, uint64_t seed, void* stream, thc_mlp** out);
+/* Host arrays: mu_in, sd_in [n_in]; mu_out, sd_out [n_out]; scales must be positive. */
+int thc_mlp_set_norm(thc_mlp* net, const float* mu_in, const float* sd_in, const float* mu_out, const float* sd_out);
+int thc_mlp_num_params(const thc_mlp* net, int64_t* n);
+int thc_mlp_get_params(thc_mlp* net, float* p);       /* p[n] device */
+int thc_mlp_set_params(thc_mlp* net, const float* p); /* p[n] device; resets the Adam moments */
+/* FP32 forward: X[rows][n_in] -> Y[rows][n_out]. */
+int thc_mlp_forward(thc_mlp* net, const float* X, int64_t rows, float* Y);
+/* loss = mean over rows and outputs of (y_n - (T - mu_out) / sd_out)^2 (host float, may be NULL)
+ * and its gradient grad[n] (device, may be NULL), FP32. */
+int thc_mlp_loss_grad(thc_mlp* net, const float* X, const float* T, int64_t rows, float* loss, float* grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the loss above. */
+int thc_mlp_train_step(thc_mlp* net, const float* X, const float* T, int64_t rows, float lr, float* loss);
+/* BF16 inference on MFMA with FP32 accumulation (width 256, n_in <= 16, n_out <= 16). */
+int thc_mlp_infer(thc_mlp* net, const float* X, int64_t rows, float* Y);
+const char* thc_mlp_last_error(const thc_mlp* net);
+void thc_mlp_destroy(thc_mlp* net);
+
 #ifdef __cplusplus
 }
 #endif

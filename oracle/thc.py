@@ -144,10 +144,12 @@ def _diis_extrapolate(vecs, errs):
 
 
 def solve(eps, L, Xo, Xv, xo=None, xv=None, Z0=None, singles=True, tol=1e-8, tol_e=1e-8,
-          maxit=100, diis=8, V=None) -> SolveResult:
+          maxit=100, diis=8, V=None, scale=None, shift=None) -> SolveResult:
     """Jacobi + DIIS solution of sigma(Z, t1) = 0 in the pseudo-canonical basis.
     Each iteration: residual and energy at the current amplitudes, convergence test,
-    T^ <- T^ - sigma^/(e_P + e_Q), t1 <- t1 - sigma1/(eps_a - eps_i), DIIS(diis)."""
+    T^ <- T^ - sigma^/D, t1 <- t1 - sigma1/(eps_a - eps_i), DIIS(diis), with D_PQ = e_P + e_Q.
+    Learned-guess hooks: `scale` (c_P) starts from diag(1+c) T^0 diag(1+c); `shift` (delta_P)
+    uses D_PQ = max(e_P + e_Q + delta_P + delta_Q, (e_P + e_Q) / 2)."""
     o, v = Xo.shape[0], Xv.shape[0]
     if V is None and xo is not None:
         z, _ = eri_fit(L, o, xo, xv)
@@ -155,10 +157,14 @@ def solve(eps, L, Xo, Xv, xo=None, xv=None, Z0=None, singles=True, tol=1e-8, tol
     e, W = pseudo_canonical(Xo, Xv, eps)
     S = metric(Xo, Xv)
     D2 = e[:, None] + e[None, :]
+    if shift is not None:
+        D2 = np.maximum(D2 + shift[:, None] + shift[None, :], 0.5 * D2)
     D1 = eps[o:][None, :] - eps[:o][:, None]
     if Z0 is None:
         Z0 = mp2_guess(eps, L, Xo, Xv)
     Th = W.T @ S @ Z0 @ S @ W
+    if scale is not None:
+        Th = (1.0 + scale)[:, None] * Th * (1.0 + scale)[None, :]
     t1 = np.zeros((o, v))
     vecs, errs, hist = [], [], []
     E_old = None

@@ -58,8 +58,11 @@ hipError_t k_diag_eri(int64_t P, int64_t Q, int64_t o, const double* xo, const d
                       hipStream_t s);
 hipError_t k_dot(int64_t n, const double* x, const double* y, double* out, hipStream_t s);
 hipError_t k_sum(int64_t n, const double* x, double* out, hipStream_t s);
-hipError_t k_jacobi(int64_t P, int64_t o, int64_t v, const double* sh, const double* e, const double* s1,
+hipError_t k_jacobi(int64_t P, int64_t o, int64_t v, const double* sh, const double* e, const double* delta, const double* s1,
                     const double* eps, double* Th, double* t1, double* dT, double* dt1, hipStream_t s);
+hipError_t k_guess_features(int64_t P, int64_t o, int64_t v, const double* Th, const double* e, const double* eps,
+                            const double* fro2, float* phi, hipStream_t s);
+hipError_t k_guess_apply(int64_t P, const float* pred, int64_t ld, double* Th, double* delta, hipStream_t s);
 hipError_t k_lincomb(int64_t n, int m, const double* coef, const double* const* vecs, double* out, hipStream_t s);
 hipError_t k_kr(int64_t o, int64_t v, int64_t P, const double* Yo, const double* Yv, double* B, hipStream_t s);
 hipError_t k_mp2_denom(int64_t rows0, int64_t rows, int64_t ov, int64_t v, const double* eps, int64_t o,
@@ -72,6 +75,29 @@ hipError_t k_set_diag(int64_t n, const double* d, double* X, int64_t ld, hipStre
 bool exch_supported(int64_t o);
 hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx,
                       double* Gt, hipStream_t s);
+
+// Learned-guess network kernels (mlp.hip).  sgemm epilogues: 0 none, 1 bias + SiLU (pre-activation
+// to Z), 2 bias, 3 times SiLU'(Z).
+hipError_t mlp_sgemm(bool tA, bool tB, int epi, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                     const float* B, int64_t ldb, float* C, int64_t ldc, const float* bias, float* Z, int64_t ldz,
+                     hipStream_t s);
+hipError_t mlp_normalize(int64_t rows, int64_t cols, const float* X, const float* mu, const float* sd, float* Xn,
+                         hipStream_t s);
+hipError_t mlp_denorm(int64_t rows, int64_t cols, const float* Yn, const float* mu, const float* sd, float* Y,
+                      hipStream_t s);
+hipError_t mlp_mse_grad(int64_t rows, int64_t cols, const float* Yn, const float* T, const float* mu, const float* sd,
+                        float* dY, double* part, int64_t nparts, float* loss, hipStream_t s);
+hipError_t mlp_colsum(int64_t rows, int64_t cols, const float* D, float* out, hipStream_t s);
+hipError_t mlp_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                    int64_t step, hipStream_t s);
+hipError_t mlp_init(int64_t n_in, int64_t w, int64_t n_out, uint64_t seed, float* p, hipStream_t s);
+bool mlp_infer_supported(int64_t n_in, int64_t w, int64_t n_out);
+int64_t mlp_bf16_weights(int64_t n_in);
+int64_t mlp_bf16_biases();
+hipError_t mlp_pack_bf16(int64_t n_in, int64_t n_out, const float* p, short* Wb, float* bias, hipStream_t s);
+hipError_t mlp_infer_bf16(int64_t rows, int64_t n_in, int64_t n_out, const float* X, const float* mu_in,
+                          const float* sd_in, const short* Wb, const float* bias, const float* mu_out,
+                          const float* sd_out, float* Y, hipStream_t s);
 
 // VALU kernel for H^XYZ += sum_I (E^XY F^XZ + E^XZ F^XY) G^YZ (kernels_h.hip).
 // E, F: [I][Pp][Xb]; G: [I][Pp][Pp]; H: [Pp][Pp][Xb]; tiles from h_tiles(Pp, Xb).

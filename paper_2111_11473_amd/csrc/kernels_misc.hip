@@ -191,14 +191,17 @@ __global__ void dot_kernel(int64_t n, const double* __restrict__ x, const double
 }
 
 __global__ void jacobi_kernel(int64_t P, int64_t o, int64_t v, const double* __restrict__ sh,
-                              const double* __restrict__ e, const double* __restrict__ s1,
+                              const double* __restrict__ e, const double* __restrict__ delta,
+                              const double* __restrict__ s1,
                               const double* __restrict__ eps, double* __restrict__ Th, double* __restrict__ t1,
                               double* __restrict__ dT, double* __restrict__ dt1) {
   const int64_t n2 = P * P, n1 = o * v;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n2 + n1; k += (int64_t)gridDim.x * blockDim.x) {
     if (k < n2) {
       const int64_t p = k / P, q = k % P;
-      const double d = -sh[k] / (e[p] + e[q]);
+      const double base = e[p] + e[q];
+      const double den = delta ? fmax(base + delta[p] + delta[q], 0.5 * base) : base;
+      const double d = -sh[k] / den;
       dT[k] = d;
       Th[k] += d;
     } else if (s1) {
@@ -209,6 +212,41 @@ __global__ void jacobi_kernel(int64_t P, int64_t o, int64_t v, const double* __r
     } else {
       dt1[k - n2] = 0.0;
     }
+  }
+}
+
+// Learned-guess features per rank index P (FP32): [T_PP, e_P, T_PP e_P, eps_HOMO, eps_LUMO,
+// mean eps_occ, mean eps_vir, N_P / o, ||T||_F / sqrt(N_P), sum_Q |T_PQ|]; fro2 = ||T||_F^2.
+__global__ void guess_features_kernel(int64_t P, int64_t o, int64_t v, const double* __restrict__ Th,
+                                      const double* __restrict__ e, const double* __restrict__ eps,
+                                      const double* __restrict__ fro2, float* __restrict__ phi) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    double homo = eps[0], lumo = eps[o], so = 0.0, sv = 0.0, rs = 0.0;
+    for (int64_t i = 0; i < o; ++i) { homo = fmax(homo, eps[i]); so += eps[i]; }
+    for (int64_t a = 0; a < v; ++a) { lumo = fmin(lumo, eps[o + a]); sv += eps[o + a]; }
+    for (int64_t q = 0; q < P; ++q) rs += fabs(Th[p * P + q]);
+    const double d = Th[p * P + p];
+    float* f = phi + p * 10;
+    f[0] = (float)d;
+    f[1] = (float)e[p];
+    f[2] = (float)(d * e[p]);
+    f[3] = (float)homo;
+    f[4] = (float)lumo;
+    f[5] = (float)(so / (double)o);
+    f[6] = (float)(sv / (double)v);
+    f[7] = (float)((double)P / (double)o);
+    f[8] = (float)sqrt(fro2[0] / (double)P);
+    f[9] = (float)rs;
+  }
+}
+
+// T_PQ <- (1 + c_P) T_PQ (1 + c_Q), delta_P <- pred[P][1]; c_P = pred[P][0]
+__global__ void guess_apply_kernel(int64_t P, const float* __restrict__ pred, int64_t ld, double* __restrict__ Th,
+                                   double* __restrict__ delta) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P * P; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = k / P, q = k % P;
+    Th[k] *= (1.0 + (double)pred[p * ld]) * (1.0 + (double)pred[q * ld]);
+    if (q == 0 && delta) delta[p] = ld > 1 ? (double)pred[p * ld + 1] : 0.0;
   }
 }
 
@@ -325,9 +363,16 @@ hipError_t k_dot(int64_t n, const double* x, const double* y, double* out, hipSt
 hipError_t k_sum(int64_t n, const double* x, double* out, hipStream_t s) {
   LAUNCH(dot_kernel, dim3(1), dim3(1024), n, x, (const double*)nullptr, out);
 }
-hipError_t k_jacobi(int64_t P, int64_t o, int64_t v, const double* sh, const double* e, const double* s1,
+hipError_t k_jacobi(int64_t P, int64_t o, int64_t v, const double* sh, const double* e, const double* delta, const double* s1,
                     const double* eps, double* Th, double* t1, double* dT, double* dt1, hipStream_t s) {
-  LAUNCH(jacobi_kernel, dim3(nblocks(P * P + o * v)), dim3(TPB), P, o, v, sh, e, s1, eps, Th, t1, dT, dt1);
+  LAUNCH(jacobi_kernel, dim3(nblocks(P * P + o * v)), dim3(TPB), P, o, v, sh, e, delta, s1, eps, Th, t1, dT, dt1);
+}
+hipError_t k_guess_features(int64_t P, int64_t o, int64_t v, const double* Th, const double* e, const double* eps,
+                            const double* fro2, float* phi, hipStream_t s) {
+  LAUNCH(guess_features_kernel, dim3(nblocks(P)), dim3(TPB), P, o, v, Th, e, eps, fro2, phi);
+}
+hipError_t k_guess_apply(int64_t P, const float* pred, int64_t ld, double* Th, double* delta, hipStream_t s) {
+  LAUNCH(guess_apply_kernel, dim3(nblocks(P * P)), dim3(TPB), P, pred, ld, Th, delta);
 }
 hipError_t k_lincomb(int64_t n, int m, const double* coef, const double* const* vecs, double* out, hipStream_t s) {
   if (m > 16) return hipErrorInvalidValue;

@@ -78,6 +78,8 @@ struct thc_ctx {
   double *tmpoP = nullptr, *tmpvP = nullptr, *Fxoo = nullptr, *Fxvv = nullptr, *Tf = nullptr, *fd = nullptr;
   // Alg. 6
   double *C6 = nullptr, *D6 = nullptr, *Ec = nullptr, *Fc = nullptr, *Gc = nullptr, *GYc = nullptr, *Hb = nullptr;
+  double* delta = nullptr;     // Jacobi denominator shift of the learned guess (nP)
+  bool has_shift = false;
   uint32_t* htiles = nullptr;  // H-kernel tile table
   int64_t nhtiles = 0;
   double *R1 = nullptr, *I6 = nullptr;
@@ -295,7 +297,7 @@ int plan_and_alloc(thc_ctx* ctx) {
       {&ctx->xo, (size_t)(o * Q)}, {&ctx->xv, (size_t)(v * Q)}, {&ctx->Go, (size_t)PP}, {&ctx->Gv, (size_t)PP},
       {&ctx->S, (size_t)PP}, {&ctx->z, (size_t)(Q * Q)}, {&ctx->Bq, (size_t)(Q * ov)}, {&ctx->Bkr, (size_t)(ov * P)},
       {&ctx->W, (size_t)PP}, {&ctx->e, (size_t)P},
-      {&ctx->Th, (size_t)PP}, {&ctx->t1, (size_t)ov}, {&ctx->Zs, (size_t)PP},
+      {&ctx->Th, (size_t)PP}, {&ctx->t1, (size_t)ov}, {&ctx->Zs, (size_t)PP}, {&ctx->delta, (size_t)P},
       {&ctx->dvec, (size_t)(std::max<int64_t>(dm, 1) * (PP + ov))}, {&ctx->derr, (size_t)(std::max<int64_t>(dm, 1) * (PP + ov))},
       {&ctx->dT, (size_t)(PP + ov)},
       {&ctx->sig, (size_t)PP}, {&ctx->sig1, (size_t)ov}, {&ctx->sigh, (size_t)PP}, {&ctx->scal, 64},
@@ -697,6 +699,108 @@ int need_built(thc_ctx* ctx) {
 }  // namespace
 
 // =========================================================================================
+namespace {
+// Solves (A + ridge max|diag A| I) x = b for a symmetric positive semi-definite A (overwritten).
+bool spd_solve(int64_t n, std::vector<double>& A, std::vector<double>& b, double ridge) {
+  double dmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) dmax = std::max(dmax, std::fabs(A[(size_t)i * n + i]));
+  if (!(dmax > 0.0)) dmax = 1.0;
+  for (int64_t i = 0; i < n; ++i) A[(size_t)i * n + i] += ridge * dmax;
+  if (host_cholesky(n, A.data()) != 0) return false;
+  for (int64_t i = 0; i < n; ++i) {  // L y = b
+    double acc = b[i];
+    for (int64_t k = 0; k < i; ++k) acc -= A[(size_t)i * n + k] * b[k];
+    b[i] = acc / A[(size_t)i * n + i];
+  }
+  for (int64_t i = n - 1; i >= 0; --i) {  // L^T x = y
+    double acc = b[i];
+    for (int64_t k = i + 1; k < n; ++k) acc -= A[(size_t)k * n + i] * b[k];
+    b[i] = acc / A[(size_t)i * n + i];
+  }
+  return true;
+}
+}  // namespace
+
+struct thc_mlp {
+  int64_t n_in = 0, w = 0, n_out = 0, np = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  float *mu_in = nullptr, *sd_in = nullptr, *mu_out = nullptr, *sd_out = nullptr, *loss = nullptr;
+  double* part = nullptr;
+  int64_t step = 0;
+  // activations for up to `cap` rows
+  int64_t cap = 0;
+  float *xn = nullptr, *z1 = nullptr, *h1 = nullptr, *z2 = nullptr, *h2 = nullptr, *yn = nullptr, *dy = nullptr,
+        *d2 = nullptr, *d1 = nullptr;
+  short* wb = nullptr;
+  float* bb = nullptr;
+  bool packed = false;
+  std::vector<void*> allocs, acts;
+};
+
+namespace {
+constexpr int64_t MLP_PARTS = 1024;
+
+template <class T>
+int mlp_alloc(thc_mlp* ctx, T** p, size_t count, std::vector<void*>& list) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "hipMalloc failed";
+    return THC_ENOMEM;
+  }
+  list.push_back(q);
+  *p = (T*)q;
+  return THC_OK;
+}
+
+int mlp_reserve(thc_mlp* ctx, int64_t rows) {
+  if (rows <= ctx->cap) return THC_OK;
+  for (void* q : ctx->acts) (void)hipFree(q);
+  ctx->acts.clear();
+  const int64_t R = std::max<int64_t>(rows, 1024), w = ctx->w;
+  RCHK(mlp_alloc(ctx, &ctx->xn, (size_t)(R * ctx->n_in), ctx->acts));
+  for (float** a : {&ctx->z1, &ctx->h1, &ctx->z2, &ctx->h2, &ctx->d2, &ctx->d1})
+    RCHK(mlp_alloc(ctx, a, (size_t)(R * w), ctx->acts));
+  RCHK(mlp_alloc(ctx, &ctx->yn, (size_t)(R * ctx->n_out), ctx->acts));
+  RCHK(mlp_alloc(ctx, &ctx->dy, (size_t)(R * ctx->n_out), ctx->acts));
+  ctx->cap = R;
+  return THC_OK;
+}
+
+// forward in FP32: xn, z1, h1, z2, h2, yn (normalized outputs)
+int mlp_fwd(thc_mlp* ctx, const float* X, int64_t R) {
+  const int64_t ni = ctx->n_in, w = ctx->w, no = ctx->n_out;
+  const float *W1 = ctx->p, *b1 = W1 + ni * w, *W2 = b1 + w, *b2 = W2 + w * w, *W3 = b2 + w, *b3 = W3 + w * no;
+  hipStream_t s = ctx->stream;
+  HIPCHK(mlp_normalize(R, ni, X, ctx->mu_in, ctx->sd_in, ctx->xn, s));
+  HIPCHK(mlp_sgemm(false, false, 1, R, w, ni, ctx->xn, ni, W1, w, ctx->h1, w, b1, ctx->z1, w, s));
+  HIPCHK(mlp_sgemm(false, false, 1, R, w, w, ctx->h1, w, W2, w, ctx->h2, w, b2, ctx->z2, w, s));
+  HIPCHK(mlp_sgemm(false, false, 2, R, no, w, ctx->h2, w, W3, no, ctx->yn, no, b3, nullptr, 0, s));
+  return THC_OK;
+}
+
+// loss and gradient (into ctx->g) of the mean squared error on normalized targets
+int mlp_bwd(thc_mlp* ctx, const float* X, const float* T, int64_t R) {
+  const int64_t ni = ctx->n_in, w = ctx->w, no = ctx->n_out;
+  const float *W2 = ctx->p + ni * w + w, *W3 = W2 + w * w + w;
+  float *gW1 = ctx->g, *gb1 = gW1 + ni * w, *gW2 = gb1 + w, *gb2 = gW2 + w * w, *gW3 = gb2 + w, *gb3 = gW3 + w * no;
+  hipStream_t s = ctx->stream;
+  RCHK(mlp_fwd(ctx, X, R));
+  HIPCHK(mlp_mse_grad(R, no, ctx->yn, T, ctx->mu_out, ctx->sd_out, ctx->dy, ctx->part, MLP_PARTS, ctx->loss, s));
+  HIPCHK(mlp_sgemm(true, false, 0, w, no, R, ctx->h2, w, ctx->dy, no, gW3, no, nullptr, nullptr, 0, s));
+  HIPCHK(mlp_colsum(R, no, ctx->dy, gb3, s));
+  HIPCHK(mlp_sgemm(false, true, 3, R, w, no, ctx->dy, no, W3, no, ctx->d2, w, nullptr, ctx->z2, w, s));
+  HIPCHK(mlp_sgemm(true, false, 0, w, w, R, ctx->h1, w, ctx->d2, w, gW2, w, nullptr, nullptr, 0, s));
+  HIPCHK(mlp_colsum(R, w, ctx->d2, gb2, s));
+  HIPCHK(mlp_sgemm(false, true, 3, R, w, w, ctx->d2, w, W2, w, ctx->d1, w, nullptr, ctx->z1, w, s));
+  HIPCHK(mlp_sgemm(true, false, 0, ni, w, R, ctx->xn, ni, ctx->d1, w, gW1, w, nullptr, nullptr, 0, s));
+  HIPCHK(mlp_colsum(R, w, ctx->d1, gb1, s));
+  return THC_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
@@ -952,7 +1056,8 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
     // Jacobi step in the working basis; (dT, dt1) is the DIIS error vector
     double* dTp = ctx->dT;
     double* dt1p = ctx->dT + PP;
-    MISC(k_jacobi(P, ctx->o, ctx->v, ctx->sigh, ctx->e, singles ? ctx->sig1 : nullptr, ctx->eps, ctx->Th, ctx->t1,
+    MISC(k_jacobi(P, ctx->o, ctx->v, ctx->sigh, ctx->e, ctx->has_shift ? ctx->delta : nullptr,
+                  singles ? ctx->sig1 : nullptr, ctx->eps, ctx->Th, ctx->t1,
                   dTp, dt1p, s));
     if (dm > 0) {
       const int slot = ctx->diis_head;
@@ -1078,6 +1183,261 @@ int thc_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double al
   Gemm g = batched(mk(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc, alpha, beta), batch, sA, sB, sC);
   if (gemm_f64(g, (hipStream_t)stream) != hipSuccess) return THC_EDEVICE;
   return THC_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Learned starting guess (not part of the paper): features, application, Jacobi shift, state in
+// the working basis and least-squares training targets.
+
+int thc_guess_features(thc_ctx* ctx, float* phi) {
+  if (!ctx || !phi) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  MISC(k_dot(ctx->P * ctx->P, ctx->Th, ctx->Th, ctx->scal + 40, ctx->stream));
+  MISC(k_guess_features(ctx->P, ctx->o, ctx->v, ctx->Th, ctx->e, ctx->eps, ctx->scal + 40, phi, ctx->stream));
+  return THC_OK;
+}
+
+int thc_guess_apply(thc_ctx* ctx, const float* pred, int64_t ld) {
+  if (!ctx || !pred || ld < 1) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  MISC(k_guess_apply(ctx->P, pred, ld, ctx->Th, ctx->delta, ctx->stream));
+  ctx->has_shift = ld > 1;
+  RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
+  ctx->diis_n = 0;
+  ctx->diis_head = 0;
+  return THC_OK;
+}
+
+int thc_set_shift(thc_ctx* ctx, const double* delta) {
+  if (!ctx) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  if (delta) HIPCHK(hipMemcpyAsync(ctx->delta, delta, ctx->P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->has_shift = delta != nullptr;
+  ctx->diis_n = 0;
+  ctx->diis_head = 0;
+  return THC_OK;
+}
+
+int thc_working(thc_ctx* ctx, double* Th, double* sigma_hat) {
+  if (!ctx) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  const int64_t PP = ctx->P * ctx->P;
+  if (Th) HIPCHK(hipMemcpyAsync(Th, ctx->Th, PP * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  if (sigma_hat) {
+    RCHK(residual_impl(ctx, ctx->Zs, ctx->opt.singles ? ctx->t1 : nullptr, THC_TERM_ALL));
+    RCHK(project_basis(ctx));
+    HIPCHK(hipMemcpyAsync(sigma_hat, ctx->sigh, PP * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return THC_OK;
+}
+
+
+int thc_guess_targets(thc_ctx* ctx, const double* Th0, const double* Tstar, const double* sig0, double* c,
+                      double* delta) {
+  if (!ctx || !Th0 || !Tstar || !sig0 || !c || !delta) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  const int64_t P = ctx->P, PP = P * P;
+  std::vector<double> T0(PP), Ts(PP), S0(PP), e(P);
+  HIPCHK(hipMemcpyAsync(T0.data(), Th0, PP * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(Ts.data(), Tstar, PP * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(S0.data(), sig0, PP * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(e.data(), ctx->e, P * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  // c: Gauss-Newton on s = 1 + c for min || diag(s) T0 diag(s) - T* ||_F, r symmetric:
+  //   (J^T r)_k = 2 sum_q r_kq s_q T0_kq,  (J^T J)_kl = 2 d_kl sum_q s_q^2 T0_kq^2 + 2 s_k s_l T0_kl^2
+  std::vector<double> sv(P, 1.0), A(PP), b(P);
+  for (int it = 0; it < 12; ++it) {
+    for (int64_t k = 0; k < P; ++k) {
+      double g = 0.0, dsum = 0.0;
+      for (int64_t q = 0; q < P; ++q) {
+        const double t0 = T0[(size_t)k * P + q];
+        const double r = sv[k] * sv[q] * t0 - Ts[(size_t)k * P + q];
+        g += r * sv[q] * t0;
+        dsum += sv[q] * sv[q] * t0 * t0;
+        A[(size_t)k * P + q] = 2.0 * sv[k] * sv[q] * t0 * t0;
+      }
+      A[(size_t)k * P + k] += 2.0 * dsum;
+      b[k] = -2.0 * g;
+    }
+    if (!spd_solve(P, A, b, 1e-12)) {
+      ctx->err = "scaling target: normal matrix not positive definite";
+      return THC_ESINGULAR;
+    }
+    double step = 0.0;
+    for (int64_t k = 0; k < P; ++k) {
+      sv[k] += b[k];
+      step = std::max(step, std::fabs(b[k]));
+    }
+    if (step < 1e-12) break;
+  }
+  std::vector<double> ch(P), dh(P);
+  for (int64_t k = 0; k < P; ++k) ch[k] = sv[k] - 1.0;
+  // delta: normal equations of min sum_PQ (r_PQ - (delta_P + delta_Q) dT_PQ)^2,
+  //   r = -sigma0 - (e_P + e_Q) dT:  (diag(rowsum dT^2) + dT o dT) delta = rowsum(r o dT)
+  for (int64_t p = 0; p < P; ++p) {
+    double rs = 0.0, rhs = 0.0;
+    for (int64_t q = 0; q < P; ++q) {
+      const double dT = Ts[(size_t)p * P + q] - T0[(size_t)p * P + q];
+      const double r = -S0[(size_t)p * P + q] - (e[p] + e[q]) * dT;
+      A[(size_t)p * P + q] = dT * dT;
+      rs += dT * dT;
+      rhs += r * dT;
+    }
+    A[(size_t)p * P + p] += rs;
+    dh[p] = rhs;
+  }
+  if (!spd_solve(P, A, dh, 1e-10)) {
+    ctx->err = "shift target: normal matrix not positive definite";
+    return THC_ESINGULAR;
+  }
+  HIPCHK(hipMemcpyAsync(c, ch.data(), P * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(delta, dh.data(), P * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return THC_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// The learned-guess network.
+
+
+int thc_mlp_create(int64_t n_in, int64_t width, int64_t n_out, uint64_t seed, void* stream, thc_mlp** out) {
+  if (!out || n_in < 1 || width < 1 || n_out < 1 || n_in > 4096 || width > 4096 || n_out > 4096) return THC_EINVAL;
+  *out = nullptr;
+  thc_mlp* ctx = new (std::nothrow) thc_mlp();
+  if (!ctx) return THC_ENOMEM;
+  ctx->n_in = n_in;
+  ctx->w = width;
+  ctx->n_out = n_out;
+  ctx->np = n_in * width + width + width * width + width + width * n_out + n_out;
+  ctx->stream = (hipStream_t)stream;
+  int rc = THC_OK;
+  for (float** a : {&ctx->p, &ctx->g, &ctx->m, &ctx->v})
+    if (rc == THC_OK) rc = mlp_alloc(ctx, a, (size_t)ctx->np, ctx->allocs);
+  for (float** a : {&ctx->mu_in, &ctx->sd_in})
+    if (rc == THC_OK) rc = mlp_alloc(ctx, a, (size_t)n_in, ctx->allocs);
+  for (float** a : {&ctx->mu_out, &ctx->sd_out})
+    if (rc == THC_OK) rc = mlp_alloc(ctx, a, (size_t)n_out, ctx->allocs);
+  if (rc == THC_OK) rc = mlp_alloc(ctx, &ctx->loss, 1, ctx->allocs);
+  if (rc == THC_OK) rc = mlp_alloc(ctx, &ctx->part, (size_t)MLP_PARTS, ctx->allocs);
+  if (rc == THC_OK && mlp_infer_supported(n_in, width, n_out)) {
+    rc = mlp_alloc(ctx, &ctx->wb, (size_t)mlp_bf16_weights(n_in), ctx->allocs);
+    if (rc == THC_OK) rc = mlp_alloc(ctx, &ctx->bb, (size_t)mlp_bf16_biases(), ctx->allocs);
+  }
+  if (rc == THC_OK) {
+    std::vector<float> zeros((size_t)std::max(n_in, n_out), 0.0f), ones((size_t)std::max(n_in, n_out), 1.0f);
+    if (mlp_init(n_in, width, n_out, seed, ctx->p, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->m, 0, ctx->np * sizeof(float), ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->v, 0, ctx->np * sizeof(float), ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(ctx->mu_in, zeros.data(), n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(ctx->sd_in, ones.data(), n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(ctx->mu_out, zeros.data(), n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(ctx->sd_out, ones.data(), n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      rc = THC_EDEVICE;
+  }
+  if (rc != THC_OK) {
+    for (void* q : ctx->allocs) (void)hipFree(q);
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return THC_OK;
+}
+
+int thc_mlp_set_norm(thc_mlp* ctx, const float* mu_in, const float* sd_in, const float* mu_out, const float* sd_out) {
+  if (!ctx || !mu_in || !sd_in || !mu_out || !sd_out) return THC_EINVAL;
+  for (int64_t k = 0; k < ctx->n_in; ++k)
+    if (!(sd_in[k] > 0.0f)) { ctx->err = "input scales must be positive"; return THC_EINVAL; }
+  for (int64_t k = 0; k < ctx->n_out; ++k)
+    if (!(sd_out[k] > 0.0f)) { ctx->err = "output scales must be positive"; return THC_EINVAL; }
+  HIPCHK(hipMemcpyAsync(ctx->mu_in, mu_in, ctx->n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->sd_in, sd_in, ctx->n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->mu_out, mu_out, ctx->n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->sd_out, sd_out, ctx->n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return THC_OK;
+}
+
+int thc_mlp_num_params(const thc_mlp* ctx, int64_t* n) {
+  if (!ctx || !n) return THC_EINVAL;
+  *n = ctx->np;
+  return THC_OK;
+}
+
+int thc_mlp_get_params(thc_mlp* ctx, float* p) {
+  if (!ctx || !p) return THC_EINVAL;
+  HIPCHK(hipMemcpyAsync(p, ctx->p, ctx->np * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream));
+  return THC_OK;
+}
+
+int thc_mlp_set_params(thc_mlp* ctx, const float* p) {
+  if (!ctx || !p) return THC_EINVAL;
+  HIPCHK(hipMemcpyAsync(ctx->p, p, ctx->np * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->m, 0, ctx->np * sizeof(float), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->v, 0, ctx->np * sizeof(float), ctx->stream));
+  ctx->step = 0;
+  ctx->packed = false;
+  return THC_OK;
+}
+
+int thc_mlp_forward(thc_mlp* ctx, const float* X, int64_t rows, float* Y) {
+  if (!ctx || !X || !Y || rows < 0) return THC_EINVAL;
+  if (rows == 0) return THC_OK;
+  RCHK(mlp_reserve(ctx, rows));
+  RCHK(mlp_fwd(ctx, X, rows));
+  HIPCHK(mlp_denorm(rows, ctx->n_out, ctx->yn, ctx->mu_out, ctx->sd_out, Y, ctx->stream));
+  return THC_OK;
+}
+
+int thc_mlp_loss_grad(thc_mlp* ctx, const float* X, const float* T, int64_t rows, float* loss, float* grad) {
+  if (!ctx || !X || !T || rows < 1) return THC_EINVAL;
+  RCHK(mlp_reserve(ctx, rows));
+  RCHK(mlp_bwd(ctx, X, T, rows));
+  if (grad) HIPCHK(hipMemcpyAsync(grad, ctx->g, ctx->np * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream));
+  if (loss) {
+    HIPCHK(hipMemcpyAsync(loss, ctx->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  return THC_OK;
+}
+
+int thc_mlp_train_step(thc_mlp* ctx, const float* X, const float* T, int64_t rows, float lr, float* loss) {
+  if (!ctx || !X || !T || rows < 1 || !(lr > 0.0f)) return THC_EINVAL;
+  RCHK(mlp_reserve(ctx, rows));
+  RCHK(mlp_bwd(ctx, X, T, rows));
+  ctx->step += 1;
+  HIPCHK(mlp_adam(ctx->np, ctx->p, ctx->g, ctx->m, ctx->v, lr, 0.9f, 0.999f, 1e-8f, ctx->step, ctx->stream));
+  ctx->packed = false;
+  if (loss) {
+    HIPCHK(hipMemcpyAsync(loss, ctx->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  return THC_OK;
+}
+
+int thc_mlp_infer(thc_mlp* ctx, const float* X, int64_t rows, float* Y) {
+  if (!ctx || !X || !Y || rows < 0) return THC_EINVAL;
+  if (!ctx->wb) {
+    ctx->err = "BF16 inference needs width 256, n_in <= 16 and n_out <= 16";
+    return THC_EINVAL;
+  }
+  if (!ctx->packed) {
+    HIPCHK(mlp_pack_bf16(ctx->n_in, ctx->n_out, ctx->p, ctx->wb, ctx->bb, ctx->stream));
+    ctx->packed = true;
+  }
+  HIPCHK(mlp_infer_bf16(rows, ctx->n_in, ctx->n_out, X, ctx->mu_in, ctx->sd_in, ctx->wb, ctx->bb, ctx->mu_out,
+                        ctx->sd_out, Y, ctx->stream));
+  return THC_OK;
+}
+
+const char* thc_mlp_last_error(const thc_mlp* ctx) { return ctx ? ctx->err.c_str() : "null network"; }
+
+void thc_mlp_destroy(thc_mlp* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (void* q : ctx->acts) (void)hipFree(q);
+  for (void* q : ctx->allocs) (void)hipFree(q);
+  delete ctx;
 }
 
 const char* thc_last_error(const thc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }

@@ -29,7 +29,12 @@ TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TER
 SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_history",
            "thc_energy",
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_profile", "thc_profile_get", "thc_dgemm",
-           "thc_last_error", "thc_destroy"]
+           "thc_last_error", "thc_destroy",
+           "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
+           "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
+           "thc_mlp_forward", "thc_mlp_loss_grad", "thc_mlp_train_step", "thc_mlp_infer", "thc_mlp_last_error",
+           "thc_mlp_destroy"]
+GUESS_FEATURES = 10
 
 
 class Options(C.Structure):
@@ -74,8 +79,27 @@ def load(path: str = LIB_PATH):
     lib.thc_last_error.restype = C.c_char_p
     lib.thc_destroy.argtypes = [VP]
     lib.thc_destroy.restype = None
+    lib.thc_guess_features.argtypes = [VP, P]
+    lib.thc_guess_apply.argtypes = [VP, P, I64]
+    lib.thc_set_shift.argtypes = [VP, P]
+    lib.thc_working.argtypes = [VP, P, P]
+    lib.thc_guess_targets.argtypes = [VP, P, P, P, P, P]
+    FP = C.POINTER(C.c_float)
+    lib.thc_mlp_create.argtypes = [I64, I64, I64, C.c_uint64, VP, C.POINTER(VP)]
+    lib.thc_mlp_set_norm.argtypes = [VP, FP, FP, FP, FP]
+    lib.thc_mlp_num_params.argtypes = [VP, C.POINTER(I64)]
+    lib.thc_mlp_get_params.argtypes = [VP, P]
+    lib.thc_mlp_set_params.argtypes = [VP, P]
+    lib.thc_mlp_forward.argtypes = [VP, P, I64, P]
+    lib.thc_mlp_loss_grad.argtypes = [VP, P, P, I64, FP, P]
+    lib.thc_mlp_train_step.argtypes = [VP, P, P, I64, C.c_float, FP]
+    lib.thc_mlp_infer.argtypes = [VP, P, I64, P]
+    lib.thc_mlp_last_error.argtypes = [VP]
+    lib.thc_mlp_last_error.restype = C.c_char_p
+    lib.thc_mlp_destroy.argtypes = [VP]
+    lib.thc_mlp_destroy.restype = None
     for name in SYMBOLS:
-        if name not in ("thc_last_error", "thc_destroy"):
+        if name not in ("thc_last_error", "thc_destroy", "thc_mlp_last_error", "thc_mlp_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -86,6 +110,18 @@ def _ptr(t, n=None, name="tensor"):
         return None
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
         raise TypeError(f"{name} must be a float64 tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _fptr(t, n=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 tensor on the GPU")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if n is not None and t.numel() != n:
@@ -213,6 +249,37 @@ class THC:
         self._check(self.lib.thc_memory_bytes(self.ctx, C.byref(b)), "thc_memory_bytes")
         return b.value
 
+    # -- learned guess ------------------------------------------------------------------
+    def guess_features(self):
+        """phi (nP x 10, float32) of the current state (after build_factors: the MP2 guess)."""
+        phi = torch.empty((self.nP, GUESS_FEATURES), dtype=torch.float32, device="cuda")
+        self._check(self.lib.thc_guess_features(self.ctx, _fptr(phi)), "thc_guess_features")
+        return phi
+
+    def guess_apply(self, pred):
+        """pred (nP x k, float32): column 0 scales the state, column 1 (if any) shifts the denominators."""
+        if pred.dim() != 2 or pred.shape[0] != self.nP:
+            raise ValueError("pred must be nP x k")
+        self._check(self.lib.thc_guess_apply(self.ctx, _fptr(pred, name="pred"), pred.shape[1]), "thc_guess_apply")
+
+    def set_shift(self, delta=None):
+        self._check(self.lib.thc_set_shift(self.ctx, _ptr(delta, self.nP, "delta")), "thc_set_shift")
+
+    def working(self, residual=False):
+        """(T^, sigma^ or None) of the current state in the working basis."""
+        Th = torch.empty((self.nP, self.nP), dtype=torch.float64, device="cuda")
+        sh = torch.empty_like(Th) if residual else None
+        self._check(self.lib.thc_working(self.ctx, _ptr(Th), _ptr(sh)), "thc_working")
+        return Th, sh
+
+    def guess_targets(self, Th0, Tstar, sig0):
+        c = torch.empty(self.nP, dtype=torch.float64, device="cuda")
+        d = torch.empty_like(c)
+        n2 = self.nP * self.nP
+        self._check(self.lib.thc_guess_targets(self.ctx, _ptr(Th0, n2, "Th0"), _ptr(Tstar, n2, "Tstar"),
+                                               _ptr(sig0, n2, "sig0"), _ptr(c), _ptr(d)), "thc_guess_targets")
+        return c, d
+
     # -- profiling ----------------------------------------------------------------------
     def profile(self, enable=True):
         self._check(self.lib.thc_profile(self.ctx, int(enable)), "thc_profile")
@@ -222,3 +289,80 @@ class THC:
         n = C.c_int64(0)
         self._check(self.lib.thc_profile_get(self.ctx, name.encode(), C.byref(ms), C.byref(n)), "thc_profile_get")
         return ms.value, n.value
+
+
+class MLP:
+    """The learned-guess network (n_in -> width -> width -> n_out, SiLU) on the current GPU."""
+
+    def __init__(self, n_in=GUESS_FEATURES, width=256, n_out=2, seed=1):
+        self.lib = load()
+        self.n_in, self.width, self.n_out = n_in, width, n_out
+        h = C.c_void_p()
+        rc = self.lib.thc_mlp_create(n_in, width, n_out, C.c_uint64(seed), _stream(), C.byref(h))
+        if rc != 0:
+            raise ThcError(rc, "thc_mlp_create failed")
+        self.net = h
+        n = C.c_int64(0)
+        self._check(self.lib.thc_mlp_num_params(self.net, C.byref(n)), "thc_mlp_num_params")
+        self.n_params = n.value
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.thc_mlp_last_error(self.net)
+            raise ThcError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "net", None):
+            self.lib.thc_mlp_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_norm(self, mu_in, sd_in, mu_out, sd_out):
+        arr = lambda a, n: (C.c_float * n)(*[float(x) for x in a])
+        self._check(self.lib.thc_mlp_set_norm(self.net, arr(mu_in, self.n_in), arr(sd_in, self.n_in),
+                                              arr(mu_out, self.n_out), arr(sd_out, self.n_out)), "thc_mlp_set_norm")
+
+    def get_params(self):
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self._check(self.lib.thc_mlp_get_params(self.net, _fptr(p)), "thc_mlp_get_params")
+        return p
+
+    def set_params(self, p):
+        self._check(self.lib.thc_mlp_set_params(self.net, _fptr(p, self.n_params, "params")), "thc_mlp_set_params")
+
+    def _rows(self, X):
+        if X.dim() != 2 or X.shape[1] != self.n_in:
+            raise ValueError("X must be rows x n_in")
+        return X.shape[0]
+
+    def forward(self, X):
+        r = self._rows(X)
+        Y = torch.empty((r, self.n_out), dtype=torch.float32, device="cuda")
+        self._check(self.lib.thc_mlp_forward(self.net, _fptr(X, name="X"), r, _fptr(Y)), "thc_mlp_forward")
+        return Y
+
+    def infer(self, X):
+        r = self._rows(X)
+        Y = torch.empty((r, self.n_out), dtype=torch.float32, device="cuda")
+        self._check(self.lib.thc_mlp_infer(self.net, _fptr(X, name="X"), r, _fptr(Y)), "thc_mlp_infer")
+        return Y
+
+    def loss_grad(self, X, T):
+        r = self._rows(X)
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = C.c_float(0.0)
+        self._check(self.lib.thc_mlp_loss_grad(self.net, _fptr(X, name="X"), _fptr(T, r * self.n_out, "T"), r,
+                                               C.byref(loss), _fptr(g)), "thc_mlp_loss_grad")
+        return loss.value, g
+
+    def train_step(self, X, T, lr):
+        r = self._rows(X)
+        loss = C.c_float(0.0)
+        self._check(self.lib.thc_mlp_train_step(self.net, _fptr(X, name="X"), _fptr(T, r * self.n_out, "T"), r,
+                                                C.c_float(lr), C.byref(loss)), "thc_mlp_train_step")
+        return loss.value
