@@ -183,6 +183,11 @@ typedef struct thc_mlp thc_mlp;
 int thc_mlp_create(int64_t n_in, int64_t width, int64_t n_out, uint64_t seed, void* stream, thc_mlp** out);
 /* Host arrays: mu_in, sd_in [n_in]; mu_out, sd_out [n_out]; scales must be positive. */
 int thc_mlp_set_norm(thc_mlp* net, const float* mu_in, const float* sd_in, const float* mu_out, const float* sd_out);
+/* Standardization fitted to training data X[rows][n_in], T[rows][n_out] (device): per-column
+ * mean and standard deviation; a column with no spread gets sd = 1. */
+int thc_mlp_fit_norm(thc_mlp* net, const float* X, const float* T, int64_t rows);
+/* The standardization in use, copied to host arrays [n_in], [n_in], [n_out], [n_out]. */
+int thc_mlp_get_norm(thc_mlp* net, float* mu_in, float* sd_in, float* mu_out, float* sd_out);
 int thc_mlp_num_params(const thc_mlp* net, int64_t* n);
 int thc_mlp_get_params(thc_mlp* net, float* p);       /* p[n] device */
 int thc_mlp_set_params(thc_mlp* net, const float* p); /* p[n] device; resets the Adam moments */

@@ -27,9 +27,9 @@ def _hipcc() -> str:
 
 def _flags(src: str) -> list[str]:
     f = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-    if src.endswith(".hip"):
-        # packed FP32 instructions are disabled for every device compilation
-        f += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    # every source is compiled for gfx950 only (the .cpp files hold host code and no kernels);
+    # packed FP32 instructions are disabled for every device compilation
+    f += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     return f
 
 

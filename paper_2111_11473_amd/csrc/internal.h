@@ -88,6 +88,7 @@ hipError_t mlp_denorm(int64_t rows, int64_t cols, const float* Yn, const float* 
 hipError_t mlp_mse_grad(int64_t rows, int64_t cols, const float* Yn, const float* T, const float* mu, const float* sd,
                         float* dY, double* part, int64_t nparts, float* loss, hipStream_t s);
 hipError_t mlp_colsum(int64_t rows, int64_t cols, const float* D, float* out, hipStream_t s);
+hipError_t mlp_colstats(int64_t rows, int64_t cols, const float* D, float* mu, float* sd, hipStream_t s);
 hipError_t mlp_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                     int64_t step, hipStream_t s);
 hipError_t mlp_init(int64_t n_in, int64_t w, int64_t n_out, uint64_t seed, float* p, hipStream_t s);
@@ -100,9 +101,14 @@ hipError_t mlp_infer_bf16(int64_t rows, int64_t n_in, int64_t n_out, const float
                           const float* sd_out, float* Y, hipStream_t s);
 
 // VALU kernel for H^XYZ += sum_I (E^XY F^XZ + E^XZ F^XY) G^YZ (kernels_h.hip).
-// E, F: [I][Pp][Xb]; G: [I][Pp][Pp]; H: [Pp][Pp][Xb]; tiles from h_tiles(Pp, Xb).
-hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t nI, const double* E, const double* F, const double* G,
-                        double* H, const uint32_t* tiles, int64_t ntiles, hipStream_t s);
-std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb);
+// E, F: [I][Pp/2][ldx][2]; G: [I][Pp][ldg]; H: [Pp][Pp][Xb]; tiles from h_tiles(Pp, Xb, slots).
+// Padding of the operand rows: E, F rows of Xb + H_PAD_X (pair layout), G rows of Pp + H_PAD_G.
+// Measured on MI355X at Pp = Xb = 1024: unpadded rows run fastest (padding lowered the L2 hit rate).
+constexpr int64_t H_PAD_X = 0, H_PAD_G = 0;
+hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const double* E, const double* F,
+                        const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
+                        hipStream_t s);
+std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots);
+int64_t h_slots_per_xcd();
 
 }  // namespace thc

@@ -22,9 +22,11 @@
 // factor that is uniform across the lanes, G, is held 16 values to a VGPR pair (lane l holds
 // value l % 16) and broadcast into the FMA by the DPP row_newbcast source modifier, so the
 // inner loop has no scalar loads.
-// Tile order comes from a host-built table: runs of 64 tiles sharing an X tile, 4 Y blocks and
-// 8 Z blocks go to one XCD (workgroup b runs on XCD b % 8), so the workgroups resident on an XCD
-// share their operand rows through its L2.
+// Tile order comes from a host-built table: runs of `slots` tiles (the workgroups resident on one
+// XCD) that share an X tile, 4 Y blocks and 8 Z blocks are placed at workgroup ids b with
+// b % 8 = that XCD, so tiles sharing operand rows run on one XCD at about the same time and share
+// them through its L2.  One workgroup per tile measured faster than a persistent grid walking the
+// table (co-started tiles request the same lines at once).
 // Layouts (ranks zero-padded to Pp, a multiple of 64; X restricted to a block of Xb ranks, a
 // multiple of 64): E, F: [I][Pp/2][Xb][2] (E_I^XY at [I][Y/2][X][Y%2]); G: [I][Pp][Pp];
 // H: [Pp][Pp][Xb] (H^XYZ at [Y][Z][X]).
@@ -78,11 +80,12 @@ __device__ inline void bload_lds(__amdgpu_buffer_rsrc_t r, double* lds, unsigned
 }
 
 // Waits until at most n of this wave's vector-memory operations are outstanding (n is
-// wave-uniform), then joins the workgroup barrier.  Written as one block so that neither the
-// wait nor the barrier picks up the compiler's conservative vmcnt(0).
+// wave-uniform) and its LDS operations are complete, then joins the workgroup barrier.  Written
+// as one block so that neither the wait nor the barrier picks up the compiler's conservative
+// vmcnt(0).
 template <int N>
 __device__ inline void wait_bar() {
-  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 // Wait for stage I + 1 with `later` further stages (0 <= later < 3) of Q or Q + 1 copies each
 // (extra: this wave also copies a G chunk) still allowed in flight, then the barrier.
@@ -131,20 +134,22 @@ __device__ inline void h_row(double (&acc)[WZ], double (&accm)[WZ], double ey, d
 static_assert(WZ == 4 && WY == 8, "h_row covers four Z; a patch is eight rows");
 
 template <int NWZ, int NS>
-__global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int Xb, int64_t nI,
+__global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int Xb, int ldx, int ldg, int64_t nI,
                                                                    const double* __restrict__ E,
                                                                    const double* __restrict__ F,
                                                                    const double* __restrict__ G,
                                                                    double* __restrict__ H,
-                                                                   const uint32_t* __restrict__ tiles) {
+                                                                   const uint32_t* __restrict__ tiles,
+                                                                   int64_t ntiles) {
   using C = Geo<NWZ, NS>;
-  const uint32_t tile = tiles[blockIdx.x];
-  if (tile & EMPTY) return;  // whole workgroup, before any barrier
+  __shared__ double lds[NS * C::STAGE];
+  for (int64_t tix = blockIdx.x; tix < ntiles; tix += gridDim.x) {
+  const uint32_t tile = tiles[tix];
+  if (tile & EMPTY) continue;  // uniform over the workgroup
   const int Yb = tile & 511, Zb = (tile >> 9) & 511, zs = (tile >> 18) & 3, xt = (tile >> 20) & 1023;
   const bool mirror = Yb != Zb;
   const int y0 = Yb * BY, z0 = Zb * BY + zs * C::BZ, X0 = xt * LANES;
 
-  __shared__ double lds[NS * C::STAGE];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ly0 = (w % (BY / WY)) * WY, lz0 = (w / (BY / WY)) * WZ;
@@ -191,12 +196,12 @@ __global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int
   const unsigned voff_r = (unsigned)lane * 16u;
   const bool g_yz = w < C::CH_G, g_zy = !g_yz && w < 2 * C::CH_G && mirror;
   const int gs = g_yz ? w : w - C::CH_G;
-  const unsigned voff_g = g_yz ? ((unsigned)(lane / (C::BZ / 2)) * (unsigned)Pp + 2u * (lane % (C::BZ / 2))) * 8u
-                               : ((unsigned)(lane / (BY / 2)) * (unsigned)Pp + 2u * (lane % (BY / 2))) * 8u;
-  const unsigned so_g = g_yz ? ((unsigned)(y0 + gs * (128 / C::BZ)) * (unsigned)Pp + (unsigned)z0) * 8u
-                             : ((unsigned)(z0 + gs * (128 / BY)) * (unsigned)Pp + (unsigned)y0) * 8u;
+  const unsigned voff_g = g_yz ? ((unsigned)(lane / (C::BZ / 2)) * (unsigned)ldg + 2u * (lane % (C::BZ / 2))) * 8u
+                               : ((unsigned)(lane / (BY / 2)) * (unsigned)ldg + 2u * (lane % (BY / 2))) * 8u;
+  const unsigned so_g = g_yz ? ((unsigned)(y0 + gs * (128 / C::BZ)) * (unsigned)ldg + (unsigned)z0) * 8u
+                             : ((unsigned)(z0 + gs * (128 / BY)) * (unsigned)ldg + (unsigned)y0) * 8u;
   const bool extra = g_yz || g_zy;  // this wave copies QROWS + extra chunks per stage
-  const int64_t PX = (int64_t)Pp * Xb, PP = (int64_t)Pp * Pp;
+  const int64_t PX = (int64_t)Pp * ldx, PP = (int64_t)Pp * ldg;  // per-I strides of E, F and of G
   auto stage_in = [&](int64_t I, int buf) {
     const __amdgpu_buffer_rsrc_t re = rsrc(E + I * PX, PX * 8);
     const __amdgpu_buffer_rsrc_t rf = rsrc(F + I * PX, PX * 8);
@@ -211,7 +216,7 @@ __global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int
                        : c0 < fy_end ? y0 / 2 + c - ey_end
                        : c0 < ez_end ? z0 / 2 + c - fy_end
                                      : z0 / 2 + c - ez_end;
-      bload_lds(isF ? rf : re, sb + c * 128, voff_r, ((unsigned)pair * (unsigned)Xb + (unsigned)X0) * 16u);
+      bload_lds(isF ? rf : re, sb + c * 128, voff_r, ((unsigned)pair * (unsigned)ldx + (unsigned)X0) * 16u);
     }
     if (extra) bload_lds(rsrc(G + I * PP, PP * 8), sb + (C::CH_ROWS + w) * 128, voff_g, so_g);
   };
@@ -282,10 +287,11 @@ __global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int
         for (int k = 0; k < WZ; ++k) bstore(accm[j][k], rm, lo, (unsigned)(k * Pp + j) * xrow);
     }
   }
+  }  // tile loop: the last wait_pipe above left every wave past its final LDS read
 }
 
 template <int NWZ>
-std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb) {
+std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb, int64_t slots) {
   constexpr int NZS = BY / (WZ * NWZ);
   const int64_t nB = Pp / BY, nX = Xb / LANES;
   std::vector<uint32_t> lin;
@@ -295,23 +301,25 @@ std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb) {
         for (int64_t yb = gy * 4; yb < std::min(nB, gy * 4 + 4); ++yb)
           for (int64_t zb = std::max(yb, gz * 8); zb < std::min(nB, gz * 8 + 8); ++zb)
             for (int64_t s = 0; s < NZS; ++s) lin.push_back((uint32_t)(yb | (zb << 9) | (s << 18) | (xt << 20)));
-  const int64_t runs = ((int64_t)lin.size() + 63) / 64;
-  std::vector<uint32_t> out((size_t)(((runs + 7) / 8) * 512), EMPTY);
+  const int64_t runs = ((int64_t)lin.size() + slots - 1) / slots;
+  std::vector<uint32_t> out((size_t)(((runs + 7) / 8) * 8 * slots), EMPTY);
   for (size_t e = 0; e < lin.size(); ++e) {
-    const int64_t c = (int64_t)e / 64, k = (int64_t)e % 64;
-    out[(size_t)((c / 8) * 512 + k * 8 + c % 8)] = lin[e];
+    const int64_t c = (int64_t)e / slots, k = (int64_t)e % slots;
+    out[(size_t)((c / 8) * 8 * slots + k * 8 + c % 8)] = lin[e];
   }
   return out;
 }
 
 template <int NWZ, int NS>
-hipError_t launch(int64_t Pp, int64_t Xb, int64_t nI, const double* E, const double* F, const double* G, double* H,
-                  const uint32_t* tiles, int64_t ntiles, hipStream_t s) {
+hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const double* E, const double* F,
+                  const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots, bool persistent,
+                  hipStream_t s) {
   if (Pp % 64 != 0 || Pp > 8192 || Xb % LANES != 0 || Xb > Pp || Xb <= 0 || ntiles <= 0 || ntiles > 2147483647LL ||
-      nI < 0)
+      nI < 0 || slots < 1 || ntiles % (8 * slots) != 0 || ldx < Xb || ldx > 2 * Pp || ldg < Pp || ldg > 2 * Pp)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL((h_kernel<NWZ, NS>), dim3((unsigned)ntiles), dim3(Geo<NWZ, NS>::NTHREADS), 0, s, (int)Pp,
-                     (int)Xb, nI, E, F, G, H, tiles);
+  const int64_t grid = persistent ? std::min<int64_t>(ntiles, 8 * slots) : ntiles;
+  hipLaunchKernelGGL((h_kernel<NWZ, NS>), dim3((unsigned)grid), dim3(Geo<NWZ, NS>::NTHREADS), 0, s, (int)Pp, (int)Xb,
+                     (int)ldx, (int)ldg, nI, E, F, G, H, tiles, ntiles);
   return hipGetLastError();
 }
 
@@ -319,14 +327,28 @@ constexpr int H_NWZ = 2, H_NS = 3;  // 4 waves, 26 KB stages, three stages (two 
 
 }  // namespace
 
-// Tile table: every (X tile, Y block Yb, Z block Zb >= Yb, Z slice) once, grouped into runs of
-// 64 tiles that share an X tile, 4 Y blocks and 8 Z blocks; run c is placed at workgroups
-// b = 512 (c / 8) + 8 k + (c % 8), k = 0..63, so that it runs on one XCD; unused slots are EMPTY.
-std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb) { return tiles_for<H_NWZ>(Pp, Xb); }
+// Resident workgroups per XCD (8 XCDs; workgroup b runs on XCD b % 8): CUs per XCD times the
+// workgroups of this kernel that fit on one CU.
+int64_t h_slots_per_xcd() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, h_kernel<H_NWZ, H_NS>, Geo<H_NWZ, H_NS>::NTHREADS, 0) !=
+          hipSuccess)
+    return 0;
+  return std::max<int64_t>(1, (int64_t)(cus / 8) * std::max(per_cu, 1));
+}
 
-hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t nI, const double* E, const double* F, const double* G,
-                        double* H, const uint32_t* tiles, int64_t ntiles, hipStream_t s) {
-  return launch<H_NWZ, H_NS>(Pp, Xb, nI, E, F, G, H, tiles, ntiles, s);
+// Tile table: every (X tile, Y block Yb, Z block Zb >= Yb, Z slice) once, in runs of `slots`
+// tiles that share an X tile, 4 Y blocks and 8 Z blocks.  The kernel runs 8 slots workgroups,
+// each walking the table with stride 8 slots; run c sits at b = 8 slots (c / 8) + 8 k + (c % 8),
+// k < slots, so the tiles of one run are processed at the same time on one XCD and share their
+// operand rows through its L2.  Unused entries are EMPTY.
+std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots) { return tiles_for<H_NWZ>(Pp, Xb, slots); }
+
+hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const double* E, const double* F,
+                        const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
+                        hipStream_t s) {
+  return launch<H_NWZ, H_NS>(Pp, Xb, ldx, ldg, nI, E, F, G, H, tiles, ntiles, slots, false, s);
 }
 
 }  // namespace thc

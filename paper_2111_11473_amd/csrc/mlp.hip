@@ -161,6 +161,37 @@ __global__ void colsum_kernel(int64_t rows, int64_t cols, const float* __restric
   if (threadIdx.x == 0) out[n] = red[0];
 }
 
+// Per column of D[rows][cols]: mean and standard deviation (FP64 sums); a column whose spread is
+// below 1e-6 of its scale gets sd = 1, so constant inputs standardize to zero.
+__global__ void colstats_kernel(int64_t rows, int64_t cols, const float* __restrict__ D, float* __restrict__ mu,
+                                float* __restrict__ sd) {
+  __shared__ double r1[TPB], r2[TPB];
+  const int64_t n = blockIdx.x;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+    const double x = D[r * cols + n];
+    s1 += x;
+    s2 += x * x;
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      r1[threadIdx.x] += r1[threadIdx.x + h];
+      r2[threadIdx.x] += r2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m = r1[0] / (double)rows;
+    const double var = fmax(r2[0] / (double)rows - m * m, 0.0);
+    const double d = sqrt(var);
+    mu[n] = (float)m;
+    sd[n] = (float)(d > 1e-6 * fmax(1.0, fabs(m)) ? d : 1.0);
+  }
+}
+
 __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                             float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -368,6 +399,12 @@ hipError_t mlp_mse_grad(int64_t rows, int64_t cols, const float* Yn, const float
 hipError_t mlp_colsum(int64_t rows, int64_t cols, const float* D, float* out, hipStream_t s) {
   if (cols <= 0) return hipSuccess;
   hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cols), dim3(TPB), 0, s, rows, cols, D, out);
+  return hipGetLastError();
+}
+
+hipError_t mlp_colstats(int64_t rows, int64_t cols, const float* D, float* mu, float* sd, hipStream_t s) {
+  if (cols <= 0 || rows <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(colstats_kernel, dim3((unsigned)cols), dim3(TPB), 0, s, rows, cols, D, mu, sd);
   return hipGetLastError();
 }
 

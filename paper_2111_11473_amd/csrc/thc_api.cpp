@@ -81,7 +81,8 @@ struct thc_ctx {
   double* delta = nullptr;     // Jacobi denominator shift of the learned guess (nP)
   bool has_shift = false;
   uint32_t* htiles = nullptr;  // H-kernel tile table
-  int64_t nhtiles = 0;
+  int64_t nhtiles = 0, hslots = 0;
+  int64_t ldx = 0, ldg = 0;    // padded row lengths of the H-kernel operands (E, F, C6, D6 and G)
   double *R1 = nullptr, *I6 = nullptr;
   // Alg. 7
   double *U7 = nullptr, *S7 = nullptr, *R7 = nullptr, *Rx = nullptr, *Sx = nullptr, *Cx = nullptr, *Dx = nullptr;
@@ -93,6 +94,7 @@ struct thc_ctx {
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
+  const char* section = nullptr;  // residual section, for per-section GEMM records ("gemm@<section>")
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
 };
@@ -148,7 +150,12 @@ struct Scope {
 
 int gemm(thc_ctx* ctx, const Gemm& g) {
   Scope sc(ctx, "gemm");
-  HIPCHK(gemm_f64(g, ctx->stream));
+  if (ctx->prof && ctx->section) {
+    Scope sc2(ctx, ctx->section);
+    HIPCHK(gemm_f64(g, ctx->stream));
+  } else {
+    HIPCHK(gemm_f64(g, ctx->stream));
+  }
   return THC_OK;
 }
 
@@ -281,8 +288,11 @@ int plan_and_alloc(thc_ctx* ctx) {
   }
   if (Xb % 64 != 0 || Xb > Pp) { ctx->err = "x_block must be a multiple of 64 and <= padded rank"; return THC_EINVAL; }
   ctx->Xb = Xb;
+  ctx->ldx = Xb + H_PAD_X;
+  ctx->ldg = Pp + H_PAD_G;
+  const int64_t ldx = ctx->ldx, ldg = ctx->ldg;
   int64_t Ic = op.i_chunk;
-  if (Ic <= 0) Ic = std::max<int64_t>(1, (int64_t)(8.0e9 / (8.0 * (2.0 * Xb * Pp + (double)Pp * Pp))));
+  if (Ic <= 0) Ic = std::max<int64_t>(1, (int64_t)(8.0e9 / (8.0 * (2.0 * (Xb + H_PAD_X) * Pp + (double)Pp * (Pp + H_PAD_G)))));
   ctx->Ic = std::min(Ic, Q);
   int64_t Xc = op.x_chunk;
   if (Xc <= 0) Xc = std::max<int64_t>(1, (int64_t)(2.0e9 / (8.0 * (double)Q * Q)));
@@ -319,8 +329,8 @@ int plan_and_alloc(thc_ctx* ctx) {
       {&ctx->tmpvP, (size_t)(v * P)}, {&ctx->Fxoo, (size_t)(o * o)}, {&ctx->Fxvv, (size_t)(v * v)},
       {&ctx->Tf, (size_t)P}, {&ctx->fd, (size_t)P},
       // Alg. 6
-      {&ctx->C6, (size_t)(o * Xb * Pp)}, {&ctx->D6, (size_t)(v * Xb * Pp)}, {&ctx->Ec, (size_t)(ctx->Ic * Xb * Pp)},
-      {&ctx->Fc, (size_t)(ctx->Ic * Xb * Pp)}, {&ctx->Gc, (size_t)(ctx->Ic * Pp * Pp)}, {&ctx->GYc, (size_t)(ctx->Ic * o * P)},
+      {&ctx->C6, (size_t)(o * ldx * Pp)}, {&ctx->D6, (size_t)(v * ldx * Pp)}, {&ctx->Ec, (size_t)(ctx->Ic * ldx * Pp)},
+      {&ctx->Fc, (size_t)(ctx->Ic * ldx * Pp)}, {&ctx->Gc, (size_t)(ctx->Ic * Pp * ldg)}, {&ctx->GYc, (size_t)(ctx->Ic * o * P)},
       {&ctx->Hb, (size_t)(Xb * Pp * Pp)}, {&ctx->R1, (size_t)(Xb * Pp * o)}, {&ctx->I6, (size_t)(Xb * ov)},
       // Alg. 7
       {&ctx->U7, (size_t)(P * o * P)}, {&ctx->S7, (size_t)(P * ov)}, {&ctx->R7, (size_t)(P * ov)},
@@ -330,14 +340,16 @@ int plan_and_alloc(thc_ctx* ctx) {
   };
   for (auto& a : list) RCHK(alloc(ctx, a.p, a.n));
   // zero-padded operands of the H-kernel: padding must stay zero
-  RCHK(zero(ctx, ctx->C6, o * Xb * Pp));
-  RCHK(zero(ctx, ctx->D6, v * Xb * Pp));
-  RCHK(zero(ctx, ctx->Gc, ctx->Ic * Pp * Pp));
+  RCHK(zero(ctx, ctx->C6, o * ldx * Pp));
+  RCHK(zero(ctx, ctx->D6, v * ldx * Pp));
+  RCHK(zero(ctx, ctx->Gc, ctx->Ic * Pp * ldg));
   RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
-  RCHK(zero(ctx, ctx->Ec, ctx->Ic * Xb * Pp));
-  RCHK(zero(ctx, ctx->Fc, ctx->Ic * Xb * Pp));
+  RCHK(zero(ctx, ctx->Ec, ctx->Ic * ldx * Pp));
+  RCHK(zero(ctx, ctx->Fc, ctx->Ic * ldx * Pp));
   {
-    const std::vector<uint32_t> tiles = h_tiles(Pp, Xb);
+    ctx->hslots = h_slots_per_xcd();
+    if (ctx->hslots < 1) { ctx->err = "cannot query the device for the H-kernel launch"; return THC_EDEVICE; }
+    const std::vector<uint32_t> tiles = h_tiles(Pp, Xb, ctx->hslots);
     double* tb = nullptr;
     RCHK(alloc(ctx, &tb, (tiles.size() + 1) / 2));
     ctx->htiles = reinterpret_cast<uint32_t*>(tb);
@@ -382,6 +394,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   RCHK(zero(ctx, ctx->trK, nL));
 
   // ---------------- fused pass over blocks of Cholesky vectors (Alg. 1, 2, 3, 8) -------------
+  ctx->section = "gemm@fused";
   for (int64_t A0 = 0; A0 < nL; A0 += ctx->nb) {
     const int64_t nb = std::min(ctx->nb, nL - A0);
     const double* Loo = ctx->Loo + A0 * o * o;
@@ -477,6 +490,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   MISC(k_sum(nL, ctx->trK, ctx->scal + 3, s));
 
   // ---------------- Fock matrix, T1-transformed (Eq. 24-27) -----------------------------------
+  ctx->section = "gemm@fock";
   double* Foo = ctx->Fh;
   double* Fov = ctx->Fh + o * o;
   double* Fvo = ctx->Fh + o * o + ov;
@@ -510,6 +524,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   }
 
   // ---------------- assembly of the symmetric terms (Alg. 2, 3, 9) ----------------------------
+  ctx->section = "gemm@assembly";
   RCHK(gemm(ctx, mk(P, P, P, ctx->S, P, false, T, P, false, ctx->ST, P)));
   if (mask & THC_TERM_EQ28) MISC(k_batch_sum(ctx->KS, PP, ctx->sig28, 1.0, ctx->sig, s));
   if (mask & THC_TERM_EQ29) {
@@ -542,31 +557,34 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   }
 
   // ---------------- Alg. 6: quartic T2^2 ladder + exchange (Eq. 32 + 33) ----------------------
+  ctx->section = "gemm@alg6";
   if (mask & THC_TERM_EQ32) {
-    const int64_t Xb = ctx->Xb;
+    const int64_t Xb = ctx->Xb, ldx = ctx->ldx;
     for (int64_t X0 = 0; X0 < P; X0 += Xb) {
       const int64_t xb = std::min(Xb, P - X0);
       // C6[i][Y][x] = sum_W T[W][Y] y_i^W Gv[X][W];  D6[a][Y][x] = sum_W T[W][Y] y_a^W Go[X][W]
       // stored [Y/2][x][Y%2] (X fastest, row pairs interleaved: the H-kernel's operand layout)
       {
-        Gemm g = batched(mk(P, xb, P, T, P, true, ctx->Gv + X0 * P, P, true, ctx->C6, Xb), o, 0, 0, Xb * Pp);
+        Gemm g = batched(mk(P, xb, P, T, P, true, ctx->Gv + X0 * P, P, true, ctx->C6, ldx), o, 0, 0, ldx * Pp);
         g.kscaleA = Yo; g.ksA = 1; g.sksA = P; g.pair_rows = true;
         RCHK(gemm(ctx, g));
-        Gemm h = batched(mk(P, xb, P, T, P, true, ctx->Go + X0 * P, P, true, ctx->D6, Xb), v, 0, 0, Xb * Pp);
+        Gemm h = batched(mk(P, xb, P, T, P, true, ctx->Go + X0 * P, P, true, ctx->D6, ldx), v, 0, 0, ldx * Pp);
         h.kscaleA = Yv; h.ksA = 1; h.sksA = P; h.pair_rows = true;
         RCHK(gemm(ctx, h));
       }
       for (int64_t I0 = 0; I0 < Q; I0 += ctx->Ic) {
         const int64_t ic = std::min(ctx->Ic, Q - I0);
         // E_I = sum_i x_i^I C6[i];  F_I = sum_a x_a^I D6[a]  (elementwise in the [Y/2][x][2] layout)
-        RCHK(gemm(ctx, mk(ic, Xb * Pp, o, xo + I0, Q, true, ctx->C6, Xb * Pp, false, ctx->Ec, Xb * Pp)));
-        RCHK(gemm(ctx, mk(ic, Xb * Pp, v, xv + I0, Q, true, ctx->D6, Xb * Pp, false, ctx->Fc, Xb * Pp)));
+        RCHK(gemm(ctx, mk(ic, ldx * Pp, o, xo + I0, Q, true, ctx->C6, ldx * Pp, false, ctx->Ec, ldx * Pp)));
+        RCHK(gemm(ctx, mk(ic, ldx * Pp, v, xv + I0, Q, true, ctx->D6, ldx * Pp, false, ctx->Fc, ldx * Pp)));
         // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6)
         RCHK(gemm(ctx, mk(ic * o, P, v, ctx->Bq + I0 * ov, v, false, Yv, P, false, ctx->GYc, P)));
-        RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, Pp), ic, 0, o * P, Pp * Pp)));
+        RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, ctx->ldg), ic, 0, o * P,
+                               Pp * ctx->ldg)));
         {
           Scope sc(ctx, "h_kernel");
-          HIPCHK(h_accumulate(Pp, Xb, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles, ctx->nhtiles, s));
+          HIPCHK(h_accumulate(Pp, Xb, ctx->ldx, ctx->ldg, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles,
+                              ctx->nhtiles, ctx->hslots, s));
         }
       }
       // I^X_ia = sum_YZ y_i^Z y_a^Y H^XYZ ; sigma^XW += sum_ia y_i^W y_a^W I^X_ia  (Alg. 6)
@@ -579,6 +597,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   }
 
   // ---------------- Alg. 7: T2^2 rings (Eq. 35-37) ------------------------------------------
+  ctx->section = "gemm@alg7";
   if (mask & THC_TERM_EQ35) {
     // S^X_ia = - sum_YZ y_i^Y y_a^Z Gv[X][Y] Go[X][Z] T[Y][Z]  (Alg. 7)
     {
@@ -626,6 +645,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   }
 
   // ---------------- singles residual (Alg. 8, Alg. 10) ---------------------------------------
+  ctx->section = "gemm@singles";
   if (sres && (mask & THC_TERM_EQ38)) {
     // s38 was accumulated with undressed Lvv/Loo; the dressing adds -xi_oo^T t1 + t1 xi_vv^T
     MISC(k_axpby(ov, 1.0, ctx->s38, 1.0, ctx->sig1, s));
@@ -651,6 +671,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       RCHK(gemm(ctx, g));
     }
   }
+  ctx->section = nullptr;
   return THC_OK;
 }
 
@@ -1354,6 +1375,24 @@ int thc_mlp_set_norm(thc_mlp* ctx, const float* mu_in, const float* sd_in, const
   HIPCHK(hipMemcpyAsync(ctx->sd_in, sd_in, ctx->n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->mu_out, mu_out, ctx->n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->sd_out, sd_out, ctx->n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return THC_OK;
+}
+
+int thc_mlp_fit_norm(thc_mlp* ctx, const float* X, const float* T, int64_t rows) {
+  if (!ctx || !X || !T || rows < 1) return THC_EINVAL;
+  HIPCHK(mlp_colstats(rows, ctx->n_in, X, ctx->mu_in, ctx->sd_in, ctx->stream));
+  HIPCHK(mlp_colstats(rows, ctx->n_out, T, ctx->mu_out, ctx->sd_out, ctx->stream));
+  ctx->packed = false;
+  return THC_OK;
+}
+
+int thc_mlp_get_norm(thc_mlp* ctx, float* mu_in, float* sd_in, float* mu_out, float* sd_out) {
+  if (!ctx || !mu_in || !sd_in || !mu_out || !sd_out) return THC_EINVAL;
+  HIPCHK(hipMemcpyAsync(mu_in, ctx->mu_in, ctx->n_in * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(sd_in, ctx->sd_in, ctx->n_in * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(mu_out, ctx->mu_out, ctx->n_out * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(sd_out, ctx->sd_out, ctx->n_out * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return THC_OK;
 }

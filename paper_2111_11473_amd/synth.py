@@ -81,6 +81,7 @@ class Config:
     decay: float = 30.0
     seed: int = 1000
     gamma: float | None = None  # None: the lambda_max rule above
+    coupling: float = 0.2       # the rule's fraction of the smallest pair gap
 
     @property
     def n(self) -> int:
@@ -153,7 +154,7 @@ def make_system(cfg: Config) -> dict:
     if cfg.gamma is None:
         dmin = 2.0 * (eps[o] - eps[o - 1])
         lam = _lambda_max_ov(L[:, :o, o:])
-        gamma = float(np.sqrt(0.2 * dmin / lam))
+        gamma = float(np.sqrt(cfg.coupling * dmin / lam))
     else:
         gamma = float(cfg.gamma)
     L *= gamma

@@ -31,7 +31,7 @@ SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_term
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_profile", "thc_profile_get", "thc_dgemm",
            "thc_last_error", "thc_destroy",
            "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
-           "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
+           "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
            "thc_mlp_forward", "thc_mlp_loss_grad", "thc_mlp_train_step", "thc_mlp_infer", "thc_mlp_last_error",
            "thc_mlp_destroy"]
 GUESS_FEATURES = 10
@@ -87,6 +87,8 @@ def load(path: str = LIB_PATH):
     FP = C.POINTER(C.c_float)
     lib.thc_mlp_create.argtypes = [I64, I64, I64, C.c_uint64, VP, C.POINTER(VP)]
     lib.thc_mlp_set_norm.argtypes = [VP, FP, FP, FP, FP]
+    lib.thc_mlp_fit_norm.argtypes = [VP, P, P, I64]
+    lib.thc_mlp_get_norm.argtypes = [VP, FP, FP, FP, FP]
     lib.thc_mlp_num_params.argtypes = [VP, C.POINTER(I64)]
     lib.thc_mlp_get_params.argtypes = [VP, P]
     lib.thc_mlp_set_params.argtypes = [VP, P]
@@ -326,6 +328,16 @@ class MLP:
         arr = lambda a, n: (C.c_float * n)(*[float(x) for x in a])
         self._check(self.lib.thc_mlp_set_norm(self.net, arr(mu_in, self.n_in), arr(sd_in, self.n_in),
                                               arr(mu_out, self.n_out), arr(sd_out, self.n_out)), "thc_mlp_set_norm")
+
+    def fit_norm(self, X, T):
+        r = self._rows(X)
+        self._check(self.lib.thc_mlp_fit_norm(self.net, _fptr(X, name="X"), _fptr(T, r * self.n_out, "T"), r),
+                    "thc_mlp_fit_norm")
+
+    def get_norm(self):
+        bufs = [(C.c_float * n)() for n in (self.n_in, self.n_in, self.n_out, self.n_out)]
+        self._check(self.lib.thc_mlp_get_norm(self.net, *bufs), "thc_mlp_get_norm")
+        return tuple(list(b) for b in bufs)
 
     def get_params(self):
         p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")

@@ -1,0 +1,38 @@
+"""End-to-end learned guess on small systems of the learned set (o in [6, 9]): training rows from
+converged solves, training on the GPU, BF16 inference, and held-out solves from the predicted
+start.  The converged energy must not depend on the start, the fallback must keep every solve
+converged, and the iteration counts of both starts are reported."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ready():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_11473_amd import thc
+    thc.load()
+    return True
+
+
+def test_learned_guess_end_to_end(ready):
+    from paper_2111_11473_amd import learned
+    say = lambda *a: print("[gpu-learned]", *a, flush=True)
+    X, T, info = learned.generate(range(12), 6, 9, log=say)
+    assert X.shape[1] == 10 and T.shape[1] == 2 and X.shape[0] == sum(r["nP"] for r in info)
+    assert np.isfinite(X).all() and np.isfinite(T).all()
+    net, first, losses = learned.train(X, T, epochs=30, batch=1024, log=say)
+    assert losses[-1] < 0.8 * first
+    plain, learn = [], []
+    for s in range(200, 204):
+        r = learned.solve_pair(net, learned.system_config(s, 6, 9))
+        say(s, r["plain_iterations"], r["learned_iterations"], r["fallback"], r["energy_difference"])
+        assert r["plain_converged"] and r["learned_converged"]
+        assert r["energy_difference"] < 1e-8
+        plain.append(r["plain_iterations"])
+        learn.append(r["learned_iterations"])
+    say("mean iterations plain", np.mean(plain), "learned", np.mean(learn))
+    assert np.mean(learn) <= np.mean(plain) + 1.0
