@@ -62,7 +62,9 @@ typedef struct thc_options {
   int64_t i_chunk;          /* ERI grid points per H-kernel pass; 0 = automatic */
   int64_t x_block;          /* amplitude ranks per H block (multiple of 64); 0 = automatic */
   int64_t x_chunk;          /* amplitude ranks per Alg. 7 exchange chunk (two-GEMM form); 0 = automatic */
-  int32_t precision;        /* 0 = FP64 throughout (the only value accepted) */
+  int32_t precision;        /* 0 = FP64 throughout; 1 = mixed: FP32-MFMA contractions and FP32 H-kernel
+                               operands with FP64 accumulation, FP64 energy, denominators, fit and DIIS,
+                               and thc_iterate finishing with FP64 residuals */
   int32_t flags;            /* THC_FLAG_* bits; 0 = defaults */
 } thc_options;
 
@@ -117,6 +119,9 @@ int thc_history(const thc_ctx* ctx, int max, double* energy, double* rnorm, doub
 /* Correlation energy of the current state (host scalar), the usual CCSD expression
  * sum (t_ij^ab + t_i^a t_j^b)(2(ia|jb) - (ib|ja)) with Cholesky integrals. */
 int thc_energy(thc_ctx* ctx, double* e_corr);
+/* Per iteration of the last thc_iterate call: 1 where the residual was evaluated in mixed
+ * precision, 0 where in FP64.  mixed[max] host; *count receives the number of iterations. */
+int thc_history_precision(const thc_ctx* ctx, int max, int* mixed, int* count);
 
 /* Current state in the raw basis: Z [nP][nP], t1 [o][v] (device; either may be NULL). */
 int thc_get_state(thc_ctx* ctx, double* Z, double* t1);

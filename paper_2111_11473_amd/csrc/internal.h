@@ -28,6 +28,9 @@ struct Gemm {
   int64_t batch = 1;
   int ksplit = 1; int64_t sSplit = 0;
   bool pair_rows = false;  // C element (m, n) at C[((m / 2) ldc + n) 2 + m % 2]: rows interleaved in pairs
+  bool f32 = false;        // FP32 MFMA (operands rounded to FP32, FP32 accumulation)
+  bool keep64 = false;     // stays FP64 in the mixed-precision path
+  float* Cf = nullptr;     // FP32 output instead of C (requires f32 and beta = 0)
 };
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
@@ -108,6 +111,10 @@ constexpr int64_t H_PAD_X = 0, H_PAD_G = 0;
 hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const double* E, const double* F,
                         const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
                         hipStream_t s);
+// The same with E, F stored in FP32 (mixed-precision path); arithmetic and H stay FP64.
+hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const float* E, const float* F,
+                          const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
+                          hipStream_t s);
 std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots);
 int64_t h_slots_per_xcd();
 

@@ -43,29 +43,42 @@ constexpr int WY = 8, WZ = 4;              // per-wave patch
 constexpr int RSRC_W3 = 0x00020000;        // raw 32-bit buffer access
 constexpr uint32_t EMPTY = 0x80000000u;
 
-template <int NWZ, int NS>
+// TE: storage type of E and F (double, or float in the mixed-precision path); G and H are FP64.
+template <int NWZ, int NS, typename TE>
 struct Geo {
   static constexpr int NW = (BY / WY) * NWZ;        // waves per workgroup
   static constexpr int NTHREADS = NW * LANES;
   static constexpr int BZ = WZ * NWZ;               // Z slice per workgroup
   static constexpr int NZS = BY / BZ;               // Z slices per block
-  // stage layout in doubles: row pairs of 64 X (128 doubles = 1 KB each), then the G blocks
-  static constexpr int EY = 0, FY = (BY / 2) * 128, EZ = BY * 128, FZ = EZ + (BZ / 2) * 128;
-  static constexpr int GOFF = FZ + (BZ / 2) * 128;  // G^YZ [BY][BZ]
-  static constexpr int GMOFF = GOFF + BY * BZ;      // G^ZY [BZ][BY]
-  static constexpr int STAGE = GMOFF + BZ * BY;
-  static constexpr int CH_ROWS = BY + BZ;           // 1 KB DMA chunks of row pairs
-  static constexpr int CH_G = BY * BZ / 128;        // 1 KB chunks per G block
-  static constexpr int QROWS = CH_ROWS / NW;        // row-pair chunks issued by every wave
-  static_assert((BY / 2) % NW == 0 && (BZ / 2) % NW == 0, "each row region splits evenly over the waves");
-  static_assert(2 * CH_G <= NW && (BY * BZ) % 128 == 0, "one round of G chunks");
-  static_assert(NS >= 2 && NS * STAGE * 8 <= 160 * 1024, "stages must fit in LDS");
+  // stage layout (bytes): row pairs of 64 X (128 values each) -- E^Y, F^Y (BY/2 pairs each),
+  // E^Z, F^Z (BZ/2 pairs each) -- then the FP64 G blocks G^YZ [BY][BZ] and G^ZY [BZ][BY]
+  static constexpr int ESZ = (int)sizeof(TE);
+  static constexpr int PAIR_B = 128 * ESZ;
+  static constexpr int NPAIRS = BY + BZ;
+  static constexpr int EY = 0, FY = BY / 2, EZ = BY, FZ = BY + BZ / 2;  // in pairs
+  static constexpr int G_B = NPAIRS * PAIR_B;
+  static constexpr int GM_B = G_B + BY * BZ * 8;
+  static constexpr int STAGE_B = GM_B + BZ * BY * 8;
+  static constexpr int PPC = 1024 / PAIR_B;         // row pairs per 1 KB DMA chunk
+  static constexpr int CH_ROWS = NPAIRS / PPC;      // row chunks per stage
+  static constexpr int CH_G = BY * BZ * 8 / 1024;   // 1 KB chunks per G block
+  static constexpr int QROWS = CH_ROWS / NW;        // row chunks issued by every wave
+  static_assert(CH_ROWS % NW == 0 && (BY / 2) % PPC == 0 && (BZ / 2) % PPC == 0, "row chunks split evenly");
+  static_assert(2 * CH_G <= NW && (BY * BZ * 8) % 1024 == 0, "one round of G chunks");
+  static_assert(NS >= 2 && NS * STAGE_B <= 160 * 1024, "stages must fit in LDS");
 };
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
-__device__ inline __amdgpu_buffer_rsrc_t rsrc(const double* base, int64_t nbytes) {
+__device__ inline d2 pair_at(const char* p) { return *(const d2*)p; }
+__device__ inline d2 pair_at_f(const char* p) {
+  const f2 v = *(const f2*)p;
+  return d2{(double)v.x, (double)v.y};
+}
+
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* base, int64_t nbytes) {
   return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(uint32_t)nbytes, RSRC_W3);
 }
 __device__ inline double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
@@ -75,7 +88,7 @@ __device__ inline void bstore(double x, __amdgpu_buffer_rsrc_t r, unsigned voff,
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
 }
 // 16 bytes per lane from a buffer straight into LDS at lds + 16 * lane (no VGPR destination)
-__device__ inline void bload_lds(__amdgpu_buffer_rsrc_t r, double* lds, unsigned voff, unsigned soff) {
+__device__ inline void bload_lds(__amdgpu_buffer_rsrc_t r, void* lds, unsigned voff, unsigned soff) {
   __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, soff, 0, 0);
 }
 
@@ -133,19 +146,17 @@ __device__ inline void h_row(double (&acc)[WZ], double (&accm)[WZ], double ey, d
 }
 static_assert(WZ == 4 && WY == 8, "h_row covers four Z; a patch is eight rows");
 
-template <int NWZ, int NS>
-__global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int Xb, int ldx, int ldg, int64_t nI,
-                                                                   const double* __restrict__ E,
-                                                                   const double* __restrict__ F,
-                                                                   const double* __restrict__ G,
-                                                                   double* __restrict__ H,
-                                                                   const uint32_t* __restrict__ tiles,
-                                                                   int64_t ntiles) {
-  using C = Geo<NWZ, NS>;
-  __shared__ double lds[NS * C::STAGE];
-  for (int64_t tix = blockIdx.x; tix < ntiles; tix += gridDim.x) {
-  const uint32_t tile = tiles[tix];
-  if (tile & EMPTY) continue;  // uniform over the workgroup
+template <int NWZ, int NS, typename TE>
+__global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp, int Xb, int ldx, int ldg, int64_t nI,
+                                                                       const TE* __restrict__ E,
+                                                                       const TE* __restrict__ F,
+                                                                       const double* __restrict__ G,
+                                                                       double* __restrict__ H,
+                                                                       const uint32_t* __restrict__ tiles) {
+  using C = Geo<NWZ, NS, TE>;
+  __shared__ __attribute__((aligned(16))) char lds[NS * C::STAGE_B];
+  const uint32_t tile = tiles[blockIdx.x];
+  if (tile & EMPTY) return;  // whole workgroup, before any barrier
   const int Yb = tile & 511, Zb = (tile >> 9) & 511, zs = (tile >> 18) & 3, xt = (tile >> 20) & 1023;
   const bool mirror = Yb != Zb;
   const int y0 = Yb * BY, z0 = Zb * BY + zs * C::BZ, X0 = xt * LANES;
@@ -161,7 +172,7 @@ __global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int
   if (!mirror)
     for (int i = threadIdx.x; i < C::BZ * BY; i += C::NTHREADS)
 #pragma unroll
-      for (int b = 0; b < NS; ++b) lds[b * C::STAGE + C::GMOFF + i] = 0.0;
+      for (int b = 0; b < NS; ++b) ((double*)(lds + b * C::STAGE_B + C::GM_B))[i] = 0.0;
 
   // accumulators: acc[j][k] = H[y0+ly0+j][z0+lz0+k][X0+lane], accm[j][k] = H[z0+lz0+k][y0+ly0+j][X0+lane]
   double acc[WY][WZ], accm[WY][WZ];
@@ -189,11 +200,14 @@ __global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int
     }
   }
 
-  // DMA plan of one stage: chunk c (1 KB) lands at stage + 128 c; wave w issues chunks w + NW q.
-  // Row-pair chunks come first (E^Y pairs, F^Y pairs, E^Z pairs, F^Z pairs; the region of each
-  // round q is fixed at compile time), then one round of G chunks, c = CH_ROWS + w: G^YZ
-  // (CH_G chunks of 128 / BZ rows of BZ) and, off the diagonal, G^ZY (CH_G chunks of 8 rows of 16).
-  const unsigned voff_r = (unsigned)lane * 16u;
+  // DMA plan of one stage: chunk c (1 KB) lands at stage + 1 KB c; wave w issues chunks w + NW q.
+  // Row chunks first: chunk c holds PPC consecutive stage pairs starting at c PPC (E^Y, F^Y, E^Z,
+  // F^Z in that order; lanes 64/PPC apart take consecutive pairs), then one round of FP64 G chunks,
+  // c = CH_ROWS + w: G^YZ (CH_G chunks of 128 / BZ rows of BZ) and, off the diagonal, G^ZY (CH_G
+  // chunks of 8 rows of 16).
+  constexpr int LPP = 64 / C::PPC;                                    // lanes per row pair
+  const unsigned pstride = (unsigned)ldx * 2u * C::ESZ;               // bytes between row pairs
+  const unsigned voff_r = (unsigned)(lane / LPP) * pstride + (unsigned)(lane % LPP) * 16u;
   const bool g_yz = w < C::CH_G, g_zy = !g_yz && w < 2 * C::CH_G && mirror;
   const int gs = g_yz ? w : w - C::CH_G;
   const unsigned voff_g = g_yz ? ((unsigned)(lane / (C::BZ / 2)) * (unsigned)ldg + 2u * (lane % (C::BZ / 2))) * 8u
@@ -203,28 +217,25 @@ __global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int
   const bool extra = g_yz || g_zy;  // this wave copies QROWS + extra chunks per stage
   const int64_t PX = (int64_t)Pp * ldx, PP = (int64_t)Pp * ldg;  // per-I strides of E, F and of G
   auto stage_in = [&](int64_t I, int buf) {
-    const __amdgpu_buffer_rsrc_t re = rsrc(E + I * PX, PX * 8);
-    const __amdgpu_buffer_rsrc_t rf = rsrc(F + I * PX, PX * 8);
-    double* sb = lds + buf * C::STAGE;
+    const __amdgpu_buffer_rsrc_t re = rsrc(E + I * PX, PX * C::ESZ);
+    const __amdgpu_buffer_rsrc_t rf = rsrc(F + I * PX, PX * C::ESZ);
+    char* sb = lds + buf * C::STAGE_B;
 #pragma unroll
     for (int q = 0; q < C::QROWS; ++q) {
-      constexpr int ey_end = BY / 2, fy_end = BY, ez_end = BY + C::BZ / 2;
-      const int c0 = C::NW * q;  // first chunk of round q: fixes its region
-      const int c = w + c0;
-      const bool isF = (c0 >= ey_end && c0 < fy_end) || c0 >= ez_end;
-      const int pair = c0 < ey_end ? y0 / 2 + c
-                       : c0 < fy_end ? y0 / 2 + c - ey_end
-                       : c0 < ez_end ? z0 / 2 + c - fy_end
-                                     : z0 / 2 + c - ez_end;
-      bload_lds(isF ? rf : re, sb + c * 128, voff_r, ((unsigned)pair * (unsigned)ldx + (unsigned)X0) * 16u);
+      const int c = w + C::NW * q;
+      const int sp = c * C::PPC;  // first stage pair of the chunk (all its pairs share a region)
+      const bool isF = (sp >= C::FY && sp < C::EZ) || sp >= C::FZ;
+      const int pair = sp < C::FY ? y0 / 2 + sp : sp < C::EZ ? y0 / 2 + sp - C::FY
+                                                : sp < C::FZ ? z0 / 2 + sp - C::EZ : z0 / 2 + sp - C::FZ;
+      bload_lds(isF ? rf : re, sb + c * 1024, voff_r, (unsigned)pair * pstride + (unsigned)X0 * 2u * C::ESZ);
     }
-    if (extra) bload_lds(rsrc(G + I * PP, PP * 8), sb + (C::CH_ROWS + w) * 128, voff_g, so_g);
+    if (extra) bload_lds(rsrc(G + I * PP, PP * 8), sb + C::G_B + w * 1024, voff_g, so_g);
   };
 
   // broadcast-register sources: lane l holds G^YZ[ly0 + 4 r + m / 4][lz0 + m % 4], m = l % 16
   const int m = lane & 15;
-  const int goff0 = C::GOFF + (ly0 + (m >> 2)) * C::BZ + lz0 + (m & 3);
-  const int gmoff0 = C::GMOFF + (lz0 + (m & 3)) * BY + ly0 + (m >> 2);
+  const int goff0 = (ly0 + (m >> 2)) * C::BZ + lz0 + (m & 3);
+  const int gmoff0 = (lz0 + (m & 3)) * BY + ly0 + (m >> 2);
 
   constexpr int D = NS - 1;  // stages in flight ahead of the one being consumed
   static_assert(D <= 3, "wait_pipe allows at most two stages in flight behind the next one");
@@ -238,23 +249,29 @@ __global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int
       ++issued;
     }
     __builtin_amdgcn_sched_barrier(0);
-    const double* __restrict__ st = lds + buf * C::STAGE;
+    const char* __restrict__ st = lds + buf * C::STAGE_B;
+    const double* __restrict__ sg = (const double*)(st + C::G_B);
+    const double* __restrict__ sgm = (const double*)(st + C::GM_B);
+    auto pair = [&](int sp) {  // this lane's X in stage pair sp, as two FP64 values
+      const char* a = st + sp * C::PAIR_B + lane * 2 * C::ESZ;
+      if constexpr (C::ESZ == 8) return pair_at(a); else return pair_at_f(a);
+    };
     d2 ey[WY / 2], fy[WY / 2], ez[WZ / 2], fz[WZ / 2];
     double g[2], gm[2];
 #pragma unroll
     for (int p = 0; p < WZ / 2; ++p) {
-      ez[p] = *(const d2*)&st[C::EZ + (lz0 / 2 + p) * 128 + 2 * lane];
-      fz[p] = *(const d2*)&st[C::FZ + (lz0 / 2 + p) * 128 + 2 * lane];
+      ez[p] = pair(C::EZ + lz0 / 2 + p);
+      fz[p] = pair(C::FZ + lz0 / 2 + p);
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      g[r] = st[goff0 + 4 * r * C::BZ];
-      gm[r] = st[gmoff0 + 4 * r];
+      g[r] = sg[goff0 + 4 * r * C::BZ];
+      gm[r] = sgm[gmoff0 + 4 * r];
     }
 #pragma unroll
     for (int p = 0; p < WY / 2; ++p) {
-      ey[p] = *(const d2*)&st[C::EY + (ly0 / 2 + p) * 128 + 2 * lane];
-      fy[p] = *(const d2*)&st[C::FY + (ly0 / 2 + p) * 128 + 2 * lane];
+      ey[p] = pair(C::EY + ly0 / 2 + p);
+      fy[p] = pair(C::FY + ly0 / 2 + p);
     }
     const double ezs[WZ] = {ez[0].x, ez[0].y, ez[1].x, ez[1].y};
     const double fzs[WZ] = {fz[0].x, fz[0].y, fz[1].x, fz[1].y};
@@ -287,7 +304,6 @@ __global__ __launch_bounds__((Geo<NWZ, NS>::NTHREADS)) void h_kernel(int Pp, int
         for (int k = 0; k < WZ; ++k) bstore(accm[j][k], rm, lo, (unsigned)(k * Pp + j) * xrow);
     }
   }
-  }  // tile loop: the last wait_pipe above left every wave past its final LDS read
 }
 
 template <int NWZ>
@@ -310,45 +326,49 @@ std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb, int64_t slots) {
   return out;
 }
 
-template <int NWZ, int NS>
-hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const double* E, const double* F,
-                  const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots, bool persistent,
-                  hipStream_t s) {
+template <int NWZ, int NS, typename TE>
+hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const TE* E, const TE* F,
+                  const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots, hipStream_t s) {
   if (Pp % 64 != 0 || Pp > 8192 || Xb % LANES != 0 || Xb > Pp || Xb <= 0 || ntiles <= 0 || ntiles > 2147483647LL ||
       nI < 0 || slots < 1 || ntiles % (8 * slots) != 0 || ldx < Xb || ldx > 2 * Pp || ldg < Pp || ldg > 2 * Pp)
     return hipErrorInvalidValue;
-  const int64_t grid = persistent ? std::min<int64_t>(ntiles, 8 * slots) : ntiles;
-  hipLaunchKernelGGL((h_kernel<NWZ, NS>), dim3((unsigned)grid), dim3(Geo<NWZ, NS>::NTHREADS), 0, s, (int)Pp, (int)Xb,
-                     (int)ldx, (int)ldg, nI, E, F, G, H, tiles, ntiles);
+  hipLaunchKernelGGL((h_kernel<NWZ, NS, TE>), dim3((unsigned)ntiles), dim3(Geo<NWZ, NS, TE>::NTHREADS), 0, s,
+                     (int)Pp, (int)Xb, (int)ldx, (int)ldg, nI, E, F, G, H, tiles);
   return hipGetLastError();
 }
 
-constexpr int H_NWZ = 2, H_NS = 3;  // 4 waves, 26 KB stages, three stages (two workgroups per CU)
+constexpr int H_NWZ = 2, H_NS = 3;    // 4 waves, 26 KB stages, three stages (two workgroups per CU)
+constexpr int H_NS32 = 4;             // FP32 E, F: 14 KB stages, four stages
 
 }  // namespace
 
 // Resident workgroups per XCD (8 XCDs; workgroup b runs on XCD b % 8): CUs per XCD times the
-// workgroups of this kernel that fit on one CU.
+// workgroups of the FP64 kernel that fit on one CU.
 int64_t h_slots_per_xcd() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, h_kernel<H_NWZ, H_NS>, Geo<H_NWZ, H_NS>::NTHREADS, 0) !=
-          hipSuccess)
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, h_kernel<H_NWZ, H_NS, double>,
+                                                   Geo<H_NWZ, H_NS, double>::NTHREADS, 0) != hipSuccess)
     return 0;
   return std::max<int64_t>(1, (int64_t)(cus / 8) * std::max(per_cu, 1));
 }
 
 // Tile table: every (X tile, Y block Yb, Z block Zb >= Yb, Z slice) once, in runs of `slots`
-// tiles that share an X tile, 4 Y blocks and 8 Z blocks.  The kernel runs 8 slots workgroups,
-// each walking the table with stride 8 slots; run c sits at b = 8 slots (c / 8) + 8 k + (c % 8),
-// k < slots, so the tiles of one run are processed at the same time on one XCD and share their
-// operand rows through its L2.  Unused entries are EMPTY.
+// tiles that share an X tile, 4 Y blocks and 8 Z blocks; run c sits at workgroup ids
+// b = 8 slots (c / 8) + 8 k + (c % 8), k < slots, so that it runs on one XCD.  Unused entries are
+// EMPTY.
 std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots) { return tiles_for<H_NWZ>(Pp, Xb, slots); }
 
 hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const double* E, const double* F,
                         const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
                         hipStream_t s) {
-  return launch<H_NWZ, H_NS>(Pp, Xb, ldx, ldg, nI, E, F, G, H, tiles, ntiles, slots, false, s);
+  return launch<H_NWZ, H_NS, double>(Pp, Xb, ldx, ldg, nI, E, F, G, H, tiles, ntiles, slots, s);
+}
+
+hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const float* E, const float* F,
+                          const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
+                          hipStream_t s) {
+  return launch<H_NWZ, H_NS32, float>(Pp, Xb, ldx, ldg, nI, E, F, G, H, tiles, ntiles, slots, s);
 }
 
 }  // namespace thc

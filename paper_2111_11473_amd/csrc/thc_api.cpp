@@ -79,6 +79,9 @@ struct thc_ctx {
   // Alg. 6
   double *C6 = nullptr, *D6 = nullptr, *Ec = nullptr, *Fc = nullptr, *Gc = nullptr, *GYc = nullptr, *Hb = nullptr;
   double* delta = nullptr;     // Jacobi denominator shift of the learned guess (nP)
+  bool mixed = false;          // the residual being evaluated uses FP32 MFMA / FP32 H operands
+  bool want_mixed = false;     // requested precision of the next residual evaluation
+  float *Ec32 = nullptr, *Fc32 = nullptr;  // FP32 H-kernel operands (mixed precision only)
   bool has_shift = false;
   uint32_t* htiles = nullptr;  // H-kernel tile table
   int64_t nhtiles = 0, hslots = 0;
@@ -90,6 +93,7 @@ struct thc_ctx {
 
   // per-iteration history of the last thc_iterate call
   std::vector<double> hist_e, hist_r, hist_t;
+  std::vector<int> hist_mixed;  // 1 where the iteration's residual was mixed precision
 
   // profiling
   bool prof = false;
@@ -148,8 +152,10 @@ struct Scope {
   }
 };
 
-int gemm(thc_ctx* ctx, const Gemm& g) {
+int gemm(thc_ctx* ctx, const Gemm& g0) {
   Scope sc(ctx, "gemm");
+  Gemm g = g0;
+  if (ctx->mixed && !g.keep64) g.f32 = true;
   if (ctx->prof && ctx->section) {
     Scope sc2(ctx, ctx->section);
     HIPCHK(gemm_f64(g, ctx->stream));
@@ -158,6 +164,19 @@ int gemm(thc_ctx* ctx, const Gemm& g) {
   }
   return THC_OK;
 }
+
+// Marks a product that stays FP64 in the mixed-precision path (energy partials, T1 dressing).
+Gemm k64(Gemm g) {
+  g.keep64 = true;
+  return g;
+}
+
+// Sets the precision for one residual evaluation and restores FP64 on every exit.
+struct MixedScope {
+  thc_ctx* ctx;
+  MixedScope(thc_ctx* c) : ctx(c) { ctx->mixed = ctx->want_mixed; }
+  ~MixedScope() { ctx->mixed = false; }
+};
 
 // Plain (batched) GEMM helper.
 Gemm mk(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, bool tA, const double* B, int64_t ldb,
@@ -358,6 +377,16 @@ int plan_and_alloc(thc_ctx* ctx) {
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
   }
+  if (op.precision == 1) {  // FP32 E, F for the mixed-precision H-kernel
+    const int64_t nf = ctx->Ic * ldx * Pp;
+    double *e32 = nullptr, *f32 = nullptr;
+    RCHK(alloc(ctx, &e32, (size_t)((nf + 1) / 2)));
+    RCHK(alloc(ctx, &f32, (size_t)((nf + 1) / 2)));
+    RCHK(zero(ctx, e32, (nf + 1) / 2));
+    RCHK(zero(ctx, f32, (nf + 1) / 2));
+    ctx->Ec32 = reinterpret_cast<float*>(e32);
+    ctx->Fc32 = reinterpret_cast<float*>(f32);
+  }
   ctx->diisB.assign((size_t)std::max<int64_t>(dm, 1) * std::max<int64_t>(dm, 1), 0.0);
   return THC_OK;
 }
@@ -375,6 +404,7 @@ int read_scalars(thc_ctx* ctx, double* h, int count) {
 // energy partial sums in ctx->scal[0..3] (E_J, E_K, singles: 2 sum d_A^2, sum tr K_A^2).
 int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask) {
   Scope whole(ctx, "residual");
+  MixedScope precision(ctx);
   hipStream_t s = ctx->stream;
   const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
   const int64_t PP = P * P, Pp = ctx->Pp;
@@ -403,8 +433,8 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     const double* Lhoo = Loo;  // dressed blocks (Eq. 27); the undressed ones in CCD mode
     if (singles) {
       // tmpoo[A] = Lov t1^T (o x o), also in the [i][A][k] layout for the Fock K-term
-      RCHK(gemm(ctx, batched(mk(o, o, v, Lov, v, false, t1, v, true, ctx->tmpoo, o), nb, ov, 0, o * o)));
-      RCHK(gemm(ctx, batched(mk(o, o, v, Lov, v, false, t1, v, true, ctx->tmpooT, nb * o), nb, ov, 0, o)));
+      RCHK(gemm(ctx, k64(batched(mk(o, o, v, Lov, v, false, t1, v, true, ctx->tmpoo, o), nb, ov, 0, o * o))));
+      RCHK(gemm(ctx, k64(batched(mk(o, o, v, Lov, v, false, t1, v, true, ctx->tmpooT, nb * o), nb, ov, 0, o))));
       MISC(k_copy2d(1, nb * o, o, Loo, o, 0, ctx->Lhoo, o, 0, false, s));
       MISC(k_axpby(nb * o * o, 1.0, ctx->tmpoo, 1.0, ctx->Lhoo, s));
       Lhoo = ctx->Lhoo;
@@ -412,24 +442,24 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       // d_A = sum_ia t_ia L_ia^A
       MISC(k_gemv(nb, ov, Lov, ov, t1, ctx->dvecA + A0, s));
       // Pv[A] = Lvv t1^T (v x o), in [A][a][k] and [a][A][k] layouts
-      RCHK(gemm(ctx, batched(mk(v, o, v, Lvv, v, false, t1, v, true, ctx->Pv, o), nb, v * v, 0, v * o)));
-      RCHK(gemm(ctx, batched(mk(v, o, v, Lvv, v, false, t1, v, true, ctx->PvT, nb * o), nb, v * v, 0, o)));
+      RCHK(gemm(ctx, k64(batched(mk(v, o, v, Lvv, v, false, t1, v, true, ctx->Pv, o), nb, v * v, 0, v * o))));
+      RCHK(gemm(ctx, k64(batched(mk(v, o, v, Lvv, v, false, t1, v, true, ctx->PvT, nb * o), nb, v * v, 0, o))));
       // Lhvo[A] = Lov^T + Lvv t1^T - t1^T Lhoo
       MISC(k_copy2d(nb, v, o, Lov, v, ov, ctx->Lhvo, o, v * o, true, s));
       MISC(k_axpby(nb * v * o, 1.0, ctx->Pv, 1.0, ctx->Lhvo, s));
-      RCHK(gemm(ctx, batched(mk(v, o, o, t1, v, true, ctx->Lhoo, o, false, ctx->Lhvo, o, -1.0, 1.0), nb, 0, o * o, v * o)));
+      RCHK(gemm(ctx, k64(batched(mk(v, o, o, t1, v, true, ctx->Lhoo, o, false, ctx->Lhvo, o, -1.0, 1.0), nb, 0, o * o, v * o))));
       // Fock: inner += 2 sum_A d_A L^A - sum_A (L^A[:, vir] t1^T) L^A[occ, :]
       MISC(k_wsum(nb, o * o, ctx->dvecA + A0, Loo, o * o, 2.0, ctx->Fin, s));  // oo block written densely below
       // (the block layout of Fin: [oo | ov | vo | vv] stored contiguously)
       MISC(k_wsum(nb, ov, ctx->dvecA + A0, Lov, ov, 2.0, ctx->Fin + o * o, s));
       MISC(k_wsum(nb, v * v, ctx->dvecA + A0, Lvv, v * v, 2.0, ctx->Fin + o * o + 2 * ov, s));
-      RCHK(gemm(ctx, mk(o, o, nb * o, ctx->tmpooT, nb * o, false, Loo, o, false, ctx->Fin, o, -1.0, 1.0)));
-      RCHK(gemm(ctx, mk(o, v, nb * o, ctx->tmpooT, nb * o, false, Lov, v, false, ctx->Fin + o * o, v, -1.0, 1.0)));
-      RCHK(gemm(ctx, mk(v, o, nb * o, ctx->PvT, nb * o, false, Loo, o, false, ctx->Fin + o * o + ov, o, -1.0, 1.0)));
-      RCHK(gemm(ctx, mk(v, v, nb * o, ctx->PvT, nb * o, false, Lov, v, false, ctx->Fin + o * o + 2 * ov, v, -1.0, 1.0)));
+      RCHK(gemm(ctx, k64(mk(o, o, nb * o, ctx->tmpooT, nb * o, false, Loo, o, false, ctx->Fin, o, -1.0, 1.0))));
+      RCHK(gemm(ctx, k64(mk(o, v, nb * o, ctx->tmpooT, nb * o, false, Lov, v, false, ctx->Fin + o * o, v, -1.0, 1.0))));
+      RCHK(gemm(ctx, k64(mk(v, o, nb * o, ctx->PvT, nb * o, false, Loo, o, false, ctx->Fin + o * o + ov, o, -1.0, 1.0))));
+      RCHK(gemm(ctx, k64(mk(v, v, nb * o, ctx->PvT, nb * o, false, Lov, v, false, ctx->Fin + o * o + 2 * ov, v, -1.0, 1.0))));
     }
     // LovYv[A] = Lov Yv (o x P)
-    RCHK(gemm(ctx, batched(mk(o, P, v, Lov, v, false, Yv, P, false, ctx->LovYv, P), nb, ov, 0, o * P)));
+    RCHK(gemm(ctx, k64(batched(mk(o, P, v, Lov, v, false, Yv, P, false, ctx->LovYv, P), nb, ov, 0, o * P))));
     // Wv[A] = L^vv Yv (v x P), dressed by - t1^T (Lov Yv)
     RCHK(gemm(ctx, batched(mk(v, P, v, Lvv, v, false, Yv, P, false, ctx->Wv, P), nb, v * v, 0, v * P)));
     if (singles)
@@ -454,7 +484,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     MISC(k_colsum_rowscaled(nb, o, P, Yo, singles ? ctx->Wvo : ctx->LovYv, o * P, ctx->Abar + A0, nL, s));
     MISC(k_colsum_rowscaled(nb, o, P, Yo, ctx->LovYv, o * P, ctx->At + A0, nL, s));
     // M^T[A] = (Lov Yv)^T Yo ; F = T o M^T ; exchange energy partials  (Alg. 2)
-    RCHK(gemm(ctx, batched(mk(P, P, o, ctx->LovYv, P, true, Yo, P, false, ctx->Boo, P), nb, o * P, 0, PP)));
+    RCHK(gemm(ctx, k64(batched(mk(P, P, o, ctx->LovYv, P, true, Yo, P, false, ctx->Boo, P), nb, o * P, 0, PP))));
     MISC(k_hadamard_energy(P, nb, T, ctx->Boo, ctx->Bvv, ctx->ek + A0 * 64, s));
     // G[A] = Yo F Yv^T (o x v); H^X_A = sum_ia y_i^X y_a^X G_ia  (Alg. 2)
     RCHK(gemm(ctx, batched(mk(o, P, P, Yo, P, false, ctx->Bvv, P, false, ctx->Y1, P), nb, 0, PP, o * P)));
@@ -462,7 +492,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     RCHK(gemm(ctx, batched(mk(o, P, v, ctx->Gm, v, false, Yv, P, false, ctx->GY, P), nb, ov, 0, o * P)));
     MISC(k_colsum_rowscaled(nb, o, P, Yo, ctx->GY, o * P, ctx->Hh + A0, nL, s));
     // TA = T Atil (P x nb); Coulomb energy partials Atil^T T Atil
-    RCHK(gemm(ctx, mk(P, nb, P, T, P, false, ctx->At + A0, nL, false, ctx->TA, nb)));
+    RCHK(gemm(ctx, k64(mk(P, nb, P, T, P, false, ctx->At + A0, nL, false, ctx->TA, nb))));
     MISC(k_dot_cols(P, nb, ctx->At + A0, nL, ctx->TA, nb, ctx->ej + A0, s));
     // D8[A] = 2 Yo diag(T Atil_A) Yv^T - G[A]  (Alg. 8), in place of G
     {
@@ -491,6 +521,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
 
   // ---------------- Fock matrix, T1-transformed (Eq. 24-27) -----------------------------------
   ctx->section = "gemm@fock";
+  ctx->mixed = false;  // the T1-transformed Fock matrix stays FP64
   double* Foo = ctx->Fh;
   double* Fov = ctx->Fh + o * o;
   double* Fvo = ctx->Fh + o * o + ov;
@@ -525,6 +556,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
 
   // ---------------- assembly of the symmetric terms (Alg. 2, 3, 9) ----------------------------
   ctx->section = "gemm@assembly";
+  ctx->mixed = ctx->want_mixed;
   RCHK(gemm(ctx, mk(P, P, P, ctx->S, P, false, T, P, false, ctx->ST, P)));
   if (mask & THC_TERM_EQ28) MISC(k_batch_sum(ctx->KS, PP, ctx->sig28, 1.0, ctx->sig, s));
   if (mask & THC_TERM_EQ29) {
@@ -575,16 +607,28 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       for (int64_t I0 = 0; I0 < Q; I0 += ctx->Ic) {
         const int64_t ic = std::min(ctx->Ic, Q - I0);
         // E_I = sum_i x_i^I C6[i];  F_I = sum_a x_a^I D6[a]  (elementwise in the [Y/2][x][2] layout)
-        RCHK(gemm(ctx, mk(ic, ldx * Pp, o, xo + I0, Q, true, ctx->C6, ldx * Pp, false, ctx->Ec, ldx * Pp)));
-        RCHK(gemm(ctx, mk(ic, ldx * Pp, v, xv + I0, Q, true, ctx->D6, ldx * Pp, false, ctx->Fc, ldx * Pp)));
+        {
+          Gemm ge = mk(ic, ldx * Pp, o, xo + I0, Q, true, ctx->C6, ldx * Pp, false, ctx->Ec, ldx * Pp);
+          Gemm gf = mk(ic, ldx * Pp, v, xv + I0, Q, true, ctx->D6, ldx * Pp, false, ctx->Fc, ldx * Pp);
+          if (ctx->mixed) {  // FP32 operands for the H-kernel
+            ge.C = nullptr; ge.Cf = ctx->Ec32;
+            gf.C = nullptr; gf.Cf = ctx->Fc32;
+          }
+          RCHK(gemm(ctx, ge));
+          RCHK(gemm(ctx, gf));
+        }
         // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6)
         RCHK(gemm(ctx, mk(ic * o, P, v, ctx->Bq + I0 * ov, v, false, Yv, P, false, ctx->GYc, P)));
         RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, ctx->ldg), ic, 0, o * P,
                                Pp * ctx->ldg)));
         {
           Scope sc(ctx, "h_kernel");
-          HIPCHK(h_accumulate(Pp, Xb, ctx->ldx, ctx->ldg, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles,
-                              ctx->nhtiles, ctx->hslots, s));
+          if (ctx->mixed)
+            HIPCHK(h_accumulate32(Pp, Xb, ctx->ldx, ctx->ldg, ic, ctx->Ec32, ctx->Fc32, ctx->Gc, ctx->Hb, ctx->htiles,
+                                  ctx->nhtiles, ctx->hslots, s));
+          else
+            HIPCHK(h_accumulate(Pp, Xb, ctx->ldx, ctx->ldg, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles,
+                                ctx->nhtiles, ctx->hslots, s));
         }
       }
       // I^X_ia = sum_YZ y_i^Z y_a^Y H^XYZ ; sigma^XW += sum_ia y_i^W y_a^W I^X_ia  (Alg. 6)
@@ -828,7 +872,7 @@ int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
   if (!opt || !out) return THC_EINVAL;
   *out = nullptr;
   if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
-      opt->diis_max > 16 || opt->precision != 0 || (opt->flags & ~THC_FLAG_UNFUSED_EXCHANGE) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
+      opt->diis_max > 16 || (opt->precision != 0 && opt->precision != 1) || (opt->flags & ~THC_FLAG_UNFUSED_EXCHANGE) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
       opt->x_chunk < 0)
     return THC_EINVAL;
   thc_ctx* ctx = new (std::nothrow) thc_ctx();
@@ -987,6 +1031,7 @@ int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t
   if (!ctx) return THC_EINVAL;
   RCHK(need_built(ctx));
   if (!Z || !sigma) { ctx->err = "null argument"; return THC_EINVAL; }
+  ctx->want_mixed = ctx->opt.precision == 1;
   RCHK(residual_impl(ctx, Z, ctx->opt.singles ? t1 : nullptr, mask));
   HIPCHK(hipMemcpyAsync(sigma, ctx->sig, ctx->P * ctx->P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   if (sigma1) HIPCHK(hipMemcpyAsync(sigma1, ctx->sig1, ctx->ov * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
@@ -1011,6 +1056,7 @@ int thc_residual(thc_ctx* ctx, const double* Z, const double* t1, double* sigma,
 int thc_energy(thc_ctx* ctx, double* e_corr) {
   if (!ctx || !e_corr) return THC_EINVAL;
   RCHK(need_built(ctx));
+  ctx->want_mixed = false;
   RCHK(residual_impl(ctx, ctx->Zs, ctx->t1, 0u));
   double h[4];
   RCHK(read_scalars(ctx, h, 4));
@@ -1054,7 +1100,14 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   ctx->hist_r.clear();
   ctx->hist_t.clear();
   const auto t_start = std::chrono::steady_clock::now();
+  // precision ladder (mixed precision): FP32-MFMA residuals until their norm has dropped 1e4-fold,
+  // is within 10 tol, or stops decreasing; then FP64 residuals, which alone may declare convergence
+  bool mixed_phase = ctx->opt.precision == 1;
+  double rn_first = -1.0, rn_prev = 0.0;
+  int mixed_its = 0;
+  ctx->hist_mixed.clear();
   for (int it = 1; it <= maxit; ++it) {
+    ctx->want_mixed = mixed_phase;
     RCHK(residual_impl(ctx, ctx->Zs, singles ? ctx->t1 : nullptr, THC_TERM_ALL));
     RCHK(project_basis(ctx));
     double h[10];
@@ -1071,7 +1124,15 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
     ctx->hist_e.push_back(E);
     ctx->hist_r.push_back(rn);
     ctx->hist_t.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
-    if (have_old && rn < tol && std::fabs(E - E_old) < ctx->opt.tol_energy) return THC_OK;
+    ctx->hist_mixed.push_back(mixed_phase ? 1 : 0);
+    if (mixed_phase) {
+      ++mixed_its;
+      if (rn_first < 0.0) rn_first = rn;
+      if (rn < 1e-4 * rn_first || rn < 10.0 * tol || (mixed_its >= 3 && rn > 0.7 * rn_prev)) mixed_phase = false;
+      rn_prev = rn;
+    } else if (have_old && rn < tol && std::fabs(E - E_old) < ctx->opt.tol_energy) {
+      return THC_OK;
+    }
     E_old = E;
     have_old = true;
     // Jacobi step in the working basis; (dT, dt1) is the DIIS error vector
@@ -1150,6 +1211,14 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   }
   ctx->err = "iteration limit reached";
   return THC_ENOTCONV;
+}
+
+int thc_history_precision(const thc_ctx* ctx, int max, int* mixed, int* count) {
+  if (!ctx || max < 0 || (max > 0 && !mixed)) return THC_EINVAL;
+  const int n = (int)ctx->hist_mixed.size();
+  for (int k = 0; k < std::min(n, max); ++k) mixed[k] = ctx->hist_mixed[k];
+  if (count) *count = n;
+  return THC_OK;
 }
 
 int thc_history(const thc_ctx* ctx, int max, double* energy, double* rnorm, double* seconds, int* count) {
@@ -1245,6 +1314,7 @@ int thc_working(thc_ctx* ctx, double* Th, double* sigma_hat) {
   const int64_t PP = ctx->P * ctx->P;
   if (Th) HIPCHK(hipMemcpyAsync(Th, ctx->Th, PP * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   if (sigma_hat) {
+    ctx->want_mixed = false;
     RCHK(residual_impl(ctx, ctx->Zs, ctx->opt.singles ? ctx->t1 : nullptr, THC_TERM_ALL));
     RCHK(project_basis(ctx));
     HIPCHK(hipMemcpyAsync(sigma_hat, ctx->sigh, PP * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));

@@ -27,6 +27,7 @@ TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TER
 
 # exported symbols (kept in sync with include/thc.h; checked by the tests)
 SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_history",
+           "thc_history_precision",
            "thc_energy",
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_profile", "thc_profile_get", "thc_dgemm",
            "thc_last_error", "thc_destroy",
@@ -69,6 +70,7 @@ def load(path: str = LIB_PATH):
     lib.thc_iterate.argtypes = [VP, D, C.c_int, C.POINTER(C.c_int), C.POINTER(D)]
     lib.thc_history.argtypes = [VP, C.c_int, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(C.c_int)]
     lib.thc_energy.argtypes = [VP, C.POINTER(D)]
+    lib.thc_history_precision.argtypes = [VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.thc_get_state.argtypes = [VP, P, P]
     lib.thc_set_state.argtypes = [VP, P, P]
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
@@ -156,12 +158,12 @@ class THC:
     """One THC-CCSD problem on the current GPU (all tensors float64, CUDA, contiguous)."""
 
     def __init__(self, o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0,
-                 x_block=0, x_chunk=0, flags=0):
+                 x_block=0, x_chunk=0, flags=0, precision=0):
         self.lib = load()
         self.o, self.v, self.nL, self.nP, self.nQ = o, v, nL, nP, nQ
         self.singles = bool(singles)
-        opt = Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk, 0,
-                      flags)
+        opt = Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
+                      precision, flags)
         h = C.c_void_p()
         rc = self.lib.thc_create(C.byref(opt), _stream(), C.byref(h))
         if rc != 0:
@@ -230,6 +232,13 @@ class THC:
         self._check(self.lib.thc_history(self.ctx, max_it, e, r, t, C.byref(n)), "thc_history")
         m = min(n.value, max_it)
         return list(e[:m]), list(r[:m]), list(t[:m])
+
+    def history_precision(self, max_it=1000):
+        """1 for each iteration of the last iterate() whose residual was mixed precision, else 0."""
+        f = (C.c_int * max_it)()
+        n = C.c_int(0)
+        self._check(self.lib.thc_history_precision(self.ctx, max_it, f, C.byref(n)), "thc_history_precision")
+        return list(f[:min(n.value, max_it)])
 
     def energy(self):
         e = C.c_double(0.0)
