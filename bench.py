@@ -6,10 +6,12 @@ current amplitudes (paper Alg. 1-10), the correlation energy, the Jacobi update 
 basis and DIIS.  The workload is the FP64 configuration o=50, v=450, N_L=1500, N_P=1000,
 N_Q=2500 with seeded synthetic inputs (all resident in HBM before the timed region).
 
-Prints one JSON line: residual evaluations per second, the roofline of the dominant kernel
-(the VALU H-kernel of Alg. 6, timed with HIP events on the library's stream during the timed
-steps), the time to converge the FP64 solve to 1e-6 Eh of its final energy, and the FP64 CPU
-oracle timed on a bounded sample on the host cores.
+Prints one JSON line: FP64 residual evaluations per second (the value), the roofline of the
+dominant kernel (the VALU H-kernel of Alg. 6, timed with HIP events on the library's stream
+during the timed steps), the MFMA rates of the GEMMs and of the fused exchange kernel, the
+fraction of the ideal residual time, the time to converge to 1e-6 Eh of the final energy, the
+same for the mixed-precision path (its energy against the FP64 solve), and the FP64 CPU oracle
+timed on a bounded sample on the host cores.
 """
 import argparse
 import hashlib
@@ -22,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector peak (256 CUs, 2.4 GHz)
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -102,6 +105,7 @@ def main():
     ap.add_argument("--config", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--converge-maxit", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (a known-traffic kernel for counter scaling)")
@@ -130,30 +134,64 @@ def main():
         del a, b
     s = synth.make_system(cfg)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-    L, eps = dev(s["L"]), dev(s["eps"])
-    Xo, Xv, xo, xv = (dev(s[k]) for k in ("Xo", "Xv", "xo", "xv"))
-    ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, singles=True, diis_max=8, tol_energy=1e-8)
-    Z0 = ctx.build_factors(L, eps, Xo, Xv, xo, xv)
-    del L
-    torch.cuda.synchronize()
+    P, Q, o = cfg.nP, cfg.nQ, cfg.o
 
-    for _ in range(args.warmup):
-        ctx.iterate(tol=0.0, maxit=1, raise_on_notconv=False)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.iterate(tol=0.0, maxit=1, raise_on_notconv=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    h_ms, h_n = ctx.profile_get("h_kernel")
-    r_ms, r_n = ctx.profile_get("residual")
-    g_ms, _ = ctx.profile_get("gemm")
-    m_ms, _ = ctx.profile_get("misc")
-    ctx.profile(False)
+    def leg(precision):
+        """Timed solver steps (one residual + update each) and the converge run of one precision."""
+        ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, singles=True, diis_max=8, tol_energy=1e-8,
+                      precision=precision)
+        Z0 = ctx.build_factors(dev(s["L"]), dev(s["eps"]), *(dev(s[k]) for k in ("Xo", "Xv", "xo", "xv")))
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            ctx.iterate(tol=0.0, maxit=1, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.iterate(tol=0.0, maxit=1, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = {name: ctx.profile_get(name) for name in ("h_kernel", "residual", "gemm", "misc", "exch")}
+        flops64, flops32 = ctx.profile_flops()
+        ctx.profile(False)
+        conv = None
+        if not args.no_converge:
+            ctx.set_state(Z0)
+            tc = time.perf_counter()
+            it, rn, ok = ctx.iterate(tol=1e-7, maxit=args.converge_maxit, raise_on_notconv=False)
+            wall = time.perf_counter() - tc
+            E, R, T = ctx.history()
+            Ef = E[-1]
+            conv = {"converged": bool(ok), "iterations": it, "final_energy": Ef, "final_rnorm": rn,
+                    "solve_seconds": wall, "energies": E, "seconds": T,
+                    "mixed_iterations": sum(ctx.history_precision()),
+                    "guess": "MP2 least-squares fit", "solver": "Jacobi (pseudo-canonical) + DIIS(8)"}
+        ctx.close()
+        torch.cuda.synchronize()
+        return dt, prof, flops64 / args.steps, flops32 / args.steps, conv
 
-    P, Q = cfg.nP, cfg.nQ
+    def to_target(conv, e_ref):
+        """Iterations and seconds until the energy stays within 1e-6 Eh of e_ref."""
+        if conv is None:
+            return None
+        E, T = conv.pop("energies"), conv.pop("seconds")
+        k = len(E) - 1
+        while k > 0 and abs(E[k - 1] - e_ref) < 1e-6:
+            k -= 1
+        if abs(E[k] - e_ref) >= 1e-6:
+            return conv
+        conv["iterations_to_1e-6"] = k + 1
+        conv["seconds_to_1e-6"] = T[k]
+        return conv
+
+    dt, prof, gf64, _, conv64 = leg(0)
+    h_ms, h_n = prof["h_kernel"]
+    r_ms, r_n = prof["residual"]
+    g_ms, _ = prof["gemm"]
+    m_ms, _ = prof["misc"]
+    x_ms, _ = prof["exch"]
+
     # algorithmic: per (X, I) and unordered pair {Y, Z}, the symmetric bracket once (3 flops) and one
     # FMA into each of H^XYZ and H^XZY (4 flops): 3.5 flops per (X, Y, Z, I)
     h_flops_per_residual = 3.5 * Q * P ** 3
@@ -161,21 +199,34 @@ def main():
     flops_per_launch = h_flops_per_residual / launches_per_residual
     avg_launch_s = (h_ms / 1e3) / max(1, h_n)
     achieved = flops_per_launch / avg_launch_s / 1e12
+    exch_flops = 2 * 4.0 * P * o * Q * Q  # two exchange passes, two products of 2 o Q^2 each per X
+    g_per = g_ms / args.steps / 1e3
+    x_per = x_ms / args.steps / 1e3
+    t_res = r_ms / max(1, r_n) / 1e3
+    t_ideal = (h_flops_per_residual + gf64 + exch_flops) / (PEAK_FP64_VALU_TFLOPS * 1e12)
 
-    converge = None
-    if not args.no_converge:
-        ctx.set_state(Z0)
-        tc = time.perf_counter()
-        it, rn, ok = ctx.iterate(tol=1e-7, maxit=args.converge_maxit, raise_on_notconv=False)
-        wall = time.perf_counter() - tc
-        E, R, T = ctx.history()
-        Ef = E[-1]
-        k = len(E) - 1
-        while k > 0 and abs(E[k - 1] - Ef) < 1e-6:
-            k -= 1
-        converge = {"converged": bool(ok), "iterations": it, "final_energy": Ef, "final_rnorm": rn,
-                    "iterations_to_1e-6": k + 1, "seconds_to_1e-6": T[k], "solve_seconds": wall,
-                    "guess": "MP2 least-squares fit", "solver": "Jacobi (pseudo-canonical) + DIIS(8)"}
+    mixed = None
+    if not args.no_mixed:
+        dtm, profm, _, gf32m, convm = leg(1)
+        rm_ms, rm_n = profm["residual"]
+        gm_s = profm["gemm"][0] / args.steps / 1e3
+        t_res_m = rm_ms / max(1, rm_n) / 1e3
+        t_ideal_m = (h_flops_per_residual + exch_flops) / (PEAK_FP64_VALU_TFLOPS * 1e12) + gf32m / (PEAK_FP32_MFMA_TFLOPS * 1e12)
+        e_ref = conv64["final_energy"] if conv64 else None
+        if convm is not None and e_ref is not None:
+            convm["energy_minus_fp64"] = convm["final_energy"] - e_ref
+            convm = to_target(convm, e_ref)
+        mixed = {"residual_evals_per_s": args.steps / dtm, "ms_per_step": 1e3 * dtm / args.steps,
+                 "residual_ms": 1e3 * t_res_m, "h_kernel_ms": profm["h_kernel"][0] / args.steps,
+                 "gemm_ms": profm["gemm"][0] / args.steps,
+                 "gemm_fp32_mfma": {"achieved": gf32m / max(gm_s, 1e-12) / 1e12, "peak": PEAK_FP32_MFMA_TFLOPS,
+                                    "unit": "TFLOP/s"},
+                 "residual_roofline_frac": t_ideal_m / t_res_m,
+                 "precision": "FP32 MFMA contractions and FP32 H operands (FP64 accumulation), FP64 energy, "
+                              "denominators, fit, DIIS; FP64 finishing iterations",
+                 "converge": convm}
+    if conv64 is not None:
+        conv64 = to_target(conv64, conv64["final_energy"])
 
     out = {
         "metric": "residual_evals_per_s",
@@ -194,15 +245,20 @@ def main():
                                f"nL={cfg.nL} nP={cfg.nP} nQ={cfg.nQ}, seeded synthetic inputs",
                    "o": cfg.o, "v": cfg.v, "nL": cfg.nL, "nP": cfg.nP, "nQ": cfg.nQ, "precision": "fp64",
                    "parallelism": "single GPU"},
-        "roofline": {"kernel": "h_kernel (three-way accumulation of Alg. 6, FP64 VALU, Y<->Z symmetric)", "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS,
-                     "traffic": _traffic(cfg.name), "launches": h_n, "avg_launch_ms": 1e3 * avg_launch_s,
-                     "algorithmic_flops_per_launch": flops_per_launch},
-        "breakdown_ms_per_step": {"residual": r_ms / max(1, r_n), "h_kernel": h_ms / args.steps,
-                                  "gemm": g_ms / args.steps, "misc": m_ms / args.steps},
-        "converge": converge,
+        "roofline": {"kernel": "h_kernel (three-way accumulation of Alg. 6, FP64 VALU, Y<->Z symmetric)", "bound": "alu",
+                     "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": _traffic(cfg.name), "launches": h_n,
+                     "avg_launch_ms": 1e3 * avg_launch_s, "algorithmic_flops_per_launch": flops_per_launch},
+        "mfma": {"gemm_fp64": {"achieved": gf64 / max(g_per, 1e-12) / 1e12, "peak": PEAK_FP64_VALU_TFLOPS,
+                               "unit": "TFLOP/s", "flops_per_residual": gf64},
+                 "exchange_fp64": {"achieved": exch_flops / max(x_per, 1e-12) / 1e12, "peak": PEAK_FP64_VALU_TFLOPS,
+                                   "unit": "TFLOP/s", "flops_per_residual": exch_flops}},
+        "residual_roofline_frac": t_ideal / t_res,
+        "breakdown_ms_per_step": {"residual": 1e3 * t_res, "h_kernel": h_ms / args.steps, "gemm": g_ms / args.steps,
+                                  "exchange": x_ms / args.steps, "misc": m_ms / args.steps},
+        "converge": conv64,
+        "mixed": mixed,
         "cpu_baseline": cpu,
-        "gpu_memory_gb": ctx.memory_bytes() / 1e9,
     }
     print(json.dumps(out), flush=True)
 

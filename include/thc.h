@@ -137,6 +137,9 @@ int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes);
  * the summed duration in milliseconds and the number of launches recorded. */
 int thc_profile(thc_ctx* ctx, int enable);
 int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
+/* Flops (2 M N K per product) issued to the MFMA GEMM kernel since profiling was enabled, split
+ * into FP64 and FP32 (mixed precision) products. */
+int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops);
 
 /* The library's FP64 MFMA GEMM (exposed for testing): C = alpha op(A) op(B) + beta C,
  * row-major, op = transpose when trans* != 0, batched with element strides sA, sB, sC. */

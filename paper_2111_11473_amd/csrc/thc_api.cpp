@@ -79,6 +79,8 @@ struct thc_ctx {
   // Alg. 6
   double *C6 = nullptr, *D6 = nullptr, *Ec = nullptr, *Fc = nullptr, *Gc = nullptr, *GYc = nullptr, *Hb = nullptr;
   double* delta = nullptr;     // Jacobi denominator shift of the learned guess (nP)
+  void* pin = nullptr;         // pinned host staging buffer for every host <-> device transfer
+  size_t pin_bytes = 0;
   bool mixed = false;          // the residual being evaluated uses FP32 MFMA / FP32 H operands
   bool want_mixed = false;     // requested precision of the next residual evaluation
   float *Ec32 = nullptr, *Fc32 = nullptr;  // FP32 H-kernel operands (mixed precision only)
@@ -99,6 +101,7 @@ struct thc_ctx {
   bool prof = false;
   std::vector<ProfRec> recs;
   const char* section = nullptr;  // residual section, for per-section GEMM records ("gemm@<section>")
+  double gemm_flops = 0.0, gemm_flops32 = 0.0;  // MFMA GEMM flops (2 M N K per product) while profiling
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
 };
@@ -121,6 +124,51 @@ constexpr double C_D = 0.5;  // prefactor of the Eq. 35-37 ring contraction (clo
     int _r = (expr);               \
     if (_r != THC_OK) return _r;   \
   } while (0)
+
+// Host <-> device transfers go through one pinned staging buffer (grown on demand) and complete
+// before returning: the caller's host memory is plain pageable memory.
+template <class Ctx>
+void* pinned(Ctx* ctx, size_t bytes) {
+  if (bytes > ctx->pin_bytes) {
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
+    ctx->pin = nullptr;
+    ctx->pin_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&ctx->pin, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->pin = nullptr;
+      return nullptr;
+    }
+    ctx->pin_bytes = want;
+  }
+  return ctx->pin;
+}
+
+template <class Ctx>
+int d2h(Ctx* ctx, void* host, const void* dev, size_t bytes) {
+  if (bytes == 0) return THC_OK;
+  void* p = pinned(ctx, bytes);
+  if (!p) { ctx->err = "pinned staging allocation failed"; return THC_ENOMEM; }
+  HIPCHK(hipMemcpyAsync(p, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memcpy(host, p, bytes);
+  return THC_OK;
+}
+
+template <class Ctx>
+int h2d(Ctx* ctx, void* dev, const void* host, size_t bytes) {
+  if (bytes == 0) return THC_OK;
+  void* p = pinned(ctx, bytes);
+  if (!p) { ctx->err = "pinned staging allocation failed"; return THC_ENOMEM; }
+  std::memcpy(p, host, bytes);
+  HIPCHK(hipMemcpyAsync(dev, p, bytes, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return THC_OK;
+}
+
+// rows x cols block of doubles with device row pitch ld (elements) <-> packed host rows
+int d2h_block(thc_ctx* ctx, double* host, const double* dev, int64_t ld, int64_t rows, int64_t cols);
+int h2d_block(thc_ctx* ctx, double* dev, int64_t ld, const double* host, int64_t rows, int64_t cols);
 
 hipEvent_t next_event(thc_ctx* ctx) {
   if (ctx->pool_used == ctx->pool.size()) {
@@ -156,6 +204,7 @@ int gemm(thc_ctx* ctx, const Gemm& g0) {
   Scope sc(ctx, "gemm");
   Gemm g = g0;
   if (ctx->mixed && !g.keep64) g.f32 = true;
+  if (ctx->prof && g.K > 0) (g.f32 ? ctx->gemm_flops32 : ctx->gemm_flops) += 2.0 * g.M * g.N * g.K * g.batch;
   if (ctx->prof && ctx->section) {
     Scope sc2(ctx, ctx->section);
     HIPCHK(gemm_f64(g, ctx->stream));
@@ -227,23 +276,44 @@ int zero(thc_ctx* ctx, double* p, size_t count) {
 // updates are GEMMs.  Linv receives the inverses of the diagonal blocks.
 constexpr int64_t CB = 64;
 
-int potrf(thc_ctx* ctx, double* A, int64_t n, double* Linv, double* tmp) {
+int d2h_block(thc_ctx* ctx, double* host, const double* dev, int64_t ld, int64_t rows, int64_t cols) {
+  const size_t bytes = (size_t)(rows * cols) * sizeof(double);
+  void* p = pinned(ctx, bytes);
+  if (!p) { ctx->err = "pinned staging allocation failed"; return THC_ENOMEM; }
+  HIPCHK(hipMemcpy2DAsync(p, cols * sizeof(double), dev, ld * sizeof(double), cols * sizeof(double), rows,
+                          hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memcpy(host, p, bytes);
+  return THC_OK;
+}
+
+int h2d_block(thc_ctx* ctx, double* dev, int64_t ld, const double* host, int64_t rows, int64_t cols) {
+  const size_t bytes = (size_t)(rows * cols) * sizeof(double);
+  void* p = pinned(ctx, bytes);
+  if (!p) { ctx->err = "pinned staging allocation failed"; return THC_ENOMEM; }
+  std::memcpy(p, host, bytes);
+  HIPCHK(hipMemcpy2DAsync(dev, ld * sizeof(double), p, cols * sizeof(double), cols * sizeof(double), rows,
+                          hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return THC_OK;
+}
+
+int potrf(thc_ctx* ctx, double* A, int64_t n, double* Linv, double* tmp, const char* what) {
   std::vector<double> hb(CB * CB), hi(CB * CB);
   for (int64_t k0 = 0; k0 < n; k0 += CB) {
     const int64_t kb = std::min(CB, n - k0);
-    HIPCHK(hipMemcpy2DAsync(hb.data(), kb * sizeof(double), A + k0 * n + k0, n * sizeof(double), kb * sizeof(double), kb,
-                            hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    RCHK(d2h_block(ctx, hb.data(), A + k0 * n + k0, n, kb, kb));
     if (host_cholesky(kb, hb.data()) != 0) {
-      ctx->err = "matrix is not positive definite (Cholesky pivot <= 0)";
+      char buf[160];
+      snprintf(buf, sizeof buf, "%s is not positive definite (Cholesky pivot <= 0 in diagonal block %lld of %lld)",
+               what, (long long)(k0 / CB), (long long)((n + CB - 1) / CB));
+      ctx->err = buf;
       return THC_ESINGULAR;
     }
     host_tri_inverse_lower(kb, hb.data(), hi.data());
-    HIPCHK(hipMemcpy2DAsync(A + k0 * n + k0, n * sizeof(double), hb.data(), kb * sizeof(double), kb * sizeof(double), kb,
-                            hipMemcpyHostToDevice, ctx->stream));
+    RCHK(h2d_block(ctx, A + k0 * n + k0, n, hb.data(), kb, kb));
     double* Li = Linv + (k0 / CB) * CB * CB;
-    HIPCHK(hipMemcpyAsync(Li, hi.data(), kb * kb * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    RCHK(h2d(ctx, Li, hi.data(), kb * kb * sizeof(double)));
     const int64_t r0 = k0 + kb, rn = n - r0;
     if (rn <= 0) continue;
     // panel: A[r0:, k0:k0+kb] <- A[r0:, k0:k0+kb] L_kk^-T
@@ -373,9 +443,7 @@ int plan_and_alloc(thc_ctx* ctx) {
     RCHK(alloc(ctx, &tb, (tiles.size() + 1) / 2));
     ctx->htiles = reinterpret_cast<uint32_t*>(tb);
     ctx->nhtiles = (int64_t)tiles.size();
-    HIPCHK(hipMemcpyAsync(ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                          ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    RCHK(h2d(ctx, ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t)));
   }
   if (op.precision == 1) {  // FP32 E, F for the mixed-precision H-kernel
     const int64_t nf = ctx->Ic * ldx * Pp;
@@ -393,8 +461,7 @@ int plan_and_alloc(thc_ctx* ctx) {
 
 // Copies one scalar region of ctx->scal to the host.
 int read_scalars(thc_ctx* ctx, double* h, int count) {
-  HIPCHK(hipMemcpyAsync(h, ctx->scal, count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  RCHK(d2h(ctx, h, ctx->scal, count * sizeof(double)));
   return THC_OK;
 }
 
@@ -788,6 +855,8 @@ bool spd_solve(int64_t n, std::vector<double>& A, std::vector<double>& b, double
 
 struct thc_mlp {
   int64_t n_in = 0, w = 0, n_out = 0, np = 0;
+  void* pin = nullptr;  // pinned host staging buffer
+  size_t pin_bytes = 0;
   hipStream_t stream = nullptr;
   std::string err;
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
@@ -949,7 +1018,7 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
     }
     if (rc) break;
     MISC(k_copy2d(1, Q, nL, tmpw, Q, 0, Mq, nL, 0, true, s));  // M (Q x nL)
-    rc = potrf(ctx, GQ, Q, Linv, tsolve); if (rc) break;
+    rc = potrf(ctx, GQ, Q, Linv, tsolve, "the ERI grid metric G_Q"); if (rc) break;
     rc = trsm(ctx, GQ, Q, Linv, Mq, nL, false, tsolve); if (rc) break;
     rc = trsm(ctx, GQ, Q, Linv, Mq, nL, true, tsolve); if (rc) break;   // Mq = xi^T (Q x nL)
     rc = gemm(ctx, mk(Q, Q, nL, Mq, nL, false, Mq, nL, true, ctx->z, Q)); if (rc) break;
@@ -976,14 +1045,13 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
       MISC(k_hadamard(PP, tP, ctx->Gv, -1.0, 1.0, Em, s));
     }
     MISC(k_copy2d(1, P, P, ctx->S, P, 0, Sl, P, 0, false, s));
-    rc = potrf(ctx, Sl, P, Linv, tsolve); if (rc) break;
+    rc = potrf(ctx, Sl, P, Linv, tsolve, "the amplitude metric S"); if (rc) break;
     // C = L^-1 E L^-T : Y = L^-1 E, C = L^-1 Y^T
     rc = trsm(ctx, Sl, P, Linv, Em, P, false, tsolve); if (rc) break;
     MISC(k_copy2d(1, P, P, Em, P, 0, tmpw, P, 0, true, s));
     rc = trsm(ctx, Sl, P, Linv, tmpw, P, false, tsolve); if (rc) break;
     std::vector<double> hC(PP), hw(P);
-    HIPCHK(hipMemcpyAsync(hC.data(), tmpw, PP * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    rc = d2h(ctx, hC.data(), tmpw, PP * sizeof(double)); if (rc) break;
     for (int64_t i = 0; i < P; ++i)
       for (int64_t j = 0; j < i; ++j) {
         const double a = 0.5 * (hC[i * P + j] + hC[j * P + i]);
@@ -992,8 +1060,8 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
       }
     if (host_syev(P, hC.data(), hw.data()) != 0) { ctx->err = "eigensolver did not converge"; rc = THC_ENUMERIC; break; }
     if (hw[0] <= 0.0) { ctx->err = "projected Fock operator is not positive"; rc = THC_ESINGULAR; break; }
-    HIPCHK(hipMemcpyAsync(ctx->W, hC.data(), PP * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(ctx->e, hw.data(), P * sizeof(double), hipMemcpyHostToDevice, s));
+    rc = h2d(ctx, ctx->W, hC.data(), PP * sizeof(double)); if (rc) break;
+    rc = h2d(ctx, ctx->e, hw.data(), P * sizeof(double)); if (rc) break;
     rc = trsm(ctx, Sl, P, Linv, ctx->W, P, true, tsolve); if (rc) break;   // W = L^-T V
 
     // ---- MP2 guess: M = B^T t_MP2 B with t_MP2 = -(ia|jb)/Delta, T^0 = W^T M W ----
@@ -1044,8 +1112,7 @@ int thc_residual(thc_ctx* ctx, const double* Z, const double* t1, double* sigma,
   if (norms) {
     RCHK(project_basis(ctx));
     double h[10];
-    HIPCHK(hipMemcpyAsync(h, ctx->scal, 10 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    RCHK(d2h(ctx, h, ctx->scal, 10 * sizeof(double)));
     norms[0] = std::sqrt(h[8]);
     norms[1] = std::sqrt(h[9]);
     RCHK(check_finite_host(ctx, norms, 2, "residual norms"));
@@ -1157,8 +1224,7 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
       for (int k = 0; k < m; ++k)
         MISC(k_dot(len, ctx->derr + (int64_t)slots[k] * len, es, ctx->scal + 16 + k, s));
       double bd[16];
-      HIPCHK(hipMemcpyAsync(bd, ctx->scal + 16, m * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      RCHK(d2h(ctx, bd, ctx->scal + 16, m * sizeof(double)));
       for (int k = 0; k < m; ++k) {
         ctx->diisB[(size_t)slots[k] * dm + slot] = bd[k];
         ctx->diisB[(size_t)slot * dm + slots[k]] = bd[k];
@@ -1246,6 +1312,7 @@ int thc_profile(thc_ctx* ctx, int enable) {
   ctx->prof = enable != 0;
   ctx->recs.clear();
   ctx->pool_used = 0;
+  ctx->gemm_flops = ctx->gemm_flops32 = 0.0;
   return THC_OK;
 }
 
@@ -1263,6 +1330,13 @@ int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* l
   }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = cnt;
+  return THC_OK;
+}
+
+int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops) {
+  if (!ctx) return THC_EINVAL;
+  if (fp64_flops) *fp64_flops = ctx->gemm_flops;
+  if (fp32_flops) *fp32_flops = ctx->gemm_flops32;
   return THC_OK;
 }
 
@@ -1329,11 +1403,10 @@ int thc_guess_targets(thc_ctx* ctx, const double* Th0, const double* Tstar, cons
   RCHK(need_built(ctx));
   const int64_t P = ctx->P, PP = P * P;
   std::vector<double> T0(PP), Ts(PP), S0(PP), e(P);
-  HIPCHK(hipMemcpyAsync(T0.data(), Th0, PP * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(Ts.data(), Tstar, PP * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(S0.data(), sig0, PP * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(e.data(), ctx->e, P * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  RCHK(d2h(ctx, T0.data(), Th0, PP * sizeof(double)));
+  RCHK(d2h(ctx, Ts.data(), Tstar, PP * sizeof(double)));
+  RCHK(d2h(ctx, S0.data(), sig0, PP * sizeof(double)));
+  RCHK(d2h(ctx, e.data(), ctx->e, P * sizeof(double)));
   // c: Gauss-Newton on s = 1 + c for min || diag(s) T0 diag(s) - T* ||_F, r symmetric:
   //   (J^T r)_k = 2 sum_q r_kq s_q T0_kq,  (J^T J)_kl = 2 d_kl sum_q s_q^2 T0_kq^2 + 2 s_k s_l T0_kl^2
   std::vector<double> sv(P, 1.0), A(PP), b(P);
@@ -1381,9 +1454,8 @@ int thc_guess_targets(thc_ctx* ctx, const double* Th0, const double* Tstar, cons
     ctx->err = "shift target: normal matrix not positive definite";
     return THC_ESINGULAR;
   }
-  HIPCHK(hipMemcpyAsync(c, ch.data(), P * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(delta, dh.data(), P * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  RCHK(h2d(ctx, c, ch.data(), P * sizeof(double)));
+  RCHK(h2d(ctx, delta, dh.data(), P * sizeof(double)));
   return THC_OK;
 }
 
@@ -1418,16 +1490,16 @@ int thc_mlp_create(int64_t n_in, int64_t width, int64_t n_out, uint64_t seed, vo
     std::vector<float> zeros((size_t)std::max(n_in, n_out), 0.0f), ones((size_t)std::max(n_in, n_out), 1.0f);
     if (mlp_init(n_in, width, n_out, seed, ctx->p, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->m, 0, ctx->np * sizeof(float), ctx->stream) != hipSuccess ||
-        hipMemsetAsync(ctx->v, 0, ctx->np * sizeof(float), ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(ctx->mu_in, zeros.data(), n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(ctx->sd_in, ones.data(), n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(ctx->mu_out, zeros.data(), n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(ctx->sd_out, ones.data(), n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        hipMemsetAsync(ctx->v, 0, ctx->np * sizeof(float), ctx->stream) != hipSuccess)
       rc = THC_EDEVICE;
+    if (rc == THC_OK) rc = h2d(ctx, ctx->mu_in, zeros.data(), n_in * sizeof(float));
+    if (rc == THC_OK) rc = h2d(ctx, ctx->sd_in, ones.data(), n_in * sizeof(float));
+    if (rc == THC_OK) rc = h2d(ctx, ctx->mu_out, zeros.data(), n_out * sizeof(float));
+    if (rc == THC_OK) rc = h2d(ctx, ctx->sd_out, ones.data(), n_out * sizeof(float));
   }
   if (rc != THC_OK) {
     for (void* q : ctx->allocs) (void)hipFree(q);
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
     delete ctx;
     return rc;
   }
@@ -1441,11 +1513,10 @@ int thc_mlp_set_norm(thc_mlp* ctx, const float* mu_in, const float* sd_in, const
     if (!(sd_in[k] > 0.0f)) { ctx->err = "input scales must be positive"; return THC_EINVAL; }
   for (int64_t k = 0; k < ctx->n_out; ++k)
     if (!(sd_out[k] > 0.0f)) { ctx->err = "output scales must be positive"; return THC_EINVAL; }
-  HIPCHK(hipMemcpyAsync(ctx->mu_in, mu_in, ctx->n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(ctx->sd_in, sd_in, ctx->n_in * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(ctx->mu_out, mu_out, ctx->n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(ctx->sd_out, sd_out, ctx->n_out * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  RCHK(h2d(ctx, ctx->mu_in, mu_in, ctx->n_in * sizeof(float)));
+  RCHK(h2d(ctx, ctx->sd_in, sd_in, ctx->n_in * sizeof(float)));
+  RCHK(h2d(ctx, ctx->mu_out, mu_out, ctx->n_out * sizeof(float)));
+  RCHK(h2d(ctx, ctx->sd_out, sd_out, ctx->n_out * sizeof(float)));
   return THC_OK;
 }
 
@@ -1459,11 +1530,10 @@ int thc_mlp_fit_norm(thc_mlp* ctx, const float* X, const float* T, int64_t rows)
 
 int thc_mlp_get_norm(thc_mlp* ctx, float* mu_in, float* sd_in, float* mu_out, float* sd_out) {
   if (!ctx || !mu_in || !sd_in || !mu_out || !sd_out) return THC_EINVAL;
-  HIPCHK(hipMemcpyAsync(mu_in, ctx->mu_in, ctx->n_in * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(sd_in, ctx->sd_in, ctx->n_in * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(mu_out, ctx->mu_out, ctx->n_out * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(sd_out, ctx->sd_out, ctx->n_out * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  RCHK(d2h(ctx, mu_in, ctx->mu_in, ctx->n_in * sizeof(float)));
+  RCHK(d2h(ctx, sd_in, ctx->sd_in, ctx->n_in * sizeof(float)));
+  RCHK(d2h(ctx, mu_out, ctx->mu_out, ctx->n_out * sizeof(float)));
+  RCHK(d2h(ctx, sd_out, ctx->sd_out, ctx->n_out * sizeof(float)));
   return THC_OK;
 }
 
@@ -1504,8 +1574,7 @@ int thc_mlp_loss_grad(thc_mlp* ctx, const float* X, const float* T, int64_t rows
   RCHK(mlp_bwd(ctx, X, T, rows));
   if (grad) HIPCHK(hipMemcpyAsync(grad, ctx->g, ctx->np * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream));
   if (loss) {
-    HIPCHK(hipMemcpyAsync(loss, ctx->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    RCHK(d2h(ctx, loss, ctx->loss, sizeof(float)));
   }
   return THC_OK;
 }
@@ -1518,8 +1587,7 @@ int thc_mlp_train_step(thc_mlp* ctx, const float* X, const float* T, int64_t row
   HIPCHK(mlp_adam(ctx->np, ctx->p, ctx->g, ctx->m, ctx->v, lr, 0.9f, 0.999f, 1e-8f, ctx->step, ctx->stream));
   ctx->packed = false;
   if (loss) {
-    HIPCHK(hipMemcpyAsync(loss, ctx->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    RCHK(d2h(ctx, loss, ctx->loss, sizeof(float)));
   }
   return THC_OK;
 }
@@ -1546,6 +1614,7 @@ void thc_mlp_destroy(thc_mlp* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (void* q : ctx->acts) (void)hipFree(q);
   for (void* q : ctx->allocs) (void)hipFree(q);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
   delete ctx;
 }
 
@@ -1556,6 +1625,7 @@ void thc_destroy(thc_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (auto ev : ctx->pool) (void)hipEventDestroy(ev);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
   delete ctx;
 }
 

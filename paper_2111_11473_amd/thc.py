@@ -29,7 +29,7 @@ TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TER
 SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_history",
            "thc_history_precision",
            "thc_energy",
-           "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_profile", "thc_profile_get", "thc_dgemm",
+           "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
            "thc_last_error", "thc_destroy",
            "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
            "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
     lib.thc_profile.argtypes = [VP, C.c_int]
     lib.thc_profile_get.argtypes = [VP, C.c_char_p, C.POINTER(D), C.POINTER(I64)]
+    lib.thc_profile_flops.argtypes = [VP, C.POINTER(D), C.POINTER(D)]
     lib.thc_dgemm.argtypes = [C.c_int, C.c_int, I64, I64, I64, D, P, I64, I64, P, I64, I64, D, P, I64, I64, I64, VP]
     lib.thc_last_error.argtypes = [VP]
     lib.thc_last_error.restype = C.c_char_p
@@ -294,6 +295,12 @@ class THC:
     # -- profiling ----------------------------------------------------------------------
     def profile(self, enable=True):
         self._check(self.lib.thc_profile(self.ctx, int(enable)), "thc_profile")
+
+    def profile_flops(self):
+        """(FP64, FP32) MFMA GEMM flops issued since profile(True)."""
+        a, b = C.c_double(0.0), C.c_double(0.0)
+        self._check(self.lib.thc_profile_flops(self.ctx, C.byref(a), C.byref(b)), "thc_profile_flops")
+        return a.value, b.value
 
     def profile_get(self, name):
         ms = C.c_double(0.0)
