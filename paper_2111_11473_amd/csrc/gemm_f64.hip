@@ -10,7 +10,7 @@
 // walks K in steps of 16 through LDS.  Each wave owns a (BM/2) x (BN/2) sub-tile held as
 // (BM/32) x (BN/32) MFMA accumulators of 16x16 doubles.  The next K-slab is prefetched into
 // registers while the current one is multiplied.  Ragged M, N, K are handled by
-// zero-filled loads and masked stores, so no operand needs padding.
+// zero-filled LDS tiles and masked stores, so no operand needs padding.
 #include <type_traits>
 
 #include "internal.h"
@@ -23,19 +23,42 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BK = 16;
-constexpr int PAD = 1;  // odd LDS row pitch: conflict-free transposing stores
+__device__ const double kOne = 1.0;
+constexpr int RSRC_W3 = 0x00020000;  // raw 32-bit buffer access
+
+// A buffer of 2 GiB from base (uniform across the wave): byte offsets at or beyond 2^31 read
+// as zero.
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const double* base) {
+  const uint64_t a = (uint64_t)base;
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(hi << 32 | lo), (short)0, (int)0x80000000u, RSRC_W3);
+}
+__device__ inline double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0u, 0));
+}
 
 // F32: operands rounded to FP32 on their way into LDS, v_mfma_f32_16x16x4f32 with FP32
 // accumulation (the mixed-precision path); otherwise FP64 throughout.
-template <int BM, int BN, bool TA, bool TB, bool F32>
-__global__ __launch_bounds__(256) void dgemm_kernel(const Gemm g, const int64_t kchunk) {
+//
+// Loads are branch-free: an element outside the matrix is read from the tile origin (always
+// inside) and replaced by zero when it is written to LDS, and the k-indexed scaling is applied
+// there too, so the global loads of the next slab are all in flight while the current slab is
+// multiplied.  Two LDS buffers: one barrier per slab.  Per-thread offsets are 32-bit, relative
+// to a per-tile base pointer.
+template <int BM, int BN, bool TA, bool TB, bool F32, int OCC>
+__global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int64_t kchunk) {
   using TL = typename std::conditional<F32, float, double>::type;
   using ACC = typename std::conditional<F32, flt4, dbl4>::type;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TI = WM / 16, TJ = WN / 16;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
-  __shared__ TL As[BK][BM + PAD];
-  __shared__ TL Bs[BK][BN + PAD];
+  // LDS row pitch: an operand stored k-fastest is transposed on its way in (odd pitch: the 16
+  // k-rows a wave writes fall on distinct banks); one stored m- or n-fastest is copied row by
+  // row (pitch of 32 banks mod 64: consecutive k-rows on opposite halves of the banks)
+  constexpr int PA = BM + (TA ? 16 : 1), PB = BN + (TB ? 1 : 16);
+  __shared__ TL As[2][BK][PA];
+  __shared__ TL Bs[2][BK][PB];
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -47,56 +70,50 @@ __global__ __launch_bounds__(256) void dgemm_kernel(const Gemm g, const int64_t 
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = (kbeg + kchunk < g.K) ? kbeg + kchunk : g.K;
 
-  const double* __restrict__ A = g.A + b * g.sA;
-  const double* __restrict__ B = g.B + b * g.sB;
-  const double* __restrict__ sa = g.kscaleA ? g.kscaleA + b * g.sksA : nullptr;
-  const double* __restrict__ sb = g.kscaleB ? g.kscaleB + b * g.sksB : nullptr;
+  // tile origins (row m0 / column n0, k = 0)
+  const double* __restrict__ A = g.A + b * g.sA + (TA ? m0 : m0 * g.lda);
+  const double* __restrict__ B = g.B + b * g.sB + (TB ? n0 * g.ldb : n0);
+  // an absent k-scaling reads the constant 1 with stride 0, so the slab code has no branches
+  const double* __restrict__ sa = g.kscaleA ? g.kscaleA + b * g.sksA : &kOne;
+  const double* __restrict__ sb = g.kscaleB ? g.kscaleB + b * g.sksB : &kOne;
+  const int64_t ksa = g.kscaleA ? g.ksA : 0, ksb = g.kscaleB ? g.ksB : 0;
+  const uint32_t lda = (uint32_t)g.lda, ldb = (uint32_t)g.ldb;
+  const int mlim = (int)((g.M - m0 < BM) ? g.M - m0 : BM);  // rows / columns of this tile inside C
+  const int nlim = (int)((g.N - n0 < BN) ? g.N - n0 : BN);
 
-  double ra[NA], rb[NB];
+  // This thread's share of a slab: one k (ka, kb) and NA rows mm = ma + sma r of the A tile,
+  // NB columns nn = nb + snb r of the B tile; consecutive lanes read consecutive addresses.
+  const int ka = TA ? t >> 4 : t & 15, ma = TA ? t & 15 : t >> 4;
+  const int kb = TB ? t & 15 : t >> 4, nb = TB ? t >> 4 : t & 15;
+  constexpr int SMA = 16, SNB = 16;
+
+  // Operand elements come through buffer loads from the slab origin: an element outside the
+  // matrix gets an offset beyond the buffer's range, which the hardware reads as zero.
+  constexpr uint32_t OOB = 0x80000000u;
+  const uint32_t aoff = 8u * (TA ? (uint32_t)ka * lda + (uint32_t)ma : (uint32_t)ma * lda + (uint32_t)ka);
+  const uint32_t boff = 8u * (TB ? (uint32_t)nb * ldb + (uint32_t)kb : (uint32_t)kb * ldb + (uint32_t)nb);
+  const uint32_t astep = 8u * SMA * (TA ? 1u : lda), bstep = 8u * SNB * (TB ? ldb : 1u);
+
+  double ra[NA], rb[NB], rsa, rsb;
 
   auto load = [&](int64_t k0) {
+    const int kl = (int)(kend - k0);  // valid k within this slab: k < kl
+    const __amdgpu_buffer_rsrc_t rA = rsrc(A + (TA ? k0 * g.lda : k0));
+    const __amdgpu_buffer_rsrc_t rB = rsrc(B + (TB ? k0 : k0 * g.ldb));
 #pragma unroll
-    for (int r = 0; r < NA; ++r) {
-      int mm, kk;
-      if (TA) { mm = t % BM; kk = t / BM + (256 / BM) * r; }
-      else    { kk = t % BK; mm = t / BK + 16 * r; }
-      const int64_t m = m0 + mm, k = k0 + kk;
-      double x = 0.0;
-      if (m < g.M && k < kend) {
-        x = TA ? A[k * g.lda + m] : A[m * g.lda + k];
-        if (sa) x *= sa[k * g.ksA];
-      }
-      ra[r] = x;
-    }
+    for (int r = 0; r < NA; ++r)
+      ra[r] = bload(rA, (ka < kl && ma + SMA * r < mlim) ? aoff + astep * r : OOB);
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      int nn, kk;
-      if (TB) { kk = t % BK; nn = t / BK + 16 * r; }
-      else    { nn = t % BN; kk = t / BN + (256 / BN) * r; }
-      const int64_t n = n0 + nn, k = k0 + kk;
-      double x = 0.0;
-      if (n < g.N && k < kend) {
-        x = TB ? B[n * g.ldb + k] : B[k * g.ldb + n];
-        if (sb) x *= sb[k * g.ksB];
-      }
-      rb[r] = x;
-    }
+    for (int r = 0; r < NB; ++r)
+      rb[r] = bload(rB, (kb < kl && nb + SNB * r < nlim) ? boff + bstep * r : OOB);
+    rsa = sa[(k0 + (ka < kl ? ka : 0)) * ksa];
+    rsb = sb[(k0 + (kb < kl ? kb : 0)) * ksb];
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < NA; ++r) {
-      int mm, kk;
-      if (TA) { mm = t % BM; kk = t / BM + (256 / BM) * r; }
-      else    { kk = t % BK; mm = t / BK + 16 * r; }
-      As[kk][mm] = (TL)ra[r];
-    }
+    for (int r = 0; r < NA; ++r) As[buf][ka][ma + SMA * r] = (TL)(ra[r] * rsa);
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      int nn, kk;
-      if (TB) { kk = t % BK; nn = t / BK + 16 * r; }
-      else    { nn = t % BN; kk = t / BN + (256 / BN) * r; }
-      Bs[kk][nn] = (TL)rb[r];
-    }
+    for (int r = 0; r < NB; ++r) Bs[buf][kb][nb + SNB * r] = (TL)(rb[r] * rsb);
   };
 
   ACC acc[TI][TJ];
@@ -106,18 +123,14 @@ __global__ __launch_bounds__(256) void dgemm_kernel(const Gemm g, const int64_t 
     for (int j = 0; j < TJ; ++j) acc[i][j] = ACC{0, 0, 0, 0};
 
   const int lr = lane & 15, lk = lane >> 4;
-  if (kbeg < kend) load(kbeg);
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-    store();
-    __syncthreads();
-    if (k0 + BK < kend) load(k0 + BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       TL af[TI], bf[TJ];
 #pragma unroll
-      for (int i = 0; i < TI; ++i) af[i] = As[kk + lk][wm * WM + i * 16 + lr];
+      for (int i = 0; i < TI; ++i) af[i] = As[buf][kk + lk][wm * WM + i * 16 + lr];
 #pragma unroll
-      for (int j = 0; j < TJ; ++j) bf[j] = Bs[kk + lk][wn * WN + j * 16 + lr];
+      for (int j = 0; j < TJ; ++j) bf[j] = Bs[buf][kk + lk][wn * WN + j * 16 + lr];
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -127,8 +140,24 @@ __global__ __launch_bounds__(256) void dgemm_kernel(const Gemm g, const int64_t 
           else
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
+  };
+  const int nslab = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
+  if (nslab > 0) {
+    load(kbeg);
+    store(0);
   }
+  __syncthreads();
+  int buf = 0;
+  int64_t k0 = kbeg;
+  for (int sl = 1; sl < nslab; ++sl) {  // slab sl - 1 is multiplied while slab sl is fetched
+    load(k0 + BK);
+    compute(buf);
+    store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    k0 += BK;
+  }
+  if (nslab > 0) compute(buf);
 
   double* __restrict__ C = g.C ? g.C + b * g.sC + (int64_t)split * g.sSplit : nullptr;
   float* __restrict__ Cf = g.Cf ? g.Cf + b * g.sC + (int64_t)split * g.sSplit : nullptr;
@@ -158,12 +187,16 @@ __global__ __launch_bounds__(256) void dgemm_kernel(const Gemm g, const int64_t 
 
 template <int BM, int BN, bool F32>
 hipError_t launch_tile(const Gemm& g, int64_t kchunk, hipStream_t s) {
+  constexpr int OCC = 2;  // two workgroups per CU: one multiplies while the other loads
   dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
             (unsigned)(g.batch * g.ksplit));
-  if (!g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, false, F32>), grid, dim3(256), 0, s, g, kchunk);
-  else if (g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, false, F32>), grid, dim3(256), 0, s, g, kchunk);
-  else if (!g.transA && g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, true, F32>), grid, dim3(256), 0, s, g, kchunk);
-  else hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, true, F32>), grid, dim3(256), 0, s, g, kchunk);
+  // byte offsets within a slab stay below 2^31 (the buffer range)
+  const int64_t la = 8 * (BM + BK) * g.lda, lb = 8 * (BN + BK) * g.ldb;
+  if (la >= (int64_t(1) << 31) || lb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  if (!g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, false, F32, OCC>), grid, dim3(256), 0, s, g, kchunk);
+  else if (g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, false, F32, OCC>), grid, dim3(256), 0, s, g, kchunk);
+  else if (!g.transA && g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, true, F32, OCC>), grid, dim3(256), 0, s, g, kchunk);
+  else hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, true, F32, OCC>), grid, dim3(256), 0, s, g, kchunk);
   return hipGetLastError();
 }
 

@@ -367,8 +367,9 @@ int plan_and_alloc(thc_ctx* ctx) {
   int64_t nb = op.a_block > 0 ? op.a_block : std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(4.0e9 / (32.0 * P * P))));
   nb = std::min(nb, nL);
   ctx->nb = nb;
-  const int64_t t64 = ((P + 63) / 64) * ((P + 63) / 64);
-  ctx->KS = std::max<int64_t>(1, std::min<int64_t>(16, (1024 + t64 - 1) / t64));
+  // split of the N_L P-deep sum of Alg. 1: about 512 workgroups of 128 x 128 tiles (two per CU)
+  const int64_t t128 = ((P + 127) / 128) * ((P + 127) / 128);
+  ctx->KS = std::max<int64_t>(1, std::min<int64_t>(16, (512 + t128 - 1) / t128));
   // H block over X: whole rank when it fits in ~40 GB
   int64_t Xb = op.x_block;
   if (Xb <= 0) {

@@ -57,7 +57,10 @@ def _state(s, Z0, seed):
 
 @pytest.mark.parametrize("shape", [(1, 37, 53, 29, False, False), (3, 130, 70, 257, True, False),
                                    (2, 65, 200, 17, False, True), (1, 300, 129, 64, True, True),
-                                   (4, 16, 16, 16, False, False)])
+                                   (4, 16, 16, 16, False, False),
+                                   # enough tiles for the 128 x 128 kernel, ragged in M, N and K
+                                   (20, 517, 515, 131, False, False), (40, 300, 390, 77, True, True),
+                                   (32, 260, 600, 45, True, False), (32, 600, 260, 45, False, True)])
 def test_dgemm_matches_numpy(thc, shape):
     nb, M, N, K, tA, tB = shape
     _say("dgemm", shape)
