@@ -39,16 +39,17 @@ def _kernel_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(config_name):
+def _traffic(config_name, launches_per_residual):
     """HBM bytes per H-kernel launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source with the same launches per residual (grid points per
+    launch); else None."""
     p = os.path.join(ROOT, "profiles", f"h_kernel_{config_name}_traffic.json")
     try:
         with open(p) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_sha256_16") != _kernel_hash():
+    if d.get("kernel_sha256_16") != _kernel_hash() or d.get("launches_per_residual") != launches_per_residual:
         return None
     return d.get("bytes_per_launch")
 
@@ -247,7 +248,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"kernel": "h_kernel (three-way accumulation of Alg. 6, FP64 VALU, Y<->Z symmetric)", "bound": "alu",
                      "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": _traffic(cfg.name), "launches": h_n,
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": _traffic(cfg.name, launches_per_residual), "launches": h_n,
                      "avg_launch_ms": 1e3 * avg_launch_s, "algorithmic_flops_per_launch": flops_per_launch},
         "mfma": {"gemm_fp64": {"achieved": gf64 / max(g_per, 1e-12) / 1e12, "peak": PEAK_FP64_VALU_TFLOPS,
                                "unit": "TFLOP/s", "flops_per_residual": gf64},

@@ -24,6 +24,16 @@ namespace {
 
 constexpr int BK = 16;
 __device__ const double kOne = 1.0;
+
+// Position of C element (m, n) of one batch in the output layout of g.
+__device__ inline int64_t c_offset(const Gemm& g, int64_t m, int64_t n) {
+  if (g.cblk > 0)
+    return ((m >> 4) * (g.ldc / g.cblk) + n / g.cblk) * 16 * g.cblk + (m & 15) * g.cblk + n % g.cblk;
+  if (g.pair_rows)
+    return g.xtile ? ((((n >> 6) * g.ldc + (m >> 1)) << 6) + (n & 63)) * 2 + (m & 1)
+                   : ((m >> 1) * g.ldc + n) * 2 + (m & 1);
+  return m * g.ldc + n;
+}
 constexpr int RSRC_W3 = 0x00020000;  // raw 32-bit buffer access
 
 // A buffer of 2 GiB from base (uniform across the wave): byte offsets at or beyond 2^31 read
@@ -162,27 +172,56 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
   double* __restrict__ C = g.C ? g.C + b * g.sC + (int64_t)split * g.sSplit : nullptr;
   float* __restrict__ Cf = g.Cf ? g.Cf + b * g.sC + (int64_t)split * g.sSplit : nullptr;
   const double* __restrict__ H = g.hmul ? g.hmul + b * g.sH : nullptr;
+  const bool rd = C && g.beta != 0.0;
+  // Epilogue by blocks of 16 rows: every load (C for beta, the Hadamard factor) of a block is
+  // issued before its stores, so the loads overlap instead of waiting one by one behind stores
+  // to possibly the same addresses.  Output element r of a lane: FP64 MFMA row lk + 4 r, FP32
+  // MFMA row 4 lk + r; column lr.
 #pragma unroll
-  for (int i = 0; i < TI; ++i)
+  for (int i = 0; i < TI; ++i) {
+    int64_t off[TJ][4];
+    double x[TJ][4];
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // output element r of a lane: FP64 MFMA row lk + 4 r, FP32 MFMA row 4 lk + r; column lr
         const int64_t m = m0 + wm * WM + i * 16 + (F32 ? 4 * lk + r : lk + 4 * r);
         const int64_t n = n0 + wn * WN + j * 16 + lr;
-        if (m < g.M && n < g.N) {
-          double x = g.alpha * (double)acc[i][j][r];
-          if (H) x *= H[m * g.ldh + n];
-          const int64_t off = g.pair_rows ? ((m >> 1) * g.ldc + n) * 2 + (m & 1) : m * g.ldc + n;
-          if (Cf) {
-            Cf[off] = (float)x;  // FP32 output (beta is zero for it)
-          } else {
-            if (g.beta != 0.0) x += g.beta * C[off];
-            C[off] = x;
-          }
-        }
+        const bool ok = m < g.M && n < g.N;
+        off[j][r] = ok ? c_offset(g, m, n) : -1;
+        x[j][r] = g.alpha * (double)acc[i][j][r];
+        if (H && ok) x[j][r] *= H[m * g.ldh + n];
+        if (rd && ok) x[j][r] += g.beta * C[off[j][r]];
       }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (off[j][r] < 0) continue;
+        if (Cf) Cf[off[j][r]] = (float)x[j][r];  // FP32 output (beta is zero for it)
+        else C[off[j][r]] = x[j][r];
+      }
+  }
+}
+
+// C = alpha sum_s W_s (times the Hadamard factor) + beta C for a product computed as ksplit
+// partial products W_s (each batch x M x N, rows of N) in the workspace.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const Gemm g, const double* __restrict__ ws, int ns) {
+  const int64_t MN = g.M * g.N, total = g.batch * MN;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+    const int64_t b = idx / MN, r = idx - b * MN, m = r / g.N, n = r - m * g.N;
+    double x = 0.0;
+    for (int k = 0; k < ns; ++k) x += ws[k * total + idx];
+    x *= g.alpha;
+    if (g.hmul) x *= g.hmul[b * g.sH + m * g.ldh + n];
+    const int64_t off = b * g.sC + c_offset(g, m, n);
+    if (g.Cf) {
+      g.Cf[off] = (float)x;
+    } else {
+      if (g.beta != 0.0) x += g.beta * g.C[off];
+      g.C[off] = x;
+    }
+  }
 }
 
 template <int BM, int BN, bool F32>
@@ -205,19 +244,65 @@ hipError_t launch_tile(const Gemm& g, int64_t kchunk, hipStream_t s) {
 hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   Gemm g = g0;
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  // A batch that shares B and whose A, C (and Hadamard factor) blocks follow each other row by
+  // row is one product with batch * M rows: fold it, so that it gets the large tiles.
+  if (g.batch > 1 && g.sB == 0 && !g.transA && g.sA == g.M * g.lda && g.sC == g.M * g.ldc &&
+      (!g.kscaleA || g.sksA == 0) && (!g.kscaleB || g.sksB == 0) && (!g.hmul || g.sH == g.M * g.ldh) &&
+      (!g.pair_rows || g.M % 2 == 0) && !g.xtile && g.cblk == 0 && g.ksplit == 1) {
+    g.M *= g.batch;
+    g.batch = 1;
+    g.sA = g.sC = g.sH = 0;
+  }
+  // Batches interleaved row by row (row m of batch b at m * batch + b) fold the same way.
+  if (g.batch > 1 && g.sB == 0 && !g.transA && !g.pair_rows && g.cblk == 0 && g.ksplit == 1 && g.sA >= g.K &&
+      g.sC >= g.N &&
+      g.lda == g.batch * g.sA && g.ldc == g.batch * g.sC && (!g.kscaleA || g.sksA == 0) &&
+      (!g.kscaleB || g.sksB == 0) && (!g.hmul || (g.sH >= g.N && g.ldh == g.batch * g.sH))) {
+    g.M *= g.batch;
+    g.lda = g.sA;
+    g.ldc = g.sC;
+    if (g.hmul) g.ldh = g.sH;
+    g.batch = 1;
+    g.sA = g.sC = g.sH = 0;
+  }
   if (g.ksplit < 1) g.ksplit = 1;
-  if (g.batch * g.ksplit > 65535) return hipErrorInvalidValue;
   if (g.K <= 0) {
     // C = beta * C (or zero): run with an empty K range so the epilogue still applies.
     g.K = 0;
   }
+  if ((g.C == nullptr) == (g.Cf == nullptr)) return hipErrorInvalidValue;  // exactly one output
+  if ((g.xtile && !g.pair_rows) || g.cblk < 0 || (g.cblk > 0 && (g.pair_rows || g.ldc % g.cblk != 0)))
+    return hipErrorInvalidValue;
+  if (g.Cf && (g.beta != 0.0 || !g.f32)) return hipErrorInvalidValue;
+  // Few output tiles and a long K: split K over more workgroups (about three per CU), partial
+  // products in the workspace, then one reduction that applies the epilogue.
+  if (g.ksplit == 1 && g.ws && g.K >= 256) {
+    const int64_t t64 = ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+    if (t64 < 384) {
+      const int64_t ns = std::min<int64_t>(std::min<int64_t>(g.K / 128, (768 + t64 - 1) / t64), 32);
+      if (ns >= 2 && ns * g.batch * g.M * g.N <= g.ws_len && g.batch * ns <= 65535) {
+        Gemm h = g;
+        h.C = g.ws; h.ldc = g.N; h.sC = g.M * g.N; h.sSplit = g.batch * g.M * g.N;
+        h.alpha = 1.0; h.beta = 0.0; h.hmul = nullptr; h.pair_rows = false; h.xtile = false; h.cblk = 0;
+        h.Cf = nullptr;
+        h.ksplit = (int)ns; h.ws = nullptr;
+        hipError_t e = gemm_f64(h, s);
+        if (e != hipSuccess) return e;
+        const int64_t total = g.batch * g.M * g.N;
+        const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, s, g, (const double*)g.ws, (int)ns);
+        return hipGetLastError();
+      }
+    }
+  }
+  if (g.batch * g.ksplit > 65535) return hipErrorInvalidValue;
   int64_t kchunk = (g.K + g.ksplit - 1) / g.ksplit;
   kchunk = ((kchunk + BK - 1) / BK) * BK;
   if (kchunk == 0) kchunk = BK;
   const int64_t t128 = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch * g.ksplit;
-  if ((g.C == nullptr) == (g.Cf == nullptr)) return hipErrorInvalidValue;  // exactly one output
-  if (g.Cf && (g.beta != 0.0 || !g.f32)) return hipErrorInvalidValue;
-  const bool big = g.M >= 96 && g.N >= 96 && t128 >= 480;
+  // 128 x 128 tiles need enough of them and a K long enough to amortize their prologue and
+  // epilogue; short-K products run on 64 x 64 tiles, up to eight workgroups per CU
+  const bool big = g.M >= 96 && g.N >= 96 && t128 >= 480 && kchunk > 64;
   if (big && (g.M + 127) / 128 > 65535) return hipErrorInvalidValue;
   if (!big && (g.M + 63) / 64 > 65535) return hipErrorInvalidValue;
   if (g.f32) return big ? launch_tile<128, 128, true>(g, kchunk, s) : launch_tile<64, 64, true>(g, kchunk, s);

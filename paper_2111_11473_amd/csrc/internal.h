@@ -28,9 +28,18 @@ struct Gemm {
   int64_t batch = 1;
   int ksplit = 1; int64_t sSplit = 0;
   bool pair_rows = false;  // C element (m, n) at C[((m / 2) ldc + n) 2 + m % 2]: rows interleaved in pairs
+  // With pair_rows and xtile: columns cut into tiles of 64, each tile a [ldc][64][2] block of row
+  // pairs: C[(((n / 64) ldc + m / 2) 64 + n % 64) 2 + m % 2].
+  bool xtile = false;
+  // cblk > 0: C cut into 16 x cblk blocks, block-row-major, each block row-major:
+  // C[((m / 16) (ldc / cblk) + n / cblk) 16 cblk + (m % 16) cblk + n % cblk] (ldc % cblk == 0).
+  int cblk = 0;
   bool f32 = false;        // FP32 MFMA (operands rounded to FP32, FP32 accumulation)
   bool keep64 = false;     // stays FP64 in the mixed-precision path
   float* Cf = nullptr;     // FP32 output instead of C (requires f32 and beta = 0)
+  // Workspace for an automatic split of K (products with few output tiles and a long K); the
+  // partial products go here and a reduction applies the epilogue.  Optional.
+  double* ws = nullptr; int64_t ws_len = 0;
 };
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
@@ -104,17 +113,17 @@ hipError_t mlp_infer_bf16(int64_t rows, int64_t n_in, int64_t n_out, const float
                           const float* sd_out, float* Y, hipStream_t s);
 
 // VALU kernel for H^XYZ += sum_I (E^XY F^XZ + E^XZ F^XY) G^YZ (kernels_h.hip).
-// E, F: [I][Pp/2][ldx][2]; G: [I][Pp][ldg]; H: [Pp][Pp][Xb]; tiles from h_tiles(Pp, Xb, slots).
-// Padding of the operand rows: E, F rows of Xb + H_PAD_X (pair layout), G rows of Pp + H_PAD_G.
-// Measured on MI355X at Pp = Xb = 1024: unpadded rows run fastest (padding lowered the L2 hit rate).
-constexpr int64_t H_PAD_X = 0, H_PAD_G = 0;
-hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const double* E, const double* F,
+// E, F: [Xb/64][ldi][Pp/2][64][2] (X tile, grid point, row pair, X within the tile, row of the
+// pair); G: [I][Pp/16][Pp/8][16][8] (16 x 8 blocks); H: [Pp][Pp][Xb]; tiles from
+// h_tiles(Pp, Xb, slots).  ldi >= nI is the grid-point stride of one X tile of E and F.
+hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const double* E, const double* F,
                         const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
                         hipStream_t s);
 // The same with E, F stored in FP32 (mixed-precision path); arithmetic and H stay FP64.
-hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const float* E, const float* F,
+hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
                           const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
                           hipStream_t s);
+constexpr int H_GBLK = 8;  // column width of the G blocks
 std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots);
 int64_t h_slots_per_xcd();
 

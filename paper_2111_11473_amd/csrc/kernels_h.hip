@@ -15,21 +15,28 @@
 //
 // Operand staging.  E and F are stored with pairs of rows interleaved ([Y/2][X][2]), so one
 // 16-byte LDS read gives a lane both rows of a pair at its X (16-byte reads have about twice the
-// LDS bandwidth of 8-byte ones).  Per I the workgroup's rows -- E^XY, F^XY for its 16 Y, E^XZ,
-// F^XZ for its Z slice (64 X each, 1 KB per row pair, contiguous in HBM) -- and its two G blocks
-// are copied by buffer loads straight into LDS, NS stages deep (NS - 1 values of I in flight),
-// and each wave waits only for its own copies of the next stage before the barrier.  The only
-// factor that is uniform across the lanes, G, is held 16 values to a VGPR pair (lane l holds
-// value l % 16) and broadcast into the FMA by the DPP row_newbcast source modifier, so the
-// inner loop has no scalar loads.
+// LDS bandwidth of 8-byte ones).  They are stored X tile by X tile and grid point by grid point
+// ([X/64][I][Y/2][64][2]): a tile's row pairs at one I are contiguous 1 KB pieces of one block,
+// and consecutive I are adjacent.  G is stored in 16 x 8 blocks, so a tile's G^YZ is one
+// contiguous 1 KB block and its G^ZY two 512-byte pieces.  Per I the workgroup's rows -- E^XY,
+// F^XY for its 16 Y, E^XZ, F^XZ for its Z slice -- and its two G blocks are copied by buffer
+// loads straight into LDS, NS stages deep (NS - 1 values of I in flight), and each wave waits
+// only for its own copies of the next stage before the barrier.  The only factor that is
+// uniform across the lanes, G, is held 16 values to a VGPR pair (lane l holds value l % 16) and
+// broadcast into the FMA by the DPP row_newbcast source modifier, so the inner loop has no
+// scalar loads.
 // Tile order comes from a host-built table: runs of `slots` tiles (the workgroups resident on one
 // XCD) that share an X tile, 4 Y blocks and 8 Z blocks are placed at workgroup ids b with
 // b % 8 = that XCD, so tiles sharing operand rows run on one XCD at about the same time and share
-// them through its L2.  One workgroup per tile measured faster than a persistent grid walking the
-// table (co-started tiles request the same lines at once).
+// them through its L2.  The table is launched one generation (8 runs, every slot of the device)
+// at a time, so the workgroups of a run start together and cannot drift apart by more than one
+// tile's lifetime; consecutive generations walk the grid points in opposite directions, so a
+// generation starts on the points its predecessor read last (still in the last-level cache).
+// One workgroup per tile measured faster than a persistent grid walking the table.
 // Layouts (ranks zero-padded to Pp, a multiple of 64; X restricted to a block of Xb ranks, a
-// multiple of 64): E, F: [I][Pp/2][Xb][2] (E_I^XY at [I][Y/2][X][Y%2]); G: [I][Pp][Pp];
-// H: [Pp][Pp][Xb] (H^XYZ at [Y][Z][X]).
+// multiple of 64): E, F: [Xb/64][ldi][Pp/2][64][2] (E_I^XY at [X/64][I][Y/2][X%64][Y%2]);
+// G: [I][Pp/16][Pp/8][16][8] (G_I^YZ at [I][Y/16][Z/8][Y%16][Z%8]); H: [Pp][Pp][Xb] (H^XYZ at
+// [Y][Z][X]).
 #include <vector>
 
 #include "internal.h"
@@ -66,6 +73,7 @@ struct Geo {
   static_assert(CH_ROWS % NW == 0 && (BY / 2) % PPC == 0 && (BZ / 2) % PPC == 0, "row chunks split evenly");
   static_assert(2 * CH_G <= NW && (BY * BZ * 8) % 1024 == 0, "one round of G chunks");
   static_assert(NS >= 2 && NS * STAGE_B <= 160 * 1024, "stages must fit in LDS");
+  static_assert(BZ == H_GBLK, "a Z slice is one column block of G");
 };
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -147,12 +155,13 @@ __device__ inline void h_row(double (&acc)[WZ], double (&accm)[WZ], double ey, d
 static_assert(WZ == 4 && WY == 8, "h_row covers four Z; a patch is eight rows");
 
 template <int NWZ, int NS, typename TE>
-__global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp, int Xb, int ldx, int ldg, int64_t nI,
+__global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp, int Xb, int64_t ldi, int64_t nI,
                                                                        const TE* __restrict__ E,
                                                                        const TE* __restrict__ F,
                                                                        const double* __restrict__ G,
                                                                        double* __restrict__ H,
-                                                                       const uint32_t* __restrict__ tiles) {
+                                                                       const uint32_t* __restrict__ tiles,
+                                                                       int rev) {
   using C = Geo<NWZ, NS, TE>;
   __shared__ __attribute__((aligned(16))) char lds[NS * C::STAGE_B];
   const uint32_t tile = tiles[blockIdx.x];
@@ -203,22 +212,32 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
   // DMA plan of one stage: chunk c (1 KB) lands at stage + 1 KB c; wave w issues chunks w + NW q.
   // Row chunks first: chunk c holds PPC consecutive stage pairs starting at c PPC (E^Y, F^Y, E^Z,
   // F^Z in that order; lanes 64/PPC apart take consecutive pairs), then one round of FP64 G chunks,
-  // c = CH_ROWS + w: G^YZ (CH_G chunks of 128 / BZ rows of BZ) and, off the diagonal, G^ZY (CH_G
-  // chunks of 8 rows of 16).
+  // c = CH_ROWS + w: G^YZ (the tile's 16 x 8 block, CH_G chunks) and, off the diagonal, G^ZY
+  // (rows z0.. z0+7, columns y0.. y0+15: halves of two blocks, 8 rows of 16 per chunk).
   constexpr int LPP = 64 / C::PPC;                                    // lanes per row pair
-  const unsigned pstride = (unsigned)ldx * 2u * C::ESZ;               // bytes between row pairs
-  const unsigned voff_r = (unsigned)(lane / LPP) * pstride + (unsigned)(lane % LPP) * 16u;
+  const unsigned voff_r = (unsigned)(lane / LPP) * C::PAIR_B + (unsigned)(lane % LPP) * 16u;
   const bool g_yz = w < C::CH_G, g_zy = !g_yz && w < 2 * C::CH_G && mirror;
   const int gs = g_yz ? w : w - C::CH_G;
-  const unsigned voff_g = g_yz ? ((unsigned)(lane / (C::BZ / 2)) * (unsigned)ldg + 2u * (lane % (C::BZ / 2))) * 8u
-                               : ((unsigned)(lane / (BY / 2)) * (unsigned)ldg + 2u * (lane % (BY / 2))) * 8u;
-  const unsigned so_g = g_yz ? ((unsigned)(y0 + gs * (128 / C::BZ)) * (unsigned)ldg + (unsigned)z0) * 8u
-                             : ((unsigned)(z0 + gs * (128 / BY)) * (unsigned)ldg + (unsigned)y0) * 8u;
+  constexpr unsigned GBLK_B = 16u * C::BZ * 8u;                       // bytes of one G block
+  const unsigned nbz = (unsigned)Pp / C::BZ;                          // G blocks per block row
+  unsigned voff_g, so_g;
+  if (g_yz) {
+    voff_g = (unsigned)gs * 1024u + (unsigned)lane * 16u;
+    so_g = ((unsigned)Yb * nbz + (unsigned)(z0 / C::BZ)) * GBLK_B;
+  } else {
+    const int r = gs * 8 + lane / 8, col = 2 * (lane % 8);  // destination row (Z) and column (Y)
+    voff_g = (unsigned)(col / C::BZ) * GBLK_B + ((unsigned)(zs * C::BZ + r) * C::BZ + (unsigned)(col % C::BZ)) * 8u;
+    so_g = ((unsigned)Zb * nbz + (unsigned)(y0 / C::BZ)) * GBLK_B;
+  }
   const bool extra = g_yz || g_zy;  // this wave copies QROWS + extra chunks per stage
-  const int64_t PX = (int64_t)Pp * ldx, PP = (int64_t)Pp * ldg;  // per-I strides of E, F and of G
+  const int64_t PX = (int64_t)Pp * LANES;  // elements of E, F per (X tile, I)
+  const int64_t PP = (int64_t)Pp * Pp;     // elements of G per I
+  const TE* __restrict__ Et = E + (int64_t)xt * ldi * PX;
+  const TE* __restrict__ Ft = F + (int64_t)xt * ldi * PX;
   auto stage_in = [&](int64_t I, int buf) {
-    const __amdgpu_buffer_rsrc_t re = rsrc(E + I * PX, PX * C::ESZ);
-    const __amdgpu_buffer_rsrc_t rf = rsrc(F + I * PX, PX * C::ESZ);
+    if (rev) I = nI - 1 - I;  // this generation walks the grid points backwards
+    const __amdgpu_buffer_rsrc_t re = rsrc(Et + I * PX, PX * C::ESZ);
+    const __amdgpu_buffer_rsrc_t rf = rsrc(Ft + I * PX, PX * C::ESZ);
     char* sb = lds + buf * C::STAGE_B;
 #pragma unroll
     for (int q = 0; q < C::QROWS; ++q) {
@@ -227,7 +246,7 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
       const bool isF = (sp >= C::FY && sp < C::EZ) || sp >= C::FZ;
       const int pair = sp < C::FY ? y0 / 2 + sp : sp < C::EZ ? y0 / 2 + sp - C::FY
                                                 : sp < C::FZ ? z0 / 2 + sp - C::EZ : z0 / 2 + sp - C::FZ;
-      bload_lds(isF ? rf : re, sb + c * 1024, voff_r, (unsigned)pair * pstride + (unsigned)X0 * 2u * C::ESZ);
+      bload_lds(isF ? rf : re, sb + c * 1024, voff_r, (unsigned)pair * C::PAIR_B);
     }
     if (extra) bload_lds(rsrc(G + I * PP, PP * 8), sb + C::G_B + w * 1024, voff_g, so_g);
   };
@@ -327,14 +346,22 @@ std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb, int64_t slots) {
 }
 
 template <int NWZ, int NS, typename TE>
-hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const TE* E, const TE* F,
+hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const TE* E, const TE* F,
                   const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots, hipStream_t s) {
   if (Pp % 64 != 0 || Pp > 8192 || Xb % LANES != 0 || Xb > Pp || Xb <= 0 || ntiles <= 0 || ntiles > 2147483647LL ||
-      nI < 0 || slots < 1 || ntiles % (8 * slots) != 0 || ldx < Xb || ldx > 2 * Pp || ldg < Pp || ldg > 2 * Pp)
+      nI < 0 || ldi < nI || slots < 1 || ntiles % (8 * slots) != 0)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL((h_kernel<NWZ, NS, TE>), dim3((unsigned)ntiles), dim3(Geo<NWZ, NS, TE>::NTHREADS), 0, s,
-                     (int)Pp, (int)Xb, (int)ldx, (int)ldg, nI, E, F, G, H, tiles);
-  return hipGetLastError();
+  // One launch per generation of 8 slots tiles (every workgroup resident at once): the runs of
+  // a generation start together, so the workgroups sharing operand rows through an L2 stay
+  // within one tile's lifetime of each other.
+  const int64_t gen = 8 * slots;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += gen) {
+    hipLaunchKernelGGL((h_kernel<NWZ, NS, TE>), dim3((unsigned)gen), dim3(Geo<NWZ, NS, TE>::NTHREADS), 0, s,
+                       (int)Pp, (int)Xb, ldi, nI, E, F, G, H, tiles + t0, (int)((t0 / gen) & 1));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 constexpr int H_NWZ = 2, H_NS = 3;    // 4 waves, 26 KB stages, three stages (two workgroups per CU)
@@ -359,16 +386,16 @@ int64_t h_slots_per_xcd() {
 // EMPTY.
 std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots) { return tiles_for<H_NWZ>(Pp, Xb, slots); }
 
-hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const double* E, const double* F,
+hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const double* E, const double* F,
                         const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
                         hipStream_t s) {
-  return launch<H_NWZ, H_NS, double>(Pp, Xb, ldx, ldg, nI, E, F, G, H, tiles, ntiles, slots, s);
+  return launch<H_NWZ, H_NS, double>(Pp, Xb, ldi, nI, E, F, G, H, tiles, ntiles, slots, s);
 }
 
-hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldx, int64_t ldg, int64_t nI, const float* E, const float* F,
+hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
                           const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
                           hipStream_t s) {
-  return launch<H_NWZ, H_NS32, float>(Pp, Xb, ldx, ldg, nI, E, F, G, H, tiles, ntiles, slots, s);
+  return launch<H_NWZ, H_NS32, float>(Pp, Xb, ldi, nI, E, F, G, H, tiles, ntiles, slots, s);
 }
 
 }  // namespace thc

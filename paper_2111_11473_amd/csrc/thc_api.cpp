@@ -23,9 +23,12 @@ using namespace thc;
 
 namespace {
 
+constexpr int64_t GEMM_WS = int64_t(1) << 22;  // 32 MB
+
 struct ProfRec {
   std::string name;
   hipEvent_t a, b;
+  int64_t launches;  // kernel dispatches between a and b
 };
 
 struct Buf {
@@ -87,11 +90,11 @@ struct thc_ctx {
   bool has_shift = false;
   uint32_t* htiles = nullptr;  // H-kernel tile table
   int64_t nhtiles = 0, hslots = 0;
-  int64_t ldx = 0, ldg = 0;    // padded row lengths of the H-kernel operands (E, F, C6, D6 and G)
   double *R1 = nullptr, *I6 = nullptr;
   // Alg. 7
   double *U7 = nullptr, *S7 = nullptr, *R7 = nullptr, *Rx = nullptr, *Sx = nullptr, *Cx = nullptr, *Dx = nullptr;
   double *F7 = nullptr, *Gt = nullptr, *Gts = nullptr, *G7 = nullptr, *G7s = nullptr;
+  double* gws = nullptr;  // split-K workspace of the GEMMs (GEMM_WS doubles)
 
   // per-iteration history of the last thc_iterate call
   std::vector<double> hist_e, hist_r, hist_t;
@@ -183,6 +186,7 @@ struct Scope {
   thc_ctx* ctx;
   hipEvent_t a = nullptr;
   const char* name;
+  int64_t launches = 1;
   Scope(thc_ctx* c, const char* nm) : ctx(c), name(nm) {
     if (ctx->prof) {
       a = next_event(ctx);
@@ -194,7 +198,7 @@ struct Scope {
       hipEvent_t b = next_event(ctx);
       if (b) {
         (void)hipEventRecord(b, ctx->stream);
-        ctx->recs.push_back({name, a, b});
+        ctx->recs.push_back({name, a, b, launches});
       }
     }
   }
@@ -203,6 +207,8 @@ struct Scope {
 int gemm(thc_ctx* ctx, const Gemm& g0) {
   Scope sc(ctx, "gemm");
   Gemm g = g0;
+  g.ws = ctx->gws;
+  g.ws_len = ctx->gws ? GEMM_WS : 0;
   if (ctx->mixed && !g.keep64) g.f32 = true;
   if (ctx->prof && g.K > 0) (g.f32 ? ctx->gemm_flops32 : ctx->gemm_flops) += 2.0 * g.M * g.N * g.K * g.batch;
   if (ctx->prof && ctx->section) {
@@ -378,12 +384,6 @@ int plan_and_alloc(thc_ctx* ctx) {
   }
   if (Xb % 64 != 0 || Xb > Pp) { ctx->err = "x_block must be a multiple of 64 and <= padded rank"; return THC_EINVAL; }
   ctx->Xb = Xb;
-  ctx->ldx = Xb + H_PAD_X;
-  ctx->ldg = Pp + H_PAD_G;
-  const int64_t ldx = ctx->ldx, ldg = ctx->ldg;
-  int64_t Ic = op.i_chunk;
-  if (Ic <= 0) Ic = std::max<int64_t>(1, (int64_t)(8.0e9 / (8.0 * (2.0 * (Xb + H_PAD_X) * Pp + (double)Pp * (Pp + H_PAD_G)))));
-  ctx->Ic = std::min(Ic, Q);
   int64_t Xc = op.x_chunk;
   if (Xc <= 0) Xc = std::max<int64_t>(1, (int64_t)(2.0e9 / (8.0 * (double)Q * Q)));
   ctx->Xc = std::min(Xc, P);
@@ -391,7 +391,8 @@ int plan_and_alloc(thc_ctx* ctx) {
 
   struct A { double** p; size_t n; };
   const int64_t dm = ctx->opt.diis_max;
-  std::vector<A> list = {
+  ctx->Ic = 0;  // the chunk-sized entries are sized below, from what the rest leaves free
+  auto make_list = [&]() -> std::vector<A> { return {
       {&ctx->Loo, (size_t)(nL * o * o)}, {&ctx->Lov, (size_t)(nL * ov)}, {&ctx->Lvv, (size_t)(nL * v * v)},
       {&ctx->eps, (size_t)n}, {&ctx->Yo, (size_t)(o * P)}, {&ctx->Yv, (size_t)(v * P)},
       {&ctx->xo, (size_t)(o * Q)}, {&ctx->xv, (size_t)(v * Q)}, {&ctx->Go, (size_t)PP}, {&ctx->Gv, (size_t)PP},
@@ -419,23 +420,42 @@ int plan_and_alloc(thc_ctx* ctx) {
       {&ctx->tmpvP, (size_t)(v * P)}, {&ctx->Fxoo, (size_t)(o * o)}, {&ctx->Fxvv, (size_t)(v * v)},
       {&ctx->Tf, (size_t)P}, {&ctx->fd, (size_t)P},
       // Alg. 6
-      {&ctx->C6, (size_t)(o * ldx * Pp)}, {&ctx->D6, (size_t)(v * ldx * Pp)}, {&ctx->Ec, (size_t)(ctx->Ic * ldx * Pp)},
-      {&ctx->Fc, (size_t)(ctx->Ic * ldx * Pp)}, {&ctx->Gc, (size_t)(ctx->Ic * Pp * ldg)}, {&ctx->GYc, (size_t)(ctx->Ic * o * P)},
+      {&ctx->C6, (size_t)(o * Xb * Pp)}, {&ctx->D6, (size_t)(v * Xb * Pp)}, {&ctx->Ec, (size_t)(ctx->Ic * Xb * Pp)},
+      {&ctx->Fc, (size_t)(ctx->Ic * Xb * Pp)}, {&ctx->Gc, (size_t)(ctx->Ic * Pp * Pp)}, {&ctx->GYc, (size_t)(ctx->Ic * o * P)},
       {&ctx->Hb, (size_t)(Xb * Pp * Pp)}, {&ctx->R1, (size_t)(Xb * Pp * o)}, {&ctx->I6, (size_t)(Xb * ov)},
       // Alg. 7
       {&ctx->U7, (size_t)(P * o * P)}, {&ctx->S7, (size_t)(P * ov)}, {&ctx->R7, (size_t)(P * ov)},
       {&ctx->Rx, (size_t)(P * o * Q)}, {&ctx->Sx, (size_t)(P * o * Q)}, {&ctx->Cx, (size_t)(P * Q)}, {&ctx->Dx, (size_t)(P * Q)},
       {&ctx->F7, (size_t)(exch_supported(o) && !(op.flags & THC_FLAG_UNFUSED_EXCHANGE) ? 1 : ctx->Xc * Q * Q)}, {&ctx->Gt, (size_t)(P * o * Q)}, {&ctx->Gts, (size_t)(P * o * Q)},
       {&ctx->G7, (size_t)(P * ov)}, {&ctx->G7s, (size_t)(P * ov)},
-  };
+      {&ctx->gws, (size_t)GEMM_WS},
+  }; };
+  // Grid-point chunk of the H accumulation (E, F, G for Ic points): every chunk reads and
+  // writes the whole H block once, so chunks are large -- up to 16 GB, and at most half of the
+  // device memory the rest of the plan leaves free.  (Measured at the fp64 size, with the
+  // H-kernel launched one generation at a time: 367 ms per residual at 318 points per chunk,
+  // 356 at 636, 361 at 1250.)
+  int64_t Ic = op.i_chunk;
+  if (Ic <= 0) {
+    double fixed = 0.0;
+    for (auto& a : make_list()) fixed += 8.0 * (double)a.n;
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) { ctx->err = "hipMemGetInfo failed"; return THC_EDEVICE; }
+    const double per_i = 8.0 * (2.0 * (double)Xb * Pp + (double)Pp * Pp + (double)o * P) +
+                         (op.precision == 1 ? 4.0 * 2.0 * (double)Xb * Pp : 0.0);
+    const double budget = std::min(16.0e9, std::max(2.0e9, 0.5 * ((double)freeb - fixed)));
+    Ic = std::max<int64_t>(1, (int64_t)(budget / per_i));
+  }
+  ctx->Ic = std::min(Ic, Q);
+  const std::vector<A> list = make_list();
   for (auto& a : list) RCHK(alloc(ctx, a.p, a.n));
   // zero-padded operands of the H-kernel: padding must stay zero
-  RCHK(zero(ctx, ctx->C6, o * ldx * Pp));
-  RCHK(zero(ctx, ctx->D6, v * ldx * Pp));
-  RCHK(zero(ctx, ctx->Gc, ctx->Ic * Pp * ldg));
+  RCHK(zero(ctx, ctx->C6, o * Xb * Pp));
+  RCHK(zero(ctx, ctx->D6, v * Xb * Pp));
+  RCHK(zero(ctx, ctx->Gc, ctx->Ic * Pp * Pp));
   RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
-  RCHK(zero(ctx, ctx->Ec, ctx->Ic * ldx * Pp));
-  RCHK(zero(ctx, ctx->Fc, ctx->Ic * ldx * Pp));
+  RCHK(zero(ctx, ctx->Ec, ctx->Ic * Xb * Pp));
+  RCHK(zero(ctx, ctx->Fc, ctx->Ic * Xb * Pp));
   {
     ctx->hslots = h_slots_per_xcd();
     if (ctx->hslots < 1) { ctx->err = "cannot query the device for the H-kernel launch"; return THC_EDEVICE; }
@@ -447,7 +467,7 @@ int plan_and_alloc(thc_ctx* ctx) {
     RCHK(h2d(ctx, ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t)));
   }
   if (op.precision == 1) {  // FP32 E, F for the mixed-precision H-kernel
-    const int64_t nf = ctx->Ic * ldx * Pp;
+    const int64_t nf = ctx->Ic * Xb * Pp;
     double *e32 = nullptr, *f32 = nullptr;
     RCHK(alloc(ctx, &e32, (size_t)((nf + 1) / 2)));
     RCHK(alloc(ctx, &f32, (size_t)((nf + 1) / 2)));
@@ -659,25 +679,27 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   // ---------------- Alg. 6: quartic T2^2 ladder + exchange (Eq. 32 + 33) ----------------------
   ctx->section = "gemm@alg6";
   if (mask & THC_TERM_EQ32) {
-    const int64_t Xb = ctx->Xb, ldx = ctx->ldx;
+    const int64_t Xb = ctx->Xb, nX = Xb / 64;
     for (int64_t X0 = 0; X0 < P; X0 += Xb) {
       const int64_t xb = std::min(Xb, P - X0);
       // C6[i][Y][x] = sum_W T[W][Y] y_i^W Gv[X][W];  D6[a][Y][x] = sum_W T[W][Y] y_a^W Go[X][W]
-      // stored [Y/2][x][Y%2] (X fastest, row pairs interleaved: the H-kernel's operand layout)
+      // stored [x/64][Y/2][x%64][Y%2] (X tiles of 64, row pairs interleaved: the H-kernel's layout)
       {
-        Gemm g = batched(mk(P, xb, P, T, P, true, ctx->Gv + X0 * P, P, true, ctx->C6, ldx), o, 0, 0, ldx * Pp);
-        g.kscaleA = Yo; g.ksA = 1; g.sksA = P; g.pair_rows = true;
+        Gemm g = batched(mk(P, xb, P, T, P, true, ctx->Gv + X0 * P, P, true, ctx->C6, Pp / 2), o, 0, 0, Xb * Pp);
+        g.kscaleA = Yo; g.ksA = 1; g.sksA = P; g.pair_rows = true; g.xtile = true;
         RCHK(gemm(ctx, g));
-        Gemm h = batched(mk(P, xb, P, T, P, true, ctx->Go + X0 * P, P, true, ctx->D6, ldx), v, 0, 0, ldx * Pp);
-        h.kscaleA = Yv; h.ksA = 1; h.sksA = P; h.pair_rows = true;
+        Gemm h = batched(mk(P, xb, P, T, P, true, ctx->Go + X0 * P, P, true, ctx->D6, Pp / 2), v, 0, 0, Xb * Pp);
+        h.kscaleA = Yv; h.ksA = 1; h.sksA = P; h.pair_rows = true; h.xtile = true;
         RCHK(gemm(ctx, h));
       }
       for (int64_t I0 = 0; I0 < Q; I0 += ctx->Ic) {
         const int64_t ic = std::min(ctx->Ic, Q - I0);
-        // E_I = sum_i x_i^I C6[i];  F_I = sum_a x_a^I D6[a]  (elementwise in the [Y/2][x][2] layout)
+        // E_I = sum_i x_i^I C6[i];  F_I = sum_a x_a^I D6[a], one product per X tile, stored
+        // [x/64][I][Y/2][x%64][Y%2] (a tile's rows for consecutive I are adjacent)
         {
-          Gemm ge = mk(ic, ldx * Pp, o, xo + I0, Q, true, ctx->C6, ldx * Pp, false, ctx->Ec, ldx * Pp);
-          Gemm gf = mk(ic, ldx * Pp, v, xv + I0, Q, true, ctx->D6, ldx * Pp, false, ctx->Fc, ldx * Pp);
+          const int64_t tb = Pp * 64;  // elements of one X tile of C6[i], D6[a], E_I, F_I
+          Gemm ge = batched(mk(ic, tb, o, xo + I0, Q, true, ctx->C6, Xb * Pp, false, ctx->Ec, tb), nX, 0, tb, ctx->Ic * tb);
+          Gemm gf = batched(mk(ic, tb, v, xv + I0, Q, true, ctx->D6, Xb * Pp, false, ctx->Fc, tb), nX, 0, tb, ctx->Ic * tb);
           if (ctx->mixed) {  // FP32 operands for the H-kernel
             ge.C = nullptr; ge.Cf = ctx->Ec32;
             gf.C = nullptr; gf.Cf = ctx->Fc32;
@@ -685,17 +707,21 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
           RCHK(gemm(ctx, ge));
           RCHK(gemm(ctx, gf));
         }
-        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6)
+        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6), stored in 16 x H_GBLK blocks
         RCHK(gemm(ctx, mk(ic * o, P, v, ctx->Bq + I0 * ov, v, false, Yv, P, false, ctx->GYc, P)));
-        RCHK(gemm(ctx, batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, ctx->ldg), ic, 0, o * P,
-                               Pp * ctx->ldg)));
+        {
+          Gemm gg = batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, Pp), ic, 0, o * P, Pp * Pp);
+          gg.cblk = H_GBLK;
+          RCHK(gemm(ctx, gg));
+        }
         {
           Scope sc(ctx, "h_kernel");
+          sc.launches = ctx->nhtiles / (8 * ctx->hslots);  // one dispatch per generation of tiles
           if (ctx->mixed)
-            HIPCHK(h_accumulate32(Pp, Xb, ctx->ldx, ctx->ldg, ic, ctx->Ec32, ctx->Fc32, ctx->Gc, ctx->Hb, ctx->htiles,
+            HIPCHK(h_accumulate32(Pp, Xb, ctx->Ic, ic, ctx->Ec32, ctx->Fc32, ctx->Gc, ctx->Hb, ctx->htiles,
                                   ctx->nhtiles, ctx->hslots, s));
           else
-            HIPCHK(h_accumulate(Pp, Xb, ctx->ldx, ctx->ldg, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles,
+            HIPCHK(h_accumulate(Pp, Xb, ctx->Ic, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles,
                                 ctx->nhtiles, ctx->hslots, s));
         }
       }
@@ -1327,7 +1353,7 @@ int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* l
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
     tot += ms;
-    ++cnt;
+    cnt += r.launches;
   }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = cnt;

@@ -74,6 +74,21 @@ def test_dgemm_matches_numpy(thc, shape):
     assert np.abs(_host(Cd) - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("shape", [(6, 50, 300, 70), (64, 50, 1000, 45), (3, 7, 129, 33)])
+def test_dgemm_shared_B(thc, shape):
+    """A batch sharing one B (batch stride 0) is folded into a single product of batch * M rows."""
+    nb, M, N, K = shape
+    _say("dgemm shared B", shape)
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((nb, M, K))
+    B = rng.standard_normal((1, K, N))
+    C0 = rng.standard_normal((nb, M, N))
+    Cd = _dev(C0.copy())
+    thc.dgemm(_dev(A), _dev(B), Cd, alpha=1.3, beta=0.5)
+    ref = 1.3 * np.matmul(A, B) + 0.5 * C0
+    assert np.abs(_host(Cd) - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
 @pytest.mark.parametrize("name", ["small", "tiny"])
 def test_mp2_guess_and_energy(thc, name):
     cfg = synth.CONFIGS[name]
