@@ -11,6 +11,9 @@
 // B element of k-step r (row lane/16, column lane % 16 of rows 4 r .. 4 r + 3).  The o x 16
 // slices of Rx^X and xo and the 64 x 16 slice of z for the next J block are prefetched into
 // registers while the current one is used from LDS.
+// The slices are fetched with buffer loads whose out-of-range lanes read zero (k >= o, J >= Q,
+// I >= Q), so the padded k-steps multiply zeros and the loop has no branches; two LDS buffers, one
+// barrier per J block.
 // Layouts (row-major): xo [o][Q]; z [Q][Q]; Rx, Gt [X][o][Q].  Requires o <= 16 OB.
 #include "internal.h"
 
@@ -20,18 +23,31 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BI = 64, BJ = 16, NT = 256;
+constexpr int RSRC_W3 = 0x00020000;  // raw 32-bit buffer access
+constexpr uint32_t OOB = 0x80000000u;
+
+// A buffer of 2 GiB from base (uniform across the wave): offsets at or beyond 2^31 read as zero.
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const double* base) {
+  const uint64_t a = (uint64_t)base;
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(hi << 32 | lo), (short)0, (int)OOB, RSRC_W3);
+}
+__device__ inline double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0u, 0));
+}
 
 template <int OB>
-__global__ __launch_bounds__(NT) void exch_kernel(int64_t o, int64_t Q, const double* __restrict__ xo,
+__global__ __launch_bounds__(NT, 3) void exch_kernel(int64_t o, int64_t Q, const double* __restrict__ xo,
                                                   const double* __restrict__ z, const double* __restrict__ Rx,
                                                   double* __restrict__ Gt) {
   constexpr int OP = 16 * OB;             // padded o
   constexpr int NRX = (OP * BJ) / NT;     // Rx / xo slice elements per thread
   constexpr int NZ = (BI * BJ) / NT;      // z slice elements per thread
   static_assert((OP * BJ) % NT == 0, "whole slices per thread");
-  __shared__ double rx_s[OP * BJ];        // [k][j]
-  __shared__ double xj_s[BJ * (OP + 1)];  // [j][i], padded row
-  __shared__ double z_s[BJ * BI];         // [j][I]
+  __shared__ double rx_s[2][OP * BJ];        // [k][j]
+  __shared__ double xj_s[2][BJ * (OP + 1)];  // [j][i], padded row
+  __shared__ double z_s[2][BJ * BI];         // [j][I]
 
   const int64_t X = blockIdx.y;
   const int64_t I0 = (int64_t)blockIdx.x * BI;
@@ -40,7 +56,6 @@ __global__ __launch_bounds__(NT) void exch_kernel(int64_t o, int64_t Q, const do
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int64_t Iw = I0 + 16 * w + lr;    // this lane's I (B operand column, output column)
-  const int S = (int)((o + 3) / 4);       // k-steps of the first product
 
   // B operand of the first product: xo[4 s + lk][Iw], held for the whole J walk
   double xb[4 * OB];
@@ -50,34 +65,47 @@ __global__ __launch_bounds__(NT) void exch_kernel(int64_t o, int64_t Q, const do
     xb[s] = (k < o && Iw < Q) ? xo[k * Q + Iw] : 0.0;
   }
 
+  // element q of this thread's share of a J block: Rx / xo row k, column jr; z row I0 + iz, column jz
+  const int jr = t % BJ, jz = t % BJ;
+  uint32_t roff[NRX], zoff[NZ];
+  bool rok[NRX], zok[NZ];
+#pragma unroll
+  for (int q = 0; q < NRX; ++q) {
+    const int k = (t + NT * q) / BJ;
+    roff[q] = 8u * ((uint32_t)k * (uint32_t)Q + (uint32_t)jr);
+    rok[q] = k < o;
+  }
+#pragma unroll
+  for (int q = 0; q < NZ; ++q) {
+    const int iz = (t + NT * q) / BJ;
+    zoff[q] = 8u * ((uint32_t)iz * (uint32_t)Q + (uint32_t)jz);
+    zok[q] = I0 + iz < Q;
+  }
+
   double prx[NRX], pxj[NRX], pz[NZ];
   auto load = [&](int64_t J0) {
+    const bool jok = J0 + jr < Q;  // jr == jz
+    const __amdgpu_buffer_rsrc_t rr = rsrc(R + J0), rx = rsrc(xo + J0), rz = rsrc(z + I0 * Q + J0);
 #pragma unroll
     for (int q = 0; q < NRX; ++q) {
-      const int e = t + NT * q;
-      const int64_t k = e / BJ, J = J0 + e % BJ;
-      const bool ok = k < o && J < Q;
-      prx[q] = ok ? R[k * Q + J] : 0.0;
-      pxj[q] = ok ? xo[k * Q + J] : 0.0;
+      const uint32_t off = rok[q] && jok ? roff[q] : OOB;
+      prx[q] = bload(rr, off);
+      pxj[q] = bload(rx, off);
     }
 #pragma unroll
-    for (int q = 0; q < NZ; ++q) {
-      const int e = t + NT * q;
-      const int64_t I = I0 + e / BJ, J = J0 + e % BJ;
-      pz[q] = (I < Q && J < Q) ? z[I * Q + J] : 0.0;
-    }
+    for (int q = 0; q < NZ; ++q) pz[q] = bload(rz, zok[q] && jok ? zoff[q] : OOB);
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < NRX; ++q) {
       const int e = t + NT * q;
-      rx_s[e] = prx[q];
-      xj_s[(e % BJ) * (OP + 1) + e / BJ] = pxj[q];
+      rx_s[buf][e] = prx[q];
+      xj_s[buf][(e % BJ) * (OP + 1) + e / BJ] = pxj[q];
     }
 #pragma unroll
     for (int q = 0; q < NZ; ++q) {
       const int e = t + NT * q;
-      z_s[(e % BJ) * BI + e / BJ] = pz[q];
+      z_s[buf][(e % BJ) * BI + e / BJ] = pz[q];
     }
   };
 
@@ -85,28 +113,37 @@ __global__ __launch_bounds__(NT) void exch_kernel(int64_t o, int64_t Q, const do
 #pragma unroll
   for (int b = 0; b < OB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  load(0);
-  for (int64_t J0 = 0; J0 < Q; J0 += BJ) {
-    store();
-    __syncthreads();
-    if (J0 + BJ < Q) load(J0 + BJ);
+  auto compute = [&](int buf) {
     // Ft[J][I] for J in this block (rows), this wave's 16 I (columns)
     d4 ft = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4 * OB; ++s)
-      if (s < S) ft = __builtin_amdgcn_mfma_f64_16x16x4f64(rx_s[(4 * s + lk) * BJ + lr], xb[s], ft, 0, 0, 0);
+      ft = __builtin_amdgcn_mfma_f64_16x16x4f64(rx_s[buf][(4 * s + lk) * BJ + lr], xb[s], ft, 0, 0, 0);
     // scale by z[I][J]: element r is (J = lk + 4 r, I = 16 w + lr)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) ft[r] *= z_s[(lk + 4 * r) * BI + 16 * w + lr];
+    for (int r = 0; r < 4; ++r) ft[r] *= z_s[buf][(lk + 4 * r) * BI + 16 * w + lr];
     // Gt[i][I] += sum_J xo[i][J] Ft[J][I]; k-step r uses ft[r] as its B element
 #pragma unroll
     for (int b = 0; b < OB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xj_s[(4 * r + lk) * (OP + 1) + 16 * b + lr], ft[r], acc[b], 0, 0,
-                                                      0);
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xj_s[buf][(4 * r + lk) * (OP + 1) + 16 * b + lr], ft[r], acc[b],
+                                                      0, 0, 0);
+  };
+
+  const int64_t nb = (Q + BJ - 1) / BJ;
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t jb = 1; jb < nb; ++jb) {  // block jb - 1 is multiplied while block jb is fetched
+    load(jb * BJ);
+    compute(buf);
+    store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
+  compute(buf);
 
   // output element r of block b: i = 16 b + lk + 4 r, I = Iw
   if (Iw < Q) {
@@ -124,7 +161,9 @@ template <int OB>
 hipError_t launch(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx, double* Gt,
                   hipStream_t s) {
   const int64_t ti = (Q + BI - 1) / BI;
-  if (ti > 2147483647LL || nx > 65535) return hipErrorInvalidValue;
+  // byte offsets within a J block stay below 2^31 (the buffer range)
+  if (ti > 2147483647LL || nx > 65535 || 8 * (BI + 1) * Q >= (int64_t(1) << 31) || 8 * (16 * OB + 1) * Q >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(exch_kernel<OB>, dim3((unsigned)ti, (unsigned)nx), dim3(NT), 0, s, o, Q, xo, z, Rx, Gt);
   return hipGetLastError();
 }
