@@ -73,10 +73,24 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t bz = blockIdx.z;
+  // XCD-aware tile order: workgroups are dispatched round-robin to the 8 XCDs (dispatch id
+  // mod 8), so the dispatch id is remapped to give each XCD a contiguous range of tiles -- whole
+  // rows of tiles, splits and batches, whose shared A and B panels then meet in one L2.
+  const uint32_t nx = gridDim.x, nxy = gridDim.x * gridDim.y, total = nxy * gridDim.z;
+  const uint32_t hw = blockIdx.x + nx * blockIdx.y + nxy * blockIdx.z;
+  const uint32_t t8 = total & ~7u;
+  const uint32_t lid = hw < t8 ? (hw & 7u) * (t8 >> 3) + (hw >> 3) : hw;
+  const int64_t bz = lid / nxy;
   const int64_t b = bz / g.ksplit;
   const int split = (int)(bz % g.ksplit);
-  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  int64_t m0 = (int64_t)((lid % nxy) / nx) * BM, n0 = (int64_t)(lid % nx) * BN;
+  if (g.upper) {  // the grid enumerates the tiles (r, c) with r <= c only, row by row
+    const int nt = (int)((g.N + BN - 1) / BN);
+    int tr = (int)(lid % nxy), r = 0;
+    while (tr >= nt - r) { tr -= nt - r; ++r; }
+    m0 = (int64_t)r * BM;
+    n0 = (int64_t)(r + tr) * BN;
+  }
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = (kbeg + kchunk < g.K) ? kbeg + kchunk : g.K;
 
@@ -227,8 +241,11 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const Gemm g, const 
 template <int BM, int BN, bool F32>
 hipError_t launch_tile(const Gemm& g, int64_t kchunk, hipStream_t s) {
   constexpr int OCC = 2;  // two workgroups per CU: one multiplies while the other loads
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
+  static_assert(BM == BN, "square tiles (the upper mode walks a triangle of them)");
+  const int64_t ntn = (g.N + BN - 1) / BN;
+  dim3 grid((unsigned)(g.upper ? ntn * (ntn + 1) / 2 : ntn), (unsigned)(g.upper ? 1 : (g.M + BM - 1) / BM),
             (unsigned)(g.batch * g.ksplit));
+  if ((uint64_t)grid.x * grid.y * grid.z >= (uint64_t(1) << 32)) return hipErrorInvalidValue;  // 32-bit tile ids
   // byte offsets within a slab stay below 2^31 (the buffer range)
   const int64_t la = 8 * (BM + BK) * g.lda, lb = 8 * (BN + BK) * g.ldb;
   if (la >= (int64_t(1) << 31) || lb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
@@ -246,7 +263,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   // A batch that shares B and whose A, C (and Hadamard factor) blocks follow each other row by
   // row is one product with batch * M rows: fold it, so that it gets the large tiles.
-  if (g.batch > 1 && g.sB == 0 && !g.transA && g.sA == g.M * g.lda && g.sC == g.M * g.ldc &&
+  if (g.batch > 1 && g.sB == 0 && !g.transA && !g.upper && g.sA == g.M * g.lda && g.sC == g.M * g.ldc &&
       (!g.kscaleA || g.sksA == 0) && (!g.kscaleB || g.sksB == 0) && (!g.hmul || g.sH == g.M * g.ldh) &&
       (!g.pair_rows || g.M % 2 == 0) && !g.xtile && g.cblk == 0 && g.ksplit == 1) {
     g.M *= g.batch;
@@ -254,7 +271,8 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
     g.sA = g.sC = g.sH = 0;
   }
   // Batches interleaved row by row (row m of batch b at m * batch + b) fold the same way.
-  if (g.batch > 1 && g.sB == 0 && !g.transA && !g.pair_rows && g.cblk == 0 && g.ksplit == 1 && g.sA >= g.K &&
+  if (g.batch > 1 && g.sB == 0 && !g.transA && !g.pair_rows && !g.upper && g.cblk == 0 && g.ksplit == 1 &&
+      g.sA >= g.K &&
       g.sC >= g.N &&
       g.lda == g.batch * g.sA && g.ldc == g.batch * g.sC && (!g.kscaleA || g.sksA == 0) &&
       (!g.kscaleB || g.sksB == 0) && (!g.hmul || (g.sH >= g.N && g.ldh == g.batch * g.sH))) {
@@ -271,12 +289,13 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
     g.K = 0;
   }
   if ((g.C == nullptr) == (g.Cf == nullptr)) return hipErrorInvalidValue;  // exactly one output
-  if ((g.xtile && !g.pair_rows) || g.cblk < 0 || (g.cblk > 0 && (g.pair_rows || g.ldc % g.cblk != 0)))
+  if ((g.xtile && !g.pair_rows) || g.cblk < 0 || (g.cblk > 0 && (g.pair_rows || g.ldc % g.cblk != 0)) ||
+      (g.upper && g.M != g.N))
     return hipErrorInvalidValue;
   if (g.Cf && (g.beta != 0.0 || !g.f32)) return hipErrorInvalidValue;
   // Few output tiles and a long K: split K over more workgroups (about three per CU), partial
   // products in the workspace, then one reduction that applies the epilogue.
-  if (g.ksplit == 1 && g.ws && g.K >= 256) {
+  if (g.ksplit == 1 && g.ws && g.K >= 256 && !g.upper) {
     const int64_t t64 = ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
     if (t64 < 384) {
       const int64_t ns = std::min<int64_t>(std::min<int64_t>(g.K / 128, (768 + t64 - 1) / t64), 32);

@@ -34,6 +34,9 @@ struct Gemm {
   // cblk > 0: C cut into 16 x cblk blocks, block-row-major, each block row-major:
   // C[((m / 16) (ldc / cblk) + n / cblk) 16 cblk + (m % 16) cblk + n % cblk] (ldc % cblk == 0).
   int cblk = 0;
+  // upper: only the tiles holding some element (m, n) with m <= n are computed (every such
+  // element is); the others are left untouched.  For symmetric products (M == N).
+  bool upper = false;
   bool f32 = false;        // FP32 MFMA (operands rounded to FP32, FP32 accumulation)
   bool keep64 = false;     // stays FP64 in the mixed-precision path
   float* Cf = nullptr;     // FP32 output instead of C (requires f32 and beta = 0)
@@ -52,6 +55,8 @@ hipError_t k_colsum_rowscaled(int64_t nb, int64_t rows, int64_t P, const double*
 hipError_t k_hadamard_energy(int64_t P, int64_t nb, const double* T, const double* MT, double* F,
                              double* epart, hipStream_t s);
 hipError_t k_batch_sum(int64_t nb, int64_t len, const double* X, double alpha, double* out, hipStream_t s);
+// out[i][j] += alpha sum_b X_b[min(i, j)][max(i, j)] (X: nb upper-triangle-valid P x P matrices).
+hipError_t k_batch_sum_sym(int64_t nb, int64_t P, const double* X, double alpha, double* out, hipStream_t s);
 hipError_t k_wsum(int64_t nb, int64_t len, const double* w, const double* X, int64_t sX, double alpha,
                   double* out, hipStream_t s);
 hipError_t k_copy2d(int64_t batch, int64_t rows, int64_t cols, const double* src, int64_t lds, int64_t sbs,

@@ -66,18 +66,42 @@ __global__ void colsum_rowscaled_kernel(int64_t nb, int64_t rows, int64_t P, con
 
 // F^A = T o (M^A)^T (given MT^A = (M^A)^T) and the exchange energy partial
 // sum_YZ F^A_YZ MT^A_ZY = sum_YZ T_YZ M^A_YZ M^A_ZY, one partial per (A, block).
-__global__ void hadamard_energy_kernel(int64_t P, const double* __restrict__ T, const double* __restrict__ MT,
-                                       double* __restrict__ F, double* __restrict__ epart) {
-  const int64_t PP = P * P;
+// F[A] = T o M[A] and the partial sums of sum_YZ T[Y][Z] M[A][Y][Z] M[A][Z][Y], by 32 x 32 tiles:
+// the tile (Y-block, Z-block) and its transposed partner are both read coalesced (the partner
+// through LDS).  Grid (64, nb): block b of matrix A takes tiles b, b + 64, ... and writes its
+// sum to epart[A][b].
+__global__ __launch_bounds__(TPB) void hadamard_energy_kernel(int64_t P, const double* __restrict__ T,
+                                                              const double* __restrict__ MT, double* __restrict__ F,
+                                                              double* __restrict__ epart) {
+  constexpr int TS = 32;
+  __shared__ double mt_s[TS][TS + 1];  // M[Z-block rows][Y-block columns], read transposed
+  const int64_t PP = P * P, nt = (P + TS - 1) / TS;
   const int64_t A = blockIdx.y;
   const double* mt = MT + A * PP;
   double* f = F + A * PP;
+  const int c = threadIdx.x % TS, r0 = threadIdx.x / TS;  // 8 rows per pass
   double s = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < PP; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t Y = e / P, Z = e % P;
-    const double x = T[e] * mt[e];
-    f[e] = x;
-    s += x * mt[Z * P + Y];
+  for (int64_t tile = blockIdx.x; tile < nt * nt; tile += gridDim.x) {
+    const int64_t by = tile / nt, bz = tile % nt;
+    __syncthreads();  // the previous tile's reads of mt_s are done
+#pragma unroll
+    for (int k = 0; k < TS / 8; ++k) {
+      const int r = r0 + 8 * k;
+      const int64_t Zr = bz * TS + r, Yc = by * TS + c;
+      mt_s[r][c] = (Zr < P && Yc < P) ? mt[Zr * P + Yc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TS / 8; ++k) {
+      const int r = r0 + 8 * k;
+      const int64_t Y = by * TS + r, Z = bz * TS + c;
+      if (Y < P && Z < P) {
+        const int64_t e = Y * P + Z;
+        const double x = T[e] * mt[e];
+        f[e] = x;
+        s += x * mt_s[c][r];  // M[Z][Y]
+      }
+    }
   }
   s = block_sum<TPB>(s);
   if (threadIdx.x == 0) epart[A * gridDim.x + blockIdx.x] = s;
@@ -88,6 +112,18 @@ __global__ void batch_sum_kernel(int64_t nb, int64_t len, const double* __restri
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
     for (int64_t A = 0; A < nb; ++A) s += X[A * len + e];
+    out[e] += alpha * s;
+  }
+}
+
+__global__ void batch_sum_sym_kernel(int64_t nb, int64_t P, const double* __restrict__ X, double alpha,
+                                     double* __restrict__ out) {
+  const int64_t PP = P * P;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < PP; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / P, j = e % P;
+    const int64_t u = i <= j ? e : j * P + i;
+    double s = 0.0;
+    for (int64_t A = 0; A < nb; ++A) s += X[A * PP + u];
     out[e] += alpha * s;
   }
 }
@@ -318,6 +354,9 @@ hipError_t k_hadamard_energy(int64_t P, int64_t nb, const double* T, const doubl
 }
 hipError_t k_batch_sum(int64_t nb, int64_t len, const double* X, double alpha, double* out, hipStream_t s) {
   LAUNCH(batch_sum_kernel, dim3(nblocks(len)), dim3(TPB), nb, len, X, alpha, out);
+}
+hipError_t k_batch_sum_sym(int64_t nb, int64_t P, const double* X, double alpha, double* out, hipStream_t s) {
+  LAUNCH(batch_sum_sym_kernel, dim3(nblocks(P * P)), dim3(TPB), nb, P, X, alpha, out);
 }
 hipError_t k_wsum(int64_t nb, int64_t len, const double* w, const double* X, int64_t sX, double alpha, double* out,
                   hipStream_t s) {

@@ -373,9 +373,10 @@ int plan_and_alloc(thc_ctx* ctx) {
   int64_t nb = op.a_block > 0 ? op.a_block : std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(4.0e9 / (32.0 * P * P))));
   nb = std::min(nb, nL);
   ctx->nb = nb;
-  // split of the N_L P-deep sum of Alg. 1: about 512 workgroups of 128 x 128 tiles (two per CU)
-  const int64_t t128 = ((P + 127) / 128) * ((P + 127) / 128);
-  ctx->KS = std::max<int64_t>(1, std::min<int64_t>(16, (512 + t128 - 1) / t128));
+  // split of the N_L P-deep sum of Alg. 1: at most 512 workgroups of 128 x 128 tiles (one round
+  // at two per CU), counting the tiles on and above the diagonal (the product is symmetric)
+  const int64_t nt128 = (P + 127) / 128, t128 = nt128 * (nt128 + 1) / 2;
+  ctx->KS = std::max<int64_t>(1, std::min<int64_t>(16, 512 / t128));
   // H block over X: whole rank when it fits in ~40 GB
   int64_t Xb = op.x_block;
   if (Xb <= 0) {
@@ -561,9 +562,12 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     if (mask & THC_TERM_EQ28) {
       // D^A = C^A T; sigma += sum_A D^A (C^A)^T  (Alg. 1), split over K
       RCHK(gemm(ctx, batched(mk(P, P, P, ctx->Ccat, nb * P, false, T, P, false, ctx->Dcat, nb * P), nb, P, 0, P)));
+      // sum_A C^A T (C^A)^T is symmetric for a symmetric T (whether or not the T1-dressed C^A
+      // are): only the tiles on and above the diagonal are computed; the reduction mirrors them
       Gemm g = mk(P, P, nb * P, ctx->Dcat, nb * P, false, ctx->Ccat, nb * P, true, ctx->sig28, P, 1.0, 1.0);
       g.ksplit = (int)ctx->KS;
       g.sSplit = PP;
+      g.upper = true;
       RCHK(gemm(ctx, g));
     }
     // Abar^X_A = sum_ai y_a^X y_i^X L^_ai ; Atil^X_A = sum_ia y_i^X y_a^X L_ia  (Alg. 2)
@@ -646,7 +650,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   ctx->section = "gemm@assembly";
   ctx->mixed = ctx->want_mixed;
   RCHK(gemm(ctx, mk(P, P, P, ctx->S, P, false, T, P, false, ctx->ST, P)));
-  if (mask & THC_TERM_EQ28) MISC(k_batch_sum(ctx->KS, PP, ctx->sig28, 1.0, ctx->sig, s));
+  if (mask & THC_TERM_EQ28) MISC(k_batch_sum_sym(ctx->KS, P, ctx->sig28, 1.0, ctx->sig, s));
   if (mask & THC_TERM_EQ29) {
     // sigma += Abar K^T + K Abar^T, K = Abar/2 + 2 S T Atil - H
     RCHK(gemm(ctx, mk(P, nL, P, ctx->ST, P, false, ctx->At, nL, false, ctx->K29, nL, 2.0, 0.0)));
