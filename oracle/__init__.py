@@ -14,4 +14,5 @@ t2[i, j, a, b] = t2[j, i, b, a].
 from .ccsd import (dress_cholesky, one_electron, dressed_fock, doubles_terms, singles_terms,
                    doubles_residual, singles_residual, energy, C_D)
 from .thc import (khatri_rao, amplitudes, project, eri_fit, eri_thc_dense, metric, fock_operator,
-                  pseudo_canonical, mp2_amplitudes, mp2_guess, thc_residual, solve, SolveResult)
+                  pseudo_canonical, mp2_amplitudes, mp2_guess, thc_residual, solve, SolveResult,
+                  driver_projection, energy_from_factors)

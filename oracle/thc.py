@@ -118,6 +118,31 @@ def thc_residual(eps, L, Xo, Xv, Z, t1, V=None, terms=False):
     return project(R2, Xo, Xv), R1
 
 
+def driver_projection(L, Xo, Xv) -> np.ndarray:
+    """The projected residual at t1 = 0, t2 = 0, where every term but the driver (ia|jb)
+    vanishes (Eq. 6 applied to R_ij^ab = (ia|jb)), contracted through the factors:
+    sigma = M^T M with M[K, W] = sum_ia L_ia^K y_i^W y_a^W (Cholesky integrals)."""
+    o = Xo.shape[0]
+    M = L[:, :o, o:].reshape(L.shape[0], -1) @ khatri_rao(Xo, Xv)
+    return M.T @ M
+
+
+def energy_from_factors(L, Xo, Xv, Z) -> float:
+    """The correlation energy at t1 = 0 of the THC amplitudes t = B Z B^T (the usual
+    closed-shell expression, Sec. II.a), contracted through the factors one Cholesky vector
+    at a time: Coulomb 2 sum_K m_K^T Z m_K with m_K[W] = sum_ia y_i^W L_ia^K y_a^W, exchange
+    sum_K sum_WX Z^WX N_K[W, X] N_K[X, W] with N_K = Xo^T L_ov^K Xv."""
+    o = Xo.shape[0]
+    e = 0.0
+    for K in range(L.shape[0]):
+        Lk = L[K, :o, o:]
+        LX = Lk @ Xv
+        m = (Xo * LX).sum(axis=0)
+        N = Xo.T @ LX
+        e += 2.0 * (m @ Z @ m) - float(np.sum(Z * N * N.T))
+    return float(e)
+
+
 @dataclass
 class SolveResult:
     energy: float

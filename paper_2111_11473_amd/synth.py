@@ -101,6 +101,10 @@ CONFIGS = {
     # wider occupied spaces: the fused exchange kernel's o <= 64 and o <= 128 instantiations
     "occ40": Config("occ40", 40, 56, 200, 130, 300, 30.0, 1012),
     "occ70": Config("occ70", 70, 30, 150, 120, 260, 30.0, 1013),
+    # degenerate sizes: one occupied orbital; a pair basis and ERI grid as large as the o v
+    # pairs (complete: THC-CCSD is then CD-CCSD)
+    "one_occ": Config("one_occ", 1, 9, 12, 7, 9, 30.0, 1014),
+    "complete": Config("complete", 3, 2, 10, 6, 6, 30.0, 1039),
 }
 
 
