@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector peak (256 CUs, 2.4 GHz)
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -154,7 +155,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = {name: ctx.profile_get(name) for name in ("h_kernel", "residual", "gemm", "misc", "exch")}
-        flops64, flops32 = ctx.profile_flops()
+        flops64, flops32, flops16 = ctx.profile_flops()
         ctx.profile(False)
         conv = None
         if not args.no_converge:
@@ -170,7 +171,7 @@ def main():
                     "guess": "MP2 least-squares fit", "solver": "Jacobi (pseudo-canonical) + DIIS(8)"}
         ctx.close()
         torch.cuda.synchronize()
-        return dt, prof, flops64 / args.steps, flops32 / args.steps, conv
+        return dt, prof, flops64 / args.steps, (flops32 + flops16) / args.steps, conv
 
     def to_target(conv, e_ref):
         """Iterations and seconds until the energy stays within 1e-6 Eh of e_ref."""
@@ -206,26 +207,39 @@ def main():
     t_res = r_ms / max(1, r_n) / 1e3
     t_ideal = (h_flops_per_residual + gf64 + exch_flops) / (PEAK_FP64_VALU_TFLOPS * 1e12)
 
-    mixed = None
-    if not args.no_mixed:
-        dtm, profm, _, gf32m, convm = leg(1)
+    def mixed_leg(precision):
+        """One mixed-precision leg: its timed steps, MFMA rate, roofline fraction and converge run."""
+        dtm, profm, _, gfm, convm = leg(precision)
         rm_ms, rm_n = profm["residual"]
         gm_s = profm["gemm"][0] / args.steps / 1e3
         t_res_m = rm_ms / max(1, rm_n) / 1e3
-        t_ideal_m = (h_flops_per_residual + exch_flops) / (PEAK_FP64_VALU_TFLOPS * 1e12) + gf32m / (PEAK_FP32_MFMA_TFLOPS * 1e12)
+        # ideal: H-kernel and exchange at the FP64 peak, contractions at the FP32 (BF16) matrix peak;
+        # a split-BF16 product is three BF16 products
+        peak = PEAK_FP32_MFMA_TFLOPS if precision == 1 else PEAK_BF16_MFMA_TFLOPS / 3.0
+        t_ideal_m = (h_flops_per_residual + exch_flops) / (PEAK_FP64_VALU_TFLOPS * 1e12) + gfm / (peak * 1e12)
         e_ref = conv64["final_energy"] if conv64 else None
         if convm is not None and e_ref is not None:
             convm["energy_minus_fp64"] = convm["final_energy"] - e_ref
             convm = to_target(convm, e_ref)
-        mixed = {"residual_evals_per_s": args.steps / dtm, "ms_per_step": 1e3 * dtm / args.steps,
-                 "residual_ms": 1e3 * t_res_m, "h_kernel_ms": profm["h_kernel"][0] / args.steps,
-                 "gemm_ms": profm["gemm"][0] / args.steps,
-                 "gemm_fp32_mfma": {"achieved": gf32m / max(gm_s, 1e-12) / 1e12, "peak": PEAK_FP32_MFMA_TFLOPS,
-                                    "unit": "TFLOP/s"},
-                 "residual_roofline_frac": t_ideal_m / t_res_m,
-                 "precision": "FP32 MFMA contractions and FP32 H operands (FP64 accumulation), FP64 energy, "
-                              "denominators, fit, DIIS; FP64 finishing iterations",
-                 "converge": convm}
+        rate = gfm / max(gm_s, 1e-12) / 1e12
+        return {"residual_evals_per_s": args.steps / dtm, "ms_per_step": 1e3 * dtm / args.steps,
+                "residual_ms": 1e3 * t_res_m, "h_kernel_ms": profm["h_kernel"][0] / args.steps,
+                "gemm_ms": profm["gemm"][0] / args.steps,
+                ("gemm_fp32_mfma" if precision == 1 else "gemm_split_bf16_mfma"):
+                    {"achieved": rate if precision == 1 else 3.0 * rate,
+                     "peak": PEAK_FP32_MFMA_TFLOPS if precision == 1 else PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "note": "product flops" if precision == 1 else "three BF16 products per split product"},
+                "residual_roofline_frac": t_ideal_m / t_res_m,
+                "precision": ("FP32 MFMA contractions" if precision == 1 else
+                              "compensated split-BF16 contractions (hi hi + hi lo + lo hi, FP32 accumulation)") +
+                             " and FP32 H operands (FP64 accumulation), FP64 energy, denominators, fit, DIIS; "
+                             "FP64 finishing iterations",
+                "converge": convm}
+
+    mixed = mixed_bf16 = None
+    if not args.no_mixed:
+        mixed = mixed_leg(1)
+        mixed_bf16 = mixed_leg(2)
     if conv64 is not None:
         conv64 = to_target(conv64, conv64["final_energy"])
 
@@ -259,6 +273,7 @@ def main():
                                   "exchange": x_ms / args.steps, "misc": m_ms / args.steps},
         "converge": conv64,
         "mixed": mixed,
+        "mixed_split_bf16": mixed_bf16,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -64,7 +64,9 @@ typedef struct thc_options {
   int64_t x_chunk;          /* amplitude ranks per Alg. 7 exchange chunk (two-GEMM form); 0 = automatic */
   int32_t precision;        /* 0 = FP64 throughout; 1 = mixed: FP32-MFMA contractions and FP32 H-kernel
                                operands with FP64 accumulation, FP64 energy, denominators, fit and DIIS,
-                               and thc_iterate finishing with FP64 residuals */
+                               and thc_iterate finishing with FP64 residuals; 2 = as 1 with the
+                               contractions as compensated split-BF16 products (hi hi + hi lo + lo hi on
+                               BF16 MFMA, FP32 accumulation) */
   int32_t flags;            /* THC_FLAG_* bits; 0 = defaults */
 } thc_options;
 
@@ -137,9 +139,10 @@ int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes);
  * the summed duration in milliseconds and the number of launches recorded. */
 int thc_profile(thc_ctx* ctx, int enable);
 int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
-/* Flops (2 M N K per product) issued to the MFMA GEMM kernel since profiling was enabled, split
- * into FP64 and FP32 (mixed precision) products. */
-int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops);
+/* Flops (2 M N K per product, counted once however the product is evaluated) issued to the MFMA
+ * GEMM kernels since profiling was enabled, split into FP64, FP32 and split-BF16 products (any
+ * pointer may be NULL). */
+int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops, double* bf16x3_flops);
 
 /* The library's FP64 MFMA GEMM (exposed for testing): C = alpha op(A) op(B) + beta C,
  * row-major, op = transpose when trans* != 0, batched with element strides sA, sB, sC. */

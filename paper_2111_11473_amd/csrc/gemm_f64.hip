@@ -48,6 +48,75 @@ __device__ inline double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0u, 0));
 }
 
+// Tile of this workgroup.  XCD-aware order: workgroups are dispatched round-robin to the 8 XCDs
+// (dispatch id mod 8), so the dispatch id is remapped to give each XCD a contiguous range of
+// tiles -- whole rows of tiles, splits and batches, whose shared A and B panels then meet in one
+// L2.  In the upper mode the grid enumerates the tiles (r, c) with r <= c only, row by row.
+struct TileId {
+  int64_t b, m0, n0;
+  int split;
+};
+template <int BM, int BN>
+__device__ inline TileId tile_id(const Gemm& g) {
+  const uint32_t nx = gridDim.x, nxy = gridDim.x * gridDim.y, total = nxy * gridDim.z;
+  const uint32_t hw = blockIdx.x + nx * blockIdx.y + nxy * blockIdx.z;
+  const uint32_t t8 = total & ~7u;
+  const uint32_t lid = hw < t8 ? (hw & 7u) * (t8 >> 3) + (hw >> 3) : hw;
+  const int64_t bz = lid / nxy;
+  TileId id;
+  id.b = bz / g.ksplit;
+  id.split = (int)(bz % g.ksplit);
+  id.m0 = (int64_t)((lid % nxy) / nx) * BM;
+  id.n0 = (int64_t)(lid % nx) * BN;
+  if (g.upper) {
+    const int nt = (int)((g.N + BN - 1) / BN);
+    int tr = (int)(lid % nxy), r = 0;
+    while (tr >= nt - r) { tr -= nt - r; ++r; }
+    id.m0 = (int64_t)r * BM;
+    id.n0 = (int64_t)(r + tr) * BN;
+  }
+  return id;
+}
+
+// Epilogue by blocks of 16 rows: every load (C for beta, the Hadamard factor) of a block is
+// issued before its stores, so the loads overlap instead of waiting one by one behind stores
+// to possibly the same addresses.  acc[i][j][r] is output element r of the lane in 16 x 16
+// block (i, j) of the wave's (WM x WN) patch at (wm0, wn0): row lk + 4 r for the FP64 MFMA
+// (ROW4 false), row 4 lk + r for the FP32-accumulating ones; column lr.
+template <int TI, int TJ, bool ROW4, typename ACC>
+__device__ inline void epilogue(const Gemm& g, const TileId& id, int64_t wm0, int64_t wn0, int lr, int lk,
+                                const ACC (&acc)[TI][TJ]) {
+  double* __restrict__ C = g.C ? g.C + id.b * g.sC + (int64_t)id.split * g.sSplit : nullptr;
+  float* __restrict__ Cf = g.Cf ? g.Cf + id.b * g.sC + (int64_t)id.split * g.sSplit : nullptr;
+  const double* __restrict__ H = g.hmul ? g.hmul + id.b * g.sH : nullptr;
+  const bool rd = C && g.beta != 0.0;
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    int64_t off[TJ][4];
+    double x[TJ][4];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = id.m0 + wm0 + i * 16 + (ROW4 ? 4 * lk + r : lk + 4 * r);
+        const int64_t n = id.n0 + wn0 + j * 16 + lr;
+        const bool ok = m < g.M && n < g.N;
+        off[j][r] = ok ? c_offset(g, m, n) : -1;
+        x[j][r] = g.alpha * (double)acc[i][j][r];
+        if (H && ok) x[j][r] *= H[m * g.ldh + n];
+        if (rd && ok) x[j][r] += g.beta * C[off[j][r]];
+      }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (off[j][r] < 0) continue;
+        if (Cf) Cf[off[j][r]] = (float)x[j][r];  // FP32 output (beta is zero for it)
+        else C[off[j][r]] = x[j][r];
+      }
+  }
+}
+
 // F32: operands rounded to FP32 on their way into LDS, v_mfma_f32_16x16x4f32 with FP32
 // accumulation (the mixed-precision path); otherwise FP64 throughout.
 //
@@ -73,24 +142,9 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // XCD-aware tile order: workgroups are dispatched round-robin to the 8 XCDs (dispatch id
-  // mod 8), so the dispatch id is remapped to give each XCD a contiguous range of tiles -- whole
-  // rows of tiles, splits and batches, whose shared A and B panels then meet in one L2.
-  const uint32_t nx = gridDim.x, nxy = gridDim.x * gridDim.y, total = nxy * gridDim.z;
-  const uint32_t hw = blockIdx.x + nx * blockIdx.y + nxy * blockIdx.z;
-  const uint32_t t8 = total & ~7u;
-  const uint32_t lid = hw < t8 ? (hw & 7u) * (t8 >> 3) + (hw >> 3) : hw;
-  const int64_t bz = lid / nxy;
-  const int64_t b = bz / g.ksplit;
-  const int split = (int)(bz % g.ksplit);
-  int64_t m0 = (int64_t)((lid % nxy) / nx) * BM, n0 = (int64_t)(lid % nx) * BN;
-  if (g.upper) {  // the grid enumerates the tiles (r, c) with r <= c only, row by row
-    const int nt = (int)((g.N + BN - 1) / BN);
-    int tr = (int)(lid % nxy), r = 0;
-    while (tr >= nt - r) { tr -= nt - r; ++r; }
-    m0 = (int64_t)r * BM;
-    n0 = (int64_t)(r + tr) * BN;
-  }
+  const TileId id = tile_id<BM, BN>(g);
+  const int64_t b = id.b, m0 = id.m0, n0 = id.n0;
+  const int split = id.split;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = (kbeg + kchunk < g.K) ? kbeg + kchunk : g.K;
 
@@ -183,39 +237,165 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
   }
   if (nslab > 0) compute(buf);
 
-  double* __restrict__ C = g.C ? g.C + b * g.sC + (int64_t)split * g.sSplit : nullptr;
-  float* __restrict__ Cf = g.Cf ? g.Cf + b * g.sC + (int64_t)split * g.sSplit : nullptr;
-  const double* __restrict__ H = g.hmul ? g.hmul + b * g.sH : nullptr;
-  const bool rd = C && g.beta != 0.0;
-  // Epilogue by blocks of 16 rows: every load (C for beta, the Hadamard factor) of a block is
-  // issued before its stores, so the loads overlap instead of waiting one by one behind stores
-  // to possibly the same addresses.  Output element r of a lane: FP64 MFMA row lk + 4 r, FP32
-  // MFMA row 4 lk + r; column lr.
+  epilogue<TI, TJ, F32>(g, id, wm * WM, wn * WN, lr, lk, acc);
+}
+
+// Split-BF16 products (the compensated mode of the mixed-precision path): every operand is
+// rounded to FP32 and split into a bf16 head (its top 16 bits) and a bf16 tail (the top 16 bits
+// of the remainder), x = hi + lo + O(2^-16 |x|), and each product is hi hi + hi lo + lo hi on
+// v_mfma_f32_16x16x16bf16_1k with FP32 accumulation (the lo lo term, O(2^-16) relative, is
+// dropped).  A thread loads packets of 4 consecutive k of one row, scales them, splits them and
+// stores the hi and lo packets (8 bytes each) to LDS, where a lane's MFMA fragment (row lr,
+// k = 4 lk .. 4 lk + 3) is one packet.  One 16-k slab is one MFMA k-step; tiles, double
+// buffering, the XCD-aware order and the epilogue are those of the FP64/FP32 kernel.
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+
+// hi / lo bf16 pairs of two FP32 values, packed two to a dword (element 0 in the low half)
+__device__ inline void split_pair(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  const uint32_t h0 = __builtin_bit_cast(uint32_t, x0) & 0xFFFF0000u;
+  const uint32_t h1 = __builtin_bit_cast(uint32_t, x1) & 0xFFFF0000u;
+  const float r0 = x0 - __builtin_bit_cast(float, h0), r1 = x1 - __builtin_bit_cast(float, h1);
+  hi = (h0 >> 16) | h1;
+  lo = (__builtin_bit_cast(uint32_t, r0) >> 16) | (__builtin_bit_cast(uint32_t, r1) & 0xFFFF0000u);
+}
+
+template <int BM, int BN, bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void bgemm_kernel(const Gemm g, const int64_t kchunk) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TI = WM / 16, TJ = WN / 16;
+  constexpr int QA = BM / 64, QB = BN / 64;  // packets (4 k of one row) per thread and slab
+  // LDS: [buffer][hi, lo][k / 4][row] packets; rows padded so that the four k / 4 planes a wave
+  // reads at once sit 32 banks apart
+  __shared__ u2 As[2][2][4][BM + 16];
+  __shared__ u2 Bs[2][2][4][BN + 16];
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const TileId id = tile_id<BM, BN>(g);
+  const int64_t b = id.b, m0 = id.m0, n0 = id.n0;
+  const int64_t kbeg = (int64_t)id.split * kchunk;
+  const int64_t kend = (kbeg + kchunk < g.K) ? kbeg + kchunk : g.K;
+
+  const double* __restrict__ A = g.A + b * g.sA + (TA ? m0 : m0 * g.lda);
+  const double* __restrict__ B = g.B + b * g.sB + (TB ? n0 * g.ldb : n0);
+  const double* __restrict__ sa = g.kscaleA ? g.kscaleA + b * g.sksA : &kOne;
+  const double* __restrict__ sb = g.kscaleB ? g.kscaleB + b * g.sksB : &kOne;
+  const int64_t ksa = g.kscaleA ? g.ksA : 0, ksb = g.kscaleB ? g.ksB : 0;
+  const uint32_t lda = (uint32_t)g.lda, ldb = (uint32_t)g.ldb;
+  const int mlim = (int)((g.M - m0 < BM) ? g.M - m0 : BM);
+  const int nlim = (int)((g.N - n0 < BN) ? g.N - n0 : BN);
+  constexpr uint32_t OOB = 0x80000000u;
+
+  // packet q of this thread: row (column) and k / 4 within the slab; consecutive lanes read
+  // consecutive addresses (a k-fastest operand: 4 lanes per row; an m/n-fastest one: a row per k)
+  int am[QA], aq[QA], bn[QB], bq[QB];
 #pragma unroll
-  for (int i = 0; i < TI; ++i) {
-    int64_t off[TJ][4];
-    double x[TJ][4];
-#pragma unroll
-    for (int j = 0; j < TJ; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm * WM + i * 16 + (F32 ? 4 * lk + r : lk + 4 * r);
-        const int64_t n = n0 + wn * WN + j * 16 + lr;
-        const bool ok = m < g.M && n < g.N;
-        off[j][r] = ok ? c_offset(g, m, n) : -1;
-        x[j][r] = g.alpha * (double)acc[i][j][r];
-        if (H && ok) x[j][r] *= H[m * g.ldh + n];
-        if (rd && ok) x[j][r] += g.beta * C[off[j][r]];
-      }
-#pragma unroll
-    for (int j = 0; j < TJ; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (off[j][r] < 0) continue;
-        if (Cf) Cf[off[j][r]] = (float)x[j][r];  // FP32 output (beta is zero for it)
-        else C[off[j][r]] = x[j][r];
-      }
+  for (int q = 0; q < QA; ++q) {
+    const int p = t + 256 * q;
+    am[q] = TA ? p % BM : p >> 2;
+    aq[q] = TA ? p / BM : p & 3;
   }
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    const int p = t + 256 * q;
+    bn[q] = TB ? p >> 2 : p % BN;
+    bq[q] = TB ? p & 3 : p / BN;
+  }
+
+  double ra[QA][4], rb[QB][4], rsa[QA][4], rsb[QB][4];
+  auto load = [&](int64_t k0) {
+    const int kl = (int)(kend - k0);
+    const __amdgpu_buffer_rsrc_t rA = rsrc(A + (TA ? k0 * g.lda : k0));
+    const __amdgpu_buffer_rsrc_t rB = rsrc(B + (TB ? k0 : k0 * g.ldb));
+#pragma unroll
+    for (int q = 0; q < QA; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 4 * aq[q] + e;
+        const uint32_t off = 8u * (TA ? (uint32_t)k * lda + (uint32_t)am[q] : (uint32_t)am[q] * lda + (uint32_t)k);
+        ra[q][e] = bload(rA, (am[q] < mlim && k < kl) ? off : OOB);
+        rsa[q][e] = sa[(k0 + (k < kl ? k : 0)) * ksa];
+      }
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 4 * bq[q] + e;
+        const uint32_t off = 8u * (TB ? (uint32_t)bn[q] * ldb + (uint32_t)k : (uint32_t)k * ldb + (uint32_t)bn[q]);
+        rb[q][e] = bload(rB, (bn[q] < nlim && k < kl) ? off : OOB);
+        rsb[q][e] = sb[(k0 + (k < kl ? k : 0)) * ksb];
+      }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      uint32_t h0, l0, h1, l1;
+      split_pair((float)(ra[q][0] * rsa[q][0]), (float)(ra[q][1] * rsa[q][1]), h0, l0);
+      split_pair((float)(ra[q][2] * rsa[q][2]), (float)(ra[q][3] * rsa[q][3]), h1, l1);
+      const u2 hi = u2{h0, h1}, lo = u2{l0, l1};
+      As[buf][0][aq[q]][am[q]] = hi;
+      As[buf][1][aq[q]][am[q]] = lo;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      uint32_t h0, l0, h1, l1;
+      split_pair((float)(rb[q][0] * rsb[q][0]), (float)(rb[q][1] * rsb[q][1]), h0, l0);
+      split_pair((float)(rb[q][2] * rsb[q][2]), (float)(rb[q][3] * rsb[q][3]), h1, l1);
+      const u2 hi = u2{h0, h1}, lo = u2{l0, l1};
+      Bs[buf][0][bq[q]][bn[q]] = hi;
+      Bs[buf][1][bq[q]][bn[q]] = lo;
+    }
+  };
+
+  flt4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+
+  const int lr = lane & 15, lk = lane >> 4;
+  auto compute = [&](int buf) {
+    bf4 ah[TI], al[TI], bh[TJ], bl[TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      ah[i] = __builtin_bit_cast(bf4, As[buf][0][lk][wm * WM + i * 16 + lr]);
+      al[i] = __builtin_bit_cast(bf4, As[buf][1][lk][wm * WM + i * 16 + lr]);
+    }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      bh[j] = __builtin_bit_cast(bf4, Bs[buf][0][lk][wn * WN + j * 16 + lr]);
+      bl[j] = __builtin_bit_cast(bf4, Bs[buf][1][lk][wn * WN + j * 16 + lr]);
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+  };
+  const int nslab = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
+  if (nslab > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  int64_t k0 = kbeg;
+  for (int sl = 1; sl < nslab; ++sl) {
+    load(k0 + BK);
+    compute(buf);
+    store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    k0 += BK;
+  }
+  if (nslab > 0) compute(buf);
+
+  epilogue<TI, TJ, true>(g, id, wm * WM, wn * WN, lr, lk, acc);
 }
 
 // C = alpha sum_s W_s (times the Hadamard factor) + beta C for a product computed as ksplit
@@ -256,6 +436,21 @@ hipError_t launch_tile(const Gemm& g, int64_t kchunk, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int BM, int BN>
+hipError_t launch_btile(const Gemm& g, int64_t kchunk, hipStream_t s) {
+  const int64_t ntn = (g.N + BN - 1) / BN;
+  dim3 grid((unsigned)(g.upper ? ntn * (ntn + 1) / 2 : ntn), (unsigned)(g.upper ? 1 : (g.M + BM - 1) / BM),
+            (unsigned)(g.batch * g.ksplit));
+  if ((uint64_t)grid.x * grid.y * grid.z >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
+  const int64_t la = 8 * (BM + BK) * g.lda, lb = 8 * (BN + BK) * g.ldb;
+  if (la >= (int64_t(1) << 31) || lb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  if (!g.transA && !g.transB) hipLaunchKernelGGL((bgemm_kernel<BM, BN, false, false>), grid, dim3(256), 0, s, g, kchunk);
+  else if (g.transA && !g.transB) hipLaunchKernelGGL((bgemm_kernel<BM, BN, true, false>), grid, dim3(256), 0, s, g, kchunk);
+  else if (!g.transA && g.transB) hipLaunchKernelGGL((bgemm_kernel<BM, BN, false, true>), grid, dim3(256), 0, s, g, kchunk);
+  else hipLaunchKernelGGL((bgemm_kernel<BM, BN, true, true>), grid, dim3(256), 0, s, g, kchunk);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
@@ -292,7 +487,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   if ((g.xtile && !g.pair_rows) || g.cblk < 0 || (g.cblk > 0 && (g.pair_rows || g.ldc % g.cblk != 0)) ||
       (g.upper && g.M != g.N))
     return hipErrorInvalidValue;
-  if (g.Cf && (g.beta != 0.0 || !g.f32)) return hipErrorInvalidValue;
+  if (g.Cf && (g.beta != 0.0 || !(g.f32 || g.bf16x3))) return hipErrorInvalidValue;
   // Few output tiles and a long K: split K over more workgroups (about three per CU), partial
   // products in the workspace, then one reduction that applies the epilogue.
   if (g.ksplit == 1 && g.ws && g.K >= 256 && !g.upper) {
@@ -324,6 +519,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   const bool big = g.M >= 96 && g.N >= 96 && t128 >= 480 && kchunk > 64;
   if (big && (g.M + 127) / 128 > 65535) return hipErrorInvalidValue;
   if (!big && (g.M + 63) / 64 > 65535) return hipErrorInvalidValue;
+  if (g.bf16x3) return big ? launch_btile<128, 128>(g, kchunk, s) : launch_btile<64, 64>(g, kchunk, s);
   if (g.f32) return big ? launch_tile<128, 128, true>(g, kchunk, s) : launch_tile<64, 64, true>(g, kchunk, s);
   return big ? launch_tile<128, 128, false>(g, kchunk, s) : launch_tile<64, 64, false>(g, kchunk, s);
 }

@@ -38,6 +38,7 @@ struct Gemm {
   // element is); the others are left untouched.  For symmetric products (M == N).
   bool upper = false;
   bool f32 = false;        // FP32 MFMA (operands rounded to FP32, FP32 accumulation)
+  bool bf16x3 = false;     // split-BF16 products (hi hi + hi lo + lo hi, FP32 accumulation)
   bool keep64 = false;     // stays FP64 in the mixed-precision path
   float* Cf = nullptr;     // FP32 output instead of C (requires f32 and beta = 0)
   // Workspace for an automatic split of K (products with few output tiles and a long K); the

@@ -104,7 +104,8 @@ struct thc_ctx {
   bool prof = false;
   std::vector<ProfRec> recs;
   const char* section = nullptr;  // residual section, for per-section GEMM records ("gemm@<section>")
-  double gemm_flops = 0.0, gemm_flops32 = 0.0;  // MFMA GEMM flops (2 M N K per product) while profiling
+  double gemm_flops = 0.0, gemm_flops32 = 0.0, gemm_flops16 = 0.0;  // MFMA GEMM flops (2 M N K per product,
+                                                                     // FP64 / FP32 / split-BF16) while profiling
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
 };
@@ -209,8 +210,11 @@ int gemm(thc_ctx* ctx, const Gemm& g0) {
   Gemm g = g0;
   g.ws = ctx->gws;
   g.ws_len = ctx->gws ? GEMM_WS : 0;
-  if (ctx->mixed && !g.keep64) g.f32 = true;
-  if (ctx->prof && g.K > 0) (g.f32 ? ctx->gemm_flops32 : ctx->gemm_flops) += 2.0 * g.M * g.N * g.K * g.batch;
+  if (ctx->mixed && !g.keep64) {
+    if (ctx->opt.precision == 2) g.bf16x3 = true; else g.f32 = true;
+  }
+  if (ctx->prof && g.K > 0)
+    (g.bf16x3 ? ctx->gemm_flops16 : g.f32 ? ctx->gemm_flops32 : ctx->gemm_flops) += 2.0 * g.M * g.N * g.K * g.batch;
   if (ctx->prof && ctx->section) {
     Scope sc2(ctx, ctx->section);
     HIPCHK(gemm_f64(g, ctx->stream));
@@ -443,7 +447,7 @@ int plan_and_alloc(thc_ctx* ctx) {
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) { ctx->err = "hipMemGetInfo failed"; return THC_EDEVICE; }
     const double per_i = 8.0 * (2.0 * (double)Xb * Pp + (double)Pp * Pp + (double)o * P) +
-                         (op.precision == 1 ? 4.0 * 2.0 * (double)Xb * Pp : 0.0);
+                         (op.precision >= 1 ? 4.0 * 2.0 * (double)Xb * Pp : 0.0);
     const double budget = std::min(16.0e9, std::max(2.0e9, 0.5 * ((double)freeb - fixed)));
     Ic = std::max<int64_t>(1, (int64_t)(budget / per_i));
   }
@@ -467,7 +471,7 @@ int plan_and_alloc(thc_ctx* ctx) {
     ctx->nhtiles = (int64_t)tiles.size();
     RCHK(h2d(ctx, ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t)));
   }
-  if (op.precision == 1) {  // FP32 E, F for the mixed-precision H-kernel
+  if (op.precision >= 1) {  // FP32 E, F for the mixed-precision H-kernel
     const int64_t nf = ctx->Ic * Xb * Pp;
     double *e32 = nullptr, *f32 = nullptr;
     RCHK(alloc(ctx, &e32, (size_t)((nf + 1) / 2)));
@@ -972,7 +976,7 @@ int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
   if (!opt || !out) return THC_EINVAL;
   *out = nullptr;
   if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
-      opt->diis_max > 16 || (opt->precision != 0 && opt->precision != 1) || (opt->flags & ~THC_FLAG_UNFUSED_EXCHANGE) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
+      opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) || (opt->flags & ~THC_FLAG_UNFUSED_EXCHANGE) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
       opt->x_chunk < 0)
     return THC_EINVAL;
   thc_ctx* ctx = new (std::nothrow) thc_ctx();
@@ -1130,7 +1134,7 @@ int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t
   if (!ctx) return THC_EINVAL;
   RCHK(need_built(ctx));
   if (!Z || !sigma) { ctx->err = "null argument"; return THC_EINVAL; }
-  ctx->want_mixed = ctx->opt.precision == 1;
+  ctx->want_mixed = ctx->opt.precision >= 1;
   RCHK(residual_impl(ctx, Z, ctx->opt.singles ? t1 : nullptr, mask));
   HIPCHK(hipMemcpyAsync(sigma, ctx->sig, ctx->P * ctx->P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   if (sigma1) HIPCHK(hipMemcpyAsync(sigma1, ctx->sig1, ctx->ov * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
@@ -1200,7 +1204,7 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   const auto t_start = std::chrono::steady_clock::now();
   // precision ladder (mixed precision): FP32-MFMA residuals until their norm has dropped 1e4-fold,
   // is within 10 tol, or stops decreasing; then FP64 residuals, which alone may declare convergence
-  bool mixed_phase = ctx->opt.precision == 1;
+  bool mixed_phase = ctx->opt.precision >= 1;
   double rn_first = -1.0, rn_prev = 0.0;
   int mixed_its = 0;
   ctx->hist_mixed.clear();
@@ -1343,7 +1347,7 @@ int thc_profile(thc_ctx* ctx, int enable) {
   ctx->prof = enable != 0;
   ctx->recs.clear();
   ctx->pool_used = 0;
-  ctx->gemm_flops = ctx->gemm_flops32 = 0.0;
+  ctx->gemm_flops = ctx->gemm_flops32 = ctx->gemm_flops16 = 0.0;
   return THC_OK;
 }
 
@@ -1364,10 +1368,11 @@ int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* l
   return THC_OK;
 }
 
-int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops) {
+int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops, double* bf16x3_flops) {
   if (!ctx) return THC_EINVAL;
   if (fp64_flops) *fp64_flops = ctx->gemm_flops;
   if (fp32_flops) *fp32_flops = ctx->gemm_flops32;
+  if (bf16x3_flops) *bf16x3_flops = ctx->gemm_flops16;
   return THC_OK;
 }
 

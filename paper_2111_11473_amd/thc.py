@@ -76,7 +76,7 @@ def load(path: str = LIB_PATH):
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
     lib.thc_profile.argtypes = [VP, C.c_int]
     lib.thc_profile_get.argtypes = [VP, C.c_char_p, C.POINTER(D), C.POINTER(I64)]
-    lib.thc_profile_flops.argtypes = [VP, C.POINTER(D), C.POINTER(D)]
+    lib.thc_profile_flops.argtypes = [VP, C.POINTER(D), C.POINTER(D), C.POINTER(D)]
     lib.thc_dgemm.argtypes = [C.c_int, C.c_int, I64, I64, I64, D, P, I64, I64, P, I64, I64, D, P, I64, I64, I64, VP]
     lib.thc_last_error.argtypes = [VP]
     lib.thc_last_error.restype = C.c_char_p
@@ -297,10 +297,10 @@ class THC:
         self._check(self.lib.thc_profile(self.ctx, int(enable)), "thc_profile")
 
     def profile_flops(self):
-        """(FP64, FP32) MFMA GEMM flops issued since profile(True)."""
-        a, b = C.c_double(0.0), C.c_double(0.0)
-        self._check(self.lib.thc_profile_flops(self.ctx, C.byref(a), C.byref(b)), "thc_profile_flops")
-        return a.value, b.value
+        """(FP64, FP32, split-BF16) MFMA GEMM flops (2 M N K per product) issued since profile(True)."""
+        a, b, c = C.c_double(0.0), C.c_double(0.0), C.c_double(0.0)
+        self._check(self.lib.thc_profile_flops(self.ctx, C.byref(a), C.byref(b), C.byref(c)), "thc_profile_flops")
+        return a.value, b.value, c.value
 
     def profile_get(self, name):
         ms = C.c_double(0.0)

@@ -14,7 +14,7 @@ from oracle import ccsd
 from paper_2111_11473_amd import synth
 
 pytestmark = pytest.mark.gpu
-RTOL_MIXED = 5e-5
+RTOL_MIXED = {1: 5e-5, 2: 5e-4}
 
 
 def _say(*a):
@@ -47,11 +47,12 @@ def _make(thc, cfg, **kw):
     return s, ctx, _host(Z0)
 
 
+@pytest.mark.parametrize("precision", [1, 2])
 @pytest.mark.parametrize("name", ["tiny", "medium", "occ40"])
-def test_mixed_residual_terms_within_bound(thc, name):
+def test_mixed_residual_terms_within_bound(thc, name, precision):
     cfg = synth.CONFIGS[name]
-    _say("terms", name)
-    s, ctx, Z0 = _make(thc, cfg, precision=1)
+    _say("terms", name, "precision", precision)
+    s, ctx, Z0 = _make(thc, cfg, precision=precision)
     rng = np.random.default_rng(3)
     P = Z0.shape[0]
     R = rng.standard_normal((P, P))
@@ -68,17 +69,18 @@ def test_mixed_residual_terms_within_bound(thc, name):
         err = np.abs(got - want).max() / np.abs(want).max()
         worst = max(worst, err)
         _say(f"  {key}: relative error {err:.2e}")
-        assert err < RTOL_MIXED, (key, err)
+        assert err < RTOL_MIXED[precision], (key, err)
     _say("worst term error", worst)
 
 
-def test_mixed_solve_reaches_fp64_energy(thc):
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_solve_reaches_fp64_energy(thc, precision):
     cfg = synth.CONFIGS["medium"]
-    _say("solve medium")
+    _say("solve medium, precision", precision)
     _, c64, _ = _make(thc, cfg, tol_energy=1e-10)
     it64, _, ok64 = c64.iterate(tol=1e-8, maxit=60)
     e64 = c64.energy()
-    _, cmx, _ = _make(thc, cfg, tol_energy=1e-10, precision=1)
+    _, cmx, _ = _make(thc, cfg, tol_energy=1e-10, precision=precision)
     itmx, _, okmx = cmx.iterate(tol=1e-8, maxit=60)
     emx = cmx.energy()
     flags = cmx.history_precision()
