@@ -184,8 +184,10 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
 #pragma unroll
     for (int r = 0; r < NB; ++r)
       rb[r] = bload(rB, (kb < kl && nb + SNB * r < nlim) ? boff + bstep * r : OOB);
-    rsa = sa[(k0 + (ka < kl ? ka : 0)) * ksa];
-    rsb = sb[(k0 + (kb < kl ? kb : 0)) * ksb];
+    // scale factors through buffer loads too: a generic (flat) load would also count against the
+    // LDS wait before the slab's first product
+    rsa = bload(rsrc(sa), (uint32_t)(8 * (k0 + (ka < kl ? ka : 0)) * ksa));
+    rsb = bload(rsrc(sb), (uint32_t)(8 * (k0 + (kb < kl ? kb : 0)) * ksb));
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -309,6 +311,7 @@ __global__ __launch_bounds__(256, 2) void bgemm_kernel(const Gemm g, const int64
     const int kl = (int)(kend - k0);
     const __amdgpu_buffer_rsrc_t rA = rsrc(A + (TA ? k0 * g.lda : k0));
     const __amdgpu_buffer_rsrc_t rB = rsrc(B + (TB ? k0 : k0 * g.ldb));
+    const __amdgpu_buffer_rsrc_t rSa = rsrc(sa), rSb = rsrc(sb);
 #pragma unroll
     for (int q = 0; q < QA; ++q)
 #pragma unroll
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(256, 2) void bgemm_kernel(const Gemm g, const int64
         const int k = 4 * aq[q] + e;
         const uint32_t off = 8u * (TA ? (uint32_t)k * lda + (uint32_t)am[q] : (uint32_t)am[q] * lda + (uint32_t)k);
         ra[q][e] = bload(rA, (am[q] < mlim && k < kl) ? off : OOB);
-        rsa[q][e] = sa[(k0 + (k < kl ? k : 0)) * ksa];
+        rsa[q][e] = bload(rSa, (uint32_t)(8 * (k0 + (k < kl ? k : 0)) * ksa));
       }
 #pragma unroll
     for (int q = 0; q < QB; ++q)
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(256, 2) void bgemm_kernel(const Gemm g, const int64
         const int k = 4 * bq[q] + e;
         const uint32_t off = 8u * (TB ? (uint32_t)bn[q] * ldb + (uint32_t)k : (uint32_t)k * ldb + (uint32_t)bn[q]);
         rb[q][e] = bload(rB, (bn[q] < nlim && k < kl) ? off : OOB);
-        rsb[q][e] = sb[(k0 + (k < kl ? k : 0)) * ksb];
+        rsb[q][e] = bload(rSb, (uint32_t)(8 * (k0 + (k < kl ? k : 0)) * ksb));
       }
   };
   auto store = [&](int buf) {
@@ -486,6 +489,9 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   if ((g.C == nullptr) == (g.Cf == nullptr)) return hipErrorInvalidValue;  // exactly one output
   if ((g.xtile && !g.pair_rows) || g.cblk < 0 || (g.cblk > 0 && (g.pair_rows || g.ldc % g.cblk != 0)) ||
       (g.upper && g.M != g.N))
+    return hipErrorInvalidValue;
+  // k-scale factors are read through 32-bit byte offsets
+  if ((g.kscaleA && 8 * g.K * g.ksA >= (int64_t(1) << 31)) || (g.kscaleB && 8 * g.K * g.ksB >= (int64_t(1) << 31)))
     return hipErrorInvalidValue;
   if (g.Cf && (g.beta != 0.0 || !(g.f32 || g.bf16x3))) return hipErrorInvalidValue;
   // Few output tiles and a long K: split K over more workgroups (about three per CU), partial
