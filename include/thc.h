@@ -75,7 +75,9 @@ typedef struct thc_options {
 #define THC_FLAG_UNFUSED_EXCHANGE (1 << 0)
 
 /* Creates a context bound to the current HIP device and to `stream` (hipStream_t; NULL = the
- * default stream).  Allocates nothing on the device yet.  *out receives the context. */
+ * default stream).  Allocates nothing on the device yet.  *out receives the context.
+ * THC_EINVAL for sizes below 1, nP or nQ above o v (the metric of the pair basis and the Gram
+ * matrix of the ERI grid would be singular), or options out of range; nothing is created then. */
 int thc_create(const thc_options* opt, void* stream, thc_ctx** out);
 
 /* Set-up (paper Eq. 9-14, 17-20; Alg. 6): copies the integrals and factors, forms the

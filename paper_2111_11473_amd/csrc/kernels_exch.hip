@@ -38,7 +38,7 @@ __device__ inline double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
 }
 
 template <int OB>
-__global__ __launch_bounds__(NT, 3) void exch_kernel(int64_t o, int64_t Q, const double* __restrict__ xo,
+__global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, int64_t Q, const double* __restrict__ xo,
                                                   const double* __restrict__ z, const double* __restrict__ Rx,
                                                   double* __restrict__ Gt) {
   constexpr int OP = 16 * OB;             // padded o

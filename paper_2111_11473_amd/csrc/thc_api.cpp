@@ -979,6 +979,8 @@ int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
       opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) || (opt->flags & ~THC_FLAG_UNFUSED_EXCHANGE) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
       opt->x_chunk < 0)
     return THC_EINVAL;
+  // the metric S = B^T B (nP x nP) and the ERI-grid Gram (nQ x nQ) have rank at most o v
+  if (opt->nP > opt->o * opt->v || opt->nQ > opt->o * opt->v) return THC_EINVAL;
   thc_ctx* ctx = new (std::nothrow) thc_ctx();
   if (!ctx) return THC_ENOMEM;
   ctx->opt = *opt;

@@ -49,3 +49,20 @@ def test_binding_refuses_host_tensors():
     from paper_2111_11473_amd import thc
     with pytest.raises(TypeError):
         thc._ptr(torch.zeros(3, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("field,value", [("o", 0), ("v", -1), ("nL", 0), ("nP", 0), ("nQ", 0),
+                                         ("nP", 10 * 40 + 1), ("nQ", 10 * 40 + 1), ("precision", 3),
+                                         ("diis_max", 17), ("flags", 1 << 5), ("x_block", -64)])
+def test_create_rejects_invalid_options(lib, field, value):
+    """Option validation happens before any device call: sizes below 1, a pair basis or ERI grid
+    larger than the o v pairs (singular metric / Gram matrix), out-of-range options."""
+    from paper_2111_11473_amd import thc
+    base = dict(o=10, v=40, nL=150, nP=120, nQ=300, singles=1, diis_max=8, tol_energy=1e-8, a_block=0,
+                i_chunk=0, x_block=0, x_chunk=0, precision=0, flags=0)
+    base[field] = value
+    opt = thc.Options(**base)
+    lib.thc_create.argtypes = [ctypes.POINTER(thc.Options), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    assert lib.thc_create(ctypes.byref(opt), None, ctypes.byref(h)) == -1  # THC_EINVAL
+    assert not h.value
