@@ -141,7 +141,8 @@ int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes);
  * the summed duration in milliseconds and the number of launches recorded. */
 int thc_profile(thc_ctx* ctx, int enable);
 int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
-/* Flops (2 M N K per product, counted once however the product is evaluated) issued to the MFMA
+/* Flops (2 K per distinct output: 2 M N K per product, N (N + 1) K for a symmetric product whose
+ * lower triangle is mirrored; counted once however the product is evaluated) issued to the MFMA
  * GEMM kernels since profiling was enabled, split into FP64, FP32 and split-BF16 products (any
  * pointer may be NULL). */
 int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops, double* bf16x3_flops);

@@ -27,8 +27,10 @@ __device__ const double kOne = 1.0;
 
 // Position of C element (m, n) of one batch in the output layout of g.
 __device__ inline int64_t c_offset(const Gemm& g, int64_t m, int64_t n) {
-  if (g.cblk > 0)
-    return ((m >> 4) * (g.ldc / g.cblk) + n / g.cblk) * 16 * g.cblk + (m & 15) * g.cblk + n % g.cblk;
+  if (g.cblk > 0) {  // cblk is a power of two (checked on the host): shifts and masks
+    const int sh = __builtin_ctz((unsigned)g.cblk);
+    return ((((m >> 4) * (g.ldc >> sh) + (n >> sh)) << 4) + (m & 15)) * g.cblk + (n & (g.cblk - 1));
+  }
   if (g.pair_rows)
     return g.xtile ? ((((n >> 6) * g.ldc + (m >> 1)) << 6) + (n & 63)) * 2 + (m & 1)
                    : ((m >> 1) * g.ldc + n) * 2 + (m & 1);
@@ -125,7 +127,9 @@ __device__ inline void epilogue(const Gemm& g, const TileId& id, int64_t wm0, in
 // there too, so the global loads of the next slab are all in flight while the current slab is
 // multiplied.  Two LDS buffers: one barrier per slab.  Per-thread offsets are 32-bit, relative
 // to a per-tile base pointer.
-template <int BM, int BN, bool TA, bool TB, bool F32, int OCC>
+// SHORT (K of at most four slabs): the loads of every slab are issued at once, so a tile waits
+// for memory once rather than once per slab; the slabs then pass through the two LDS buffers.
+template <int BM, int BN, bool TA, bool TB, bool F32, int OCC, bool SHORT>
 __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int64_t kchunk) {
   using TL = typename std::conditional<F32, float, double>::type;
   using ACC = typename std::conditional<F32, flt4, dbl4>::type;
@@ -186,8 +190,8 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
       rb[r] = bload(rB, (kb < kl && nb + SNB * r < nlim) ? boff + bstep * r : OOB);
     // scale factors through buffer loads too: a generic (flat) load would also count against the
     // LDS wait before the slab's first product
-    rsa = bload(rsrc(sa), (uint32_t)(8 * (k0 + (ka < kl ? ka : 0)) * ksa));
-    rsb = bload(rsrc(sb), (uint32_t)(8 * (k0 + (kb < kl ? kb : 0)) * ksb));
+    rsa = bload(rsrc(sa), ka < kl ? (uint32_t)(8 * (k0 + ka) * ksa) : OOB);
+    rsb = bload(rsrc(sb), kb < kl ? (uint32_t)(8 * (k0 + kb) * ksb) : OOB);
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -203,9 +207,11 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
     for (int j = 0; j < TJ; ++j) acc[i][j] = ACC{0, 0, 0, 0};
 
   const int lr = lane & 15, lk = lane >> 4;
-  auto compute = [&](int buf) {
+  // nk: k of the slab that hold data (the rest are zeros); a k-step of 4 is skipped when past it
+  auto compute = [&](int buf, int nk = BK) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
+      if (kk >= nk) break;
       TL af[TI], bf[TJ];
 #pragma unroll
       for (int i = 0; i < TI; ++i) af[i] = As[buf][kk + lk][wm * WM + i * 16 + lr];
@@ -222,22 +228,55 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
     }
   };
   const int nslab = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
-  if (nslab > 0) {
-    load(kbeg);
-    store(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  int64_t k0 = kbeg;
-  for (int sl = 1; sl < nslab; ++sl) {  // slab sl - 1 is multiplied while slab sl is fetched
-    load(k0 + BK);
-    compute(buf);
-    store(buf ^ 1);
+  if constexpr (SHORT) {
+    // all four slabs, branch-free: a slab past the end of K reads as zeros (every offset out of
+    // range) and adds nothing
+    constexpr int NSL = 4;
+    double pa[NSL][NA], pb[NSL][NB], psa[NSL], psb[NSL];
+#pragma unroll
+    for (int q = 0; q < NSL; ++q) {
+      load(kbeg + q * BK);
+#pragma unroll
+      for (int r = 0; r < NA; ++r) pa[q][r] = ra[r];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) pb[q][r] = rb[r];
+      psa[q] = rsa;
+      psb[q] = rsb;
+    }
+    // slab q goes to buffer q % 2 once the barrier after slab q - 2's product has passed; only
+    // the k-steps that hold data are multiplied
+#pragma unroll
+    for (int q = 0; q < NSL; ++q) {
+      if (q >= nslab) break;
+#pragma unroll
+      for (int r = 0; r < NA; ++r) ra[r] = pa[q][r];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) rb[r] = pb[q][r];
+      rsa = psa[q];
+      rsb = psb[q];
+      store(q & 1);
+      if (q > 0) compute((q - 1) & 1);
+      __syncthreads();
+    }
+    if (nslab > 0) compute((nslab - 1) & 1, (int)(kend - kbeg) - BK * (nslab - 1));
+  } else {
+    if (nslab > 0) {
+      load(kbeg);
+      store(0);
+    }
     __syncthreads();
-    buf ^= 1;
-    k0 += BK;
+    int buf = 0;
+    int64_t k0 = kbeg;
+    for (int sl = 1; sl < nslab; ++sl) {  // slab sl - 1 is multiplied while slab sl is fetched
+      load(k0 + BK);
+      compute(buf);
+      store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+      k0 += BK;
+    }
+    if (nslab > 0) compute(buf);
   }
-  if (nslab > 0) compute(buf);
 
   epilogue<TI, TJ, F32>(g, id, wm * WM, wn * WN, lr, lk, acc);
 }
@@ -421,7 +460,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const Gemm g, const 
   }
 }
 
-template <int BM, int BN, bool F32>
+template <int BM, int BN, bool F32, bool SHORT = false>
 hipError_t launch_tile(const Gemm& g, int64_t kchunk, hipStream_t s) {
   constexpr int OCC = 2;  // two workgroups per CU: one multiplies while the other loads
   static_assert(BM == BN, "square tiles (the upper mode walks a triangle of them)");
@@ -432,10 +471,10 @@ hipError_t launch_tile(const Gemm& g, int64_t kchunk, hipStream_t s) {
   // byte offsets within a slab stay below 2^31 (the buffer range)
   const int64_t la = 8 * (BM + BK) * g.lda, lb = 8 * (BN + BK) * g.ldb;
   if (la >= (int64_t(1) << 31) || lb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-  if (!g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, false, F32, OCC>), grid, dim3(256), 0, s, g, kchunk);
-  else if (g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, false, F32, OCC>), grid, dim3(256), 0, s, g, kchunk);
-  else if (!g.transA && g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, true, F32, OCC>), grid, dim3(256), 0, s, g, kchunk);
-  else hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, true, F32, OCC>), grid, dim3(256), 0, s, g, kchunk);
+  if (!g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, false, F32, OCC, SHORT>), grid, dim3(256), 0, s, g, kchunk);
+  else if (g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, false, F32, OCC, SHORT>), grid, dim3(256), 0, s, g, kchunk);
+  else if (!g.transA && g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, true, F32, OCC, SHORT>), grid, dim3(256), 0, s, g, kchunk);
+  else hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, true, F32, OCC, SHORT>), grid, dim3(256), 0, s, g, kchunk);
   return hipGetLastError();
 }
 
@@ -487,7 +526,8 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
     g.K = 0;
   }
   if ((g.C == nullptr) == (g.Cf == nullptr)) return hipErrorInvalidValue;  // exactly one output
-  if ((g.xtile && !g.pair_rows) || g.cblk < 0 || (g.cblk > 0 && (g.pair_rows || g.ldc % g.cblk != 0)) ||
+  if ((g.xtile && !g.pair_rows) || g.cblk < 0 ||
+      (g.cblk > 0 && (g.pair_rows || (g.cblk & (g.cblk - 1)) != 0 || g.ldc % g.cblk != 0)) ||
       (g.upper && g.M != g.N))
     return hipErrorInvalidValue;
   // k-scale factors are read through 32-bit byte offsets
@@ -526,8 +566,13 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   if (big && (g.M + 127) / 128 > 65535) return hipErrorInvalidValue;
   if (!big && (g.M + 63) / 64 > 65535) return hipErrorInvalidValue;
   if (g.bf16x3) return big ? launch_btile<128, 128>(g, kchunk, s) : launch_btile<64, 64>(g, kchunk, s);
-  if (g.f32) return big ? launch_tile<128, 128, true>(g, kchunk, s) : launch_tile<64, 64, true>(g, kchunk, s);
-  return big ? launch_tile<128, 128, false>(g, kchunk, s) : launch_tile<64, 64, false>(g, kchunk, s);
+  const bool shortk = kchunk <= 4 * BK;
+  if (g.f32) {
+    if (big) return launch_tile<128, 128, true>(g, kchunk, s);
+    return shortk ? launch_tile<64, 64, true, true>(g, kchunk, s) : launch_tile<64, 64, true>(g, kchunk, s);
+  }
+  if (big) return launch_tile<128, 128, false>(g, kchunk, s);
+  return shortk ? launch_tile<64, 64, false, true>(g, kchunk, s) : launch_tile<64, 64, false>(g, kchunk, s);
 }
 
 }  // namespace thc

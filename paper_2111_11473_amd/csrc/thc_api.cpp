@@ -104,7 +104,7 @@ struct thc_ctx {
   bool prof = false;
   std::vector<ProfRec> recs;
   const char* section = nullptr;  // residual section, for per-section GEMM records ("gemm@<section>")
-  double gemm_flops = 0.0, gemm_flops32 = 0.0, gemm_flops16 = 0.0;  // MFMA GEMM flops (2 M N K per product,
+  double gemm_flops = 0.0, gemm_flops32 = 0.0, gemm_flops16 = 0.0;  // MFMA GEMM flops (2 K per distinct output,
                                                                      // FP64 / FP32 / split-BF16) while profiling
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
@@ -213,8 +213,11 @@ int gemm(thc_ctx* ctx, const Gemm& g0) {
   if (ctx->mixed && !g.keep64) {
     if (ctx->opt.precision == 2) g.bf16x3 = true; else g.f32 = true;
   }
-  if (ctx->prof && g.K > 0)
-    (g.bf16x3 ? ctx->gemm_flops16 : g.f32 ? ctx->gemm_flops32 : ctx->gemm_flops) += 2.0 * g.M * g.N * g.K * g.batch;
+  if (ctx->prof && g.K > 0) {
+    // a symmetric product (upper) needs only the N (N + 1) / 2 distinct outputs
+    const double outs = g.upper ? 0.5 * g.N * (g.N + 1.0) : (double)g.M * g.N;
+    (g.bf16x3 ? ctx->gemm_flops16 : g.f32 ? ctx->gemm_flops32 : ctx->gemm_flops) += 2.0 * outs * g.K * g.batch;
+  }
   if (ctx->prof && ctx->section) {
     Scope sc2(ctx, ctx->section);
     HIPCHK(gemm_f64(g, ctx->stream));
