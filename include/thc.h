@@ -60,7 +60,8 @@ typedef struct thc_options {
   double tol_energy;        /* |dE| convergence threshold (Eh), e.g. 1e-8 */
   int64_t a_block;          /* Cholesky vectors per fused-pass block; 0 = automatic */
   int64_t i_chunk;          /* ERI grid points per H-kernel pass; 0 = automatic */
-  int64_t x_block;          /* amplitude ranks per H block (multiple of 64); 0 = automatic */
+  int64_t x_block;          /* amplitude ranks per H block (multiple of 64, at most nP rounded up to 64);
+                             * 0 = automatic */
   int64_t x_chunk;          /* amplitude ranks per Alg. 7 exchange chunk (two-GEMM form); 0 = automatic */
   int32_t precision;        /* 0 = FP64 throughout; 1 = mixed: FP32-MFMA contractions and FP32 H-kernel
                                operands with FP64 accumulation, FP64 energy, denominators, fit and DIIS,

@@ -33,8 +33,8 @@
 // tile's lifetime; consecutive generations walk the grid points in opposite directions, so a
 // generation starts on the points its predecessor read last (still in the last-level cache).
 // One workgroup per tile measured faster than a persistent grid walking the table.
-// Layouts (ranks zero-padded to Pp, a multiple of 64; X restricted to a block of Xb ranks, a
-// multiple of 64): E, F: [Xb/64][ldi][Pp/2][64][2] (E_I^XY at [X/64][I][Y/2][X%64][Y%2]);
+// Layouts (Y, Z ranks zero-padded to Pp, a multiple of 16; X restricted to a block of Xb ranks, a
+// multiple of 64 and at most Pp rounded up to 64): E, F: [Xb/64][ldi][Pp/2][64][2] (E_I^XY at [X/64][I][Y/2][X%64][Y%2]);
 // G: [I][Pp/16][Pp/8][16][8] (G_I^YZ at [I][Y/16][Z/8][Y%16][Z%8]); H: [Pp][Pp][Xb] (H^XYZ at
 // [Y][Z][X]).
 #include <vector>
@@ -348,7 +348,7 @@ std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb, int64_t slots) {
 template <int NWZ, int NS, typename TE>
 hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const TE* E, const TE* F,
                   const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots, hipStream_t s) {
-  if (Pp % 64 != 0 || Pp > 8192 || Xb % LANES != 0 || Xb > Pp || Xb <= 0 || ntiles <= 0 || ntiles > 2147483647LL ||
+  if (Pp % BY != 0 || Pp <= 0 || Pp > 8192 || Xb % LANES != 0 || Xb > (Pp + LANES - 1) / LANES * LANES || Xb <= 0 || ntiles <= 0 || ntiles > 2147483647LL ||
       nI < 0 || ldi < nI || slots < 1 || ntiles % (8 * slots) != 0)
     return hipErrorInvalidValue;
   // One launch per generation of 8 slots tiles (every workgroup resident at once): the runs of

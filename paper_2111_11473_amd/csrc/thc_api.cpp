@@ -374,7 +374,9 @@ int check_finite_host(thc_ctx* ctx, const double* x, size_t n, const char* what)
 // Working-memory plan.
 int plan_and_alloc(thc_ctx* ctx) {
   const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
-  const int64_t Pp = ctx->Pp = ((P + 63) / 64) * 64;
+  // Y, Z ranks of the H accumulation padded to its 16-wide blocks; X ranks to its 64-lane tiles
+  const int64_t Pp = ctx->Pp = ((P + 15) / 16) * 16;
+  const int64_t P64 = ((P + 63) / 64) * 64;
   const thc_options& op = ctx->opt;
   // fused-pass block: four nb x P^2 panels within ~4 GB
   int64_t nb = op.a_block > 0 ? op.a_block : std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(4.0e9 / (32.0 * P * P))));
@@ -388,9 +390,12 @@ int plan_and_alloc(thc_ctx* ctx) {
   int64_t Xb = op.x_block;
   if (Xb <= 0) {
     const double hb = 40.0e9 / (8.0 * (double)Pp * Pp);
-    Xb = std::min<int64_t>(Pp, std::max<int64_t>(64, ((int64_t)hb / 64) * 64));
+    Xb = std::min<int64_t>(P64, std::max<int64_t>(64, ((int64_t)hb / 64) * 64));
   }
-  if (Xb % 64 != 0 || Xb > Pp) { ctx->err = "x_block must be a multiple of 64 and <= padded rank"; return THC_EINVAL; }
+  if (Xb % 64 != 0 || Xb > P64) {
+    ctx->err = "x_block must be a multiple of 64 and at most the rank rounded up to 64";
+    return THC_EINVAL;
+  }
   ctx->Xb = Xb;
   int64_t Xc = op.x_chunk;
   if (Xc <= 0) Xc = std::max<int64_t>(1, (int64_t)(2.0e9 / (8.0 * (double)Q * Q)));
