@@ -172,6 +172,7 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
 
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __builtin_assume(w >= 0 && w < C::NW);
   const int ly0 = (w % (BY / WY)) * WY, lz0 = (w / (BY / WY)) * WZ;
   const unsigned xrow = (unsigned)Xb * 8u;  // bytes per (Y) row of H
   const unsigned lo = (unsigned)lane * 8u;
@@ -232,12 +233,16 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
   const bool extra = g_yz || g_zy;  // this wave copies QROWS + extra chunks per stage
   const int64_t PX = (int64_t)Pp * LANES;  // elements of E, F per (X tile, I)
   const int64_t PP = (int64_t)Pp * Pp;     // elements of G per I
-  const TE* __restrict__ Et = E + (int64_t)xt * ldi * PX;
-  const TE* __restrict__ Ft = F + (int64_t)xt * ldi * PX;
-  auto stage_in = [&](int64_t I, int buf) {
-    if (rev) I = nI - 1 - I;  // this generation walks the grid points backwards
-    const __amdgpu_buffer_rsrc_t re = rsrc(Et + I * PX, PX * C::ESZ);
-    const __amdgpu_buffer_rsrc_t rf = rsrc(Ft + I * PX, PX * C::ESZ);
+  // Sources of the next stage to copy: a generation walks the grid points forwards or (rev)
+  // backwards, so each stage moves the three row pointers by one grid point.
+  const int64_t first = (rev && nI > 0) ? nI - 1 : 0;
+  const TE* e_at = E + ((int64_t)xt * ldi + first) * PX;
+  const TE* f_at = F + ((int64_t)xt * ldi + first) * PX;
+  const double* g_at = G + first * PP;
+  const int64_t dPX = rev ? -PX : PX, dPP = rev ? -PP : PP;
+  auto stage_in = [&](int buf) {
+    const __amdgpu_buffer_rsrc_t re = rsrc(e_at, PX * C::ESZ);
+    const __amdgpu_buffer_rsrc_t rf = rsrc(f_at, PX * C::ESZ);
     char* sb = lds + buf * C::STAGE_B;
 #pragma unroll
     for (int q = 0; q < C::QROWS; ++q) {
@@ -248,7 +253,10 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
                                                 : sp < C::FZ ? z0 / 2 + sp - C::EZ : z0 / 2 + sp - C::FZ;
       bload_lds(isF ? rf : re, sb + c * 1024, voff_r, (unsigned)pair * C::PAIR_B);
     }
-    if (extra) bload_lds(rsrc(G + I * PP, PP * 8), sb + C::G_B + w * 1024, voff_g, so_g);
+    if (extra) bload_lds(rsrc(g_at, PP * 8), sb + C::G_B + w * 1024, voff_g, so_g);
+    e_at += dPX;
+    f_at += dPX;
+    g_at += dPP;
   };
 
   // broadcast-register sources: lane l holds G^YZ[ly0 + 4 r + m / 4][lz0 + m % 4], m = l % 16
@@ -258,15 +266,16 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
 
   constexpr int D = NS - 1;  // stages in flight ahead of the one being consumed
   static_assert(D <= 3, "wait_pipe allows at most two stages in flight behind the next one");
+  auto next = [](int b) { return b + 1 == NS ? 0 : b + 1; };
   int64_t issued = 0;
-  for (; issued < D && issued < nI; ++issued) stage_in(issued, (int)issued);
+  int sbuf = 0;  // buffer of the next stage to copy: (buf + D) % NS once the pipe is full
+  for (; issued < D && issued < nI; ++issued) {
+    stage_in(sbuf);
+    sbuf = next(sbuf);
+  }
   wait_pipe<C::QROWS>((int)(issued > 0 ? issued - 1 : 0), extra);  // stage 0 has landed everywhere
   int buf = 0;
-  for (int64_t I = 0; I < nI; ++I) {
-    if (I + D < nI) {
-      stage_in(I + D, buf == 0 ? D : buf - 1);  // (buf + D) % NS, the buffer consumed at I - 1
-      ++issued;
-    }
+  auto consume = [&]() {
     __builtin_amdgcn_sched_barrier(0);
     const char* __restrict__ st = lds + buf * C::STAGE_B;
     const double* __restrict__ sg = (const double*)(st + C::G_B);
@@ -303,10 +312,23 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
     h_row<8>(acc[6], accm[6], ey[3].x, fy[3].x, ezs, fzs, g[1], gm[1]);
     h_row<12>(acc[7], accm[7], ey[3].y, fy[3].y, ezs, fzs, g[1], gm[1]);
     __builtin_amdgcn_sched_barrier(0);
-    // stage I + 1 must have landed; the stages after it (issued - I - 2 of them) may be in flight
-    const int64_t later = issued - I - 2;
+  };
+  // Steady state: every grid point also issues the stage D ahead, and the stage after the next
+  // one (D - 1 of them) may stay in flight.
+  const int64_t steady = nI - D;
+  for (int64_t I = 0; I < steady; ++I) {
+    stage_in(sbuf);
+    sbuf = next(sbuf);
+    consume();
+    wait_pipe<C::QROWS>(D - 1, extra);
+    buf = next(buf);
+  }
+  // Drain: nothing more to issue; stage I + 1 must have landed, nI - I - 2 may be in flight.
+  for (int64_t I = steady > 0 ? steady : 0; I < nI; ++I) {
+    consume();
+    const int64_t later = nI - I - 2;
     wait_pipe<C::QROWS>((int)(later > 0 ? later : 0), extra);
-    buf = (buf + 1 == NS) ? 0 : buf + 1;
+    buf = next(buf);
   }
 
   {
