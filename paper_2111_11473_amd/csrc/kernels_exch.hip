@@ -37,10 +37,13 @@ __device__ inline double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0u, 0));
 }
 
-template <int OB>
+// KST: k-steps of 4 in the first product (o rounded up to 4, at most 4 OB): the steps that would
+// multiply only the zero padding of o are not issued.
+template <int OB, int KST>
 __global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, int64_t Q, const double* __restrict__ xo,
                                                   const double* __restrict__ z, const double* __restrict__ Rx,
                                                   double* __restrict__ Gt) {
+  static_assert(KST >= 1 && KST <= 4 * OB, "k-steps within the padded o");
   constexpr int OP = 16 * OB;             // padded o
   constexpr int NRX = (OP * BJ) / NT;     // Rx / xo slice elements per thread
   constexpr int NZ = (BI * BJ) / NT;      // z slice elements per thread
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, in
     // Ft[J][I] for J in this block (rows), this wave's 16 I (columns)
     d4 ft = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int s = 0; s < 4 * OB; ++s)
+    for (int s = 0; s < KST; ++s)
       ft = __builtin_amdgcn_mfma_f64_16x16x4f64(rx_s[buf][(4 * s + lk) * BJ + lr], xb[s], ft, 0, 0, 0);
     // scale by z[I][J]: element r is (J = lk + 4 r, I = 16 w + lr)
 #pragma unroll
@@ -157,14 +160,15 @@ __global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, in
   }
 }
 
-template <int OB>
+template <int OB, int KST = 4 * OB>
 hipError_t launch(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx, double* Gt,
                   hipStream_t s) {
   const int64_t ti = (Q + BI - 1) / BI;
   // byte offsets within a J block stay below 2^31 (the buffer range)
   if (ti > 2147483647LL || nx > 65535 || 8 * (BI + 1) * Q >= (int64_t(1) << 31) || 8 * (16 * OB + 1) * Q >= (int64_t(1) << 31))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(exch_kernel<OB>, dim3((unsigned)ti, (unsigned)nx), dim3(NT), 0, s, o, Q, xo, z, Rx, Gt);
+  if (4 * KST < o) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((exch_kernel<OB, KST>), dim3((unsigned)ti, (unsigned)nx), dim3(NT), 0, s, o, Q, xo, z, Rx, Gt);
   return hipGetLastError();
 }
 
@@ -177,7 +181,12 @@ hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const 
   if (nx <= 0 || Q <= 0) return hipSuccess;
   if (o <= 16) return launch<1>(o, Q, nx, xo, z, Rx, Gt, s);
   if (o <= 32) return launch<2>(o, Q, nx, xo, z, Rx, Gt, s);
-  if (o <= 64) return launch<4>(o, Q, nx, xo, z, Rx, Gt, s);
+  if (o <= 64) {  // the k-step count of the first product fitted to o in steps of 8
+    if (o <= 40) return launch<4, 10>(o, Q, nx, xo, z, Rx, Gt, s);
+    if (o <= 48) return launch<4, 12>(o, Q, nx, xo, z, Rx, Gt, s);
+    if (o <= 56) return launch<4, 14>(o, Q, nx, xo, z, Rx, Gt, s);
+    return launch<4>(o, Q, nx, xo, z, Rx, Gt, s);
+  }
   if (o <= 128) return launch<8>(o, Q, nx, xo, z, Rx, Gt, s);
   return hipErrorInvalidValue;
 }
