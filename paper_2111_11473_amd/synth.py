@@ -101,9 +101,11 @@ CONFIGS = {
     # wider occupied spaces: the fused exchange kernel's o <= 64 and o <= 128 instantiations
     "occ40": Config("occ40", 40, 56, 200, 130, 300, 30.0, 1012),
     "occ70": Config("occ70", 70, 30, 150, 120, 260, 30.0, 1013),
-    # o in (40, 48] and (48, 56]: the exchange kernel's first product stops at 12 and 14 k-steps
+    # o in (40, 48], (48, 56] and (56, 64]: the exchange kernel's first product stops at 12, 14
+    # and 16 k-steps
     "occ46": Config("occ46", 46, 24, 120, 110, 260, 30.0, 1015),
     "occ53": Config("occ53", 53, 20, 110, 100, 240, 30.0, 1016),
+    "occ60": Config("occ60", 60, 18, 110, 100, 240, 30.0, 1017),
     # degenerate sizes: one occupied orbital; a pair basis and ERI grid as large as the o v
     # pairs (complete: THC-CCSD is then CD-CCSD)
     "one_occ": Config("one_occ", 1, 9, 12, 7, 9, 30.0, 1014),

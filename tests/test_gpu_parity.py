@@ -101,7 +101,7 @@ def test_mp2_guess_and_energy(thc, name):
     assert abs(e_gpu - e_ref) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["small", "tiny", "medium", "occ40", "occ46", "occ53", "occ70", "one_occ", "complete"])
+@pytest.mark.parametrize("name", ["small", "tiny", "medium", "occ40", "occ46", "occ53", "occ60", "occ70", "one_occ", "complete"])
 def test_residual_terms_match_oracle(thc, name):
     """Each term group of the projected residual (Alg. 1-10) against the dense oracle, at a
     state with t1 != 0 (T1-dressed integrals exercised)."""
