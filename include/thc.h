@@ -63,11 +63,12 @@ typedef struct thc_options {
   int64_t x_block;          /* amplitude ranks per H block (multiple of 64, at most nP rounded up to 64);
                              * 0 = automatic */
   int64_t x_chunk;          /* amplitude ranks per Alg. 7 exchange chunk (two-GEMM form); 0 = automatic */
-  int32_t precision;        /* 0 = FP64 throughout; 1 = mixed: FP32-MFMA contractions and FP32 H-kernel
-                               operands with FP64 accumulation, FP64 energy, denominators, fit and DIIS,
-                               and thc_iterate finishing with FP64 residuals; 2 = as 1 with the
-                               contractions as compensated split-BF16 products (hi hi + hi lo + lo hi on
-                               BF16 MFMA, FP32 accumulation) */
+  int32_t precision;        /* 0 = FP64 throughout; 1 = mixed: FP32-MFMA contractions (the fused Alg. 7
+                               exchange included) and FP32 H-kernel operands with FP64 accumulation,
+                               FP64 energy, denominators, fit and DIIS, and thc_iterate finishing with
+                               FP64 residuals; 2 = as 1 with the GEMM contractions as compensated
+                               split-BF16 products (hi hi + hi lo + lo hi on BF16 MFMA, FP32
+                               accumulation); the fused exchange stays FP32 MFMA */
   int32_t flags;            /* THC_FLAG_* bits; 0 = defaults */
 } thc_options;
 

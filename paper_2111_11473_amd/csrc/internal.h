@@ -89,10 +89,11 @@ hipError_t k_fill(int64_t n, double val, double* x, hipStream_t s);
 hipError_t k_set_diag(int64_t n, const double* d, double* X, int64_t ld, hipStream_t s);
 
 // Fused exchange contraction Gt^X = xo (z o (xo^T Rx^X))^T for X = 0..nx-1 (kernels_exch.hip);
-// xo [o][Q], z [Q][Q], Rx and Gt [nx][o][Q].  Supported for 1 <= o <= 128.
+// xo [o][Q], z [Q][Q], Rx and Gt [nx][o][Q].  Supported for 1 <= o <= 128.  f32: operands rounded
+// to FP32, FP32 MFMA and accumulation (the mixed-precision path); else FP64 throughout.
 bool exch_supported(int64_t o);
 hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx,
-                      double* Gt, hipStream_t s);
+                      double* Gt, bool f32, hipStream_t s);
 
 // Learned-guess network kernels (mlp.hip).  sgemm epilogues: 0 none, 1 bias + SiLU (pre-activation
 // to Z), 2 bias, 3 times SiLU'(Z).

@@ -15,12 +15,22 @@
 // I >= Q), so the padded k-steps multiply zeros and the loop has no branches; two LDS buffers, one
 // barrier per J block.
 // Layouts (row-major): xo [o][Q]; z [Q][Q]; Rx, Gt [X][o][Q].  Requires o <= 16 OB.
+//
+// F32 (the mixed-precision path): the slices are rounded to FP32 on their way into LDS and both
+// products run on v_mfma_f32_16x16x4f32 with FP32 accumulation.  There output element r of a
+// lane is row 4 (lane / 16) + r, so the lane holds Ft rows J = 4 lk + r and k-step r of the second
+// product takes J in that order (row lk of the step is J = 4 lk + r); the A operand, xo[i][J], is
+// read in the same order.  The FP32 LDS rows are padded so that the four lane groups of a read
+// fall on distinct banks.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace thc {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BI = 64, BJ = 16, NT = 256;
 constexpr int RSRC_W3 = 0x00020000;  // raw 32-bit buffer access
@@ -39,18 +49,22 @@ __device__ inline double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
 
 // KST: k-steps of 4 in the first product (o rounded up to 4, at most 4 OB): the steps that would
 // multiply only the zero padding of o are not issued.
-template <int OB, int KST>
+template <int OB, int KST, bool F32>
 __global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, int64_t Q, const double* __restrict__ xo,
                                                   const double* __restrict__ z, const double* __restrict__ Rx,
                                                   double* __restrict__ Gt) {
+  using T = typename std::conditional<F32, float, double>::type;
+  using V4 = typename std::conditional<F32, f4, d4>::type;
   static_assert(KST >= 1 && KST <= 4 * OB, "k-steps within the padded o");
   constexpr int OP = 16 * OB;             // padded o
   constexpr int NRX = (OP * BJ) / NT;     // Rx / xo slice elements per thread
   constexpr int NZ = (BI * BJ) / NT;      // z slice elements per thread
   static_assert((OP * BJ) % NT == 0, "whole slices per thread");
-  __shared__ double rx_s[2][OP * BJ];        // [k][j]
-  __shared__ double xj_s[2][BJ * (OP + 1)];  // [j][i], padded row
-  __shared__ double z_s[2][BJ * BI];         // [j][I]
+  // row pitches (elements) of the LDS slices
+  constexpr int PR = F32 ? BJ + 4 : BJ, PJ = F32 ? OP + 4 : OP + 1, PZ = F32 ? BI + 4 : BI;
+  __shared__ T rx_s[2][OP * PR];  // [k][j]
+  __shared__ T xj_s[2][BJ * PJ];  // [j][i]
+  __shared__ T z_s[2][BJ * PZ];   // [j][I]
 
   const int64_t X = blockIdx.y;
   const int64_t I0 = (int64_t)blockIdx.x * BI;
@@ -61,11 +75,11 @@ __global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, in
   const int64_t Iw = I0 + 16 * w + lr;    // this lane's I (B operand column, output column)
 
   // B operand of the first product: xo[4 s + lk][Iw], held for the whole J walk
-  double xb[4 * OB];
+  T xb[4 * OB];
 #pragma unroll
   for (int s = 0; s < 4 * OB; ++s) {
     const int64_t k = 4 * s + lk;
-    xb[s] = (k < o && Iw < Q) ? xo[k * Q + Iw] : 0.0;
+    xb[s] = (T)((k < o && Iw < Q) ? xo[k * Q + Iw] : 0.0);
   }
 
   // element q of this thread's share of a J block: Rx / xo row k, column jr; z row I0 + iz, column jz
@@ -102,36 +116,39 @@ __global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, in
 #pragma unroll
     for (int q = 0; q < NRX; ++q) {
       const int e = t + NT * q;
-      rx_s[buf][e] = prx[q];
-      xj_s[buf][(e % BJ) * (OP + 1) + e / BJ] = pxj[q];
+      rx_s[buf][PR == BJ ? e : (e / BJ) * PR + e % BJ] = (T)prx[q];
+      xj_s[buf][(e % BJ) * PJ + e / BJ] = (T)pxj[q];
     }
 #pragma unroll
     for (int q = 0; q < NZ; ++q) {
       const int e = t + NT * q;
-      z_s[buf][(e % BJ) * BI + e / BJ] = pz[q];
+      z_s[buf][(e % BJ) * PZ + e / BJ] = (T)pz[q];
     }
   };
 
-  d4 acc[OB];
+  V4 acc[OB];
 #pragma unroll
-  for (int b = 0; b < OB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < OB; ++b) acc[b] = V4{0, 0, 0, 0};
+  auto mfma = [](T a, T b, V4 c) {
+    if constexpr (F32) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  };
+  // Ft row of output element r of this lane (and so the J of k-step r's row lk)
+  auto jrow = [&](int r) { return F32 ? 4 * lk + r : lk + 4 * r; };
 
   auto compute = [&](int buf) {
     // Ft[J][I] for J in this block (rows), this wave's 16 I (columns)
-    d4 ft = d4{0.0, 0.0, 0.0, 0.0};
+    V4 ft = V4{0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < KST; ++s)
-      ft = __builtin_amdgcn_mfma_f64_16x16x4f64(rx_s[buf][(4 * s + lk) * BJ + lr], xb[s], ft, 0, 0, 0);
-    // scale by z[I][J]: element r is (J = lk + 4 r, I = 16 w + lr)
+    for (int s = 0; s < KST; ++s) ft = mfma(rx_s[buf][(4 * s + lk) * PR + lr], xb[s], ft);
+    // scale by z[I][J]: element r is (J = jrow(r), I = 16 w + lr)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) ft[r] *= z_s[buf][(lk + 4 * r) * BI + 16 * w + lr];
+    for (int r = 0; r < 4; ++r) ft[r] *= z_s[buf][jrow(r) * PZ + 16 * w + lr];
     // Gt[i][I] += sum_J xo[i][J] Ft[J][I]; k-step r uses ft[r] as its B element
 #pragma unroll
     for (int b = 0; b < OB; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xj_s[buf][(4 * r + lk) * (OP + 1) + 16 * b + lr], ft[r], acc[b],
-                                                      0, 0, 0);
+      for (int r = 0; r < 4; ++r) acc[b] = mfma(xj_s[buf][jrow(r) * PJ + 16 * b + lr], ft[r], acc[b]);
   };
 
   const int64_t nb = (Q + BJ - 1) / BJ;
@@ -148,28 +165,34 @@ __global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, in
   }
   compute(buf);
 
-  // output element r of block b: i = 16 b + lk + 4 r, I = Iw
+  // output element r of block b: i = 16 b + jrow(r), I = Iw
   if (Iw < Q) {
 #pragma unroll
     for (int b = 0; b < OB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = 16 * b + lk + 4 * r;
-        if (i < o) out[i * Q + Iw] = acc[b][r];
+        const int64_t i = 16 * b + jrow(r);
+        if (i < o) out[i * Q + Iw] = (double)acc[b][r];
       }
   }
 }
 
-template <int OB, int KST = 4 * OB>
-hipError_t launch(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx, double* Gt,
-                  hipStream_t s) {
+template <int OB, int KST, bool F32>
+hipError_t launch_k(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx, double* Gt,
+                    hipStream_t s) {
   const int64_t ti = (Q + BI - 1) / BI;
   // byte offsets within a J block stay below 2^31 (the buffer range)
   if (ti > 2147483647LL || nx > 65535 || 8 * (BI + 1) * Q >= (int64_t(1) << 31) || 8 * (16 * OB + 1) * Q >= (int64_t(1) << 31))
     return hipErrorInvalidValue;
   if (4 * KST < o) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((exch_kernel<OB, KST>), dim3((unsigned)ti, (unsigned)nx), dim3(NT), 0, s, o, Q, xo, z, Rx, Gt);
+  hipLaunchKernelGGL((exch_kernel<OB, KST, F32>), dim3((unsigned)ti, (unsigned)nx), dim3(NT), 0, s, o, Q, xo, z, Rx,
+                     Gt);
   return hipGetLastError();
+}
+template <int OB, int KST = 4 * OB>
+hipError_t launch(bool f32, int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx,
+                  double* Gt, hipStream_t s) {
+  return f32 ? launch_k<OB, KST, true>(o, Q, nx, xo, z, Rx, Gt, s) : launch_k<OB, KST, false>(o, Q, nx, xo, z, Rx, Gt, s);
 }
 
 }  // namespace
@@ -177,17 +200,17 @@ hipError_t launch(int64_t o, int64_t Q, int64_t nx, const double* xo, const doub
 bool exch_supported(int64_t o) { return o >= 1 && o <= 128; }
 
 hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx,
-                      double* Gt, hipStream_t s) {
+                      double* Gt, bool f32, hipStream_t s) {
   if (nx <= 0 || Q <= 0) return hipSuccess;
-  if (o <= 16) return launch<1>(o, Q, nx, xo, z, Rx, Gt, s);
-  if (o <= 32) return launch<2>(o, Q, nx, xo, z, Rx, Gt, s);
+  if (o <= 16) return launch<1>(f32, o, Q, nx, xo, z, Rx, Gt, s);
+  if (o <= 32) return launch<2>(f32, o, Q, nx, xo, z, Rx, Gt, s);
   if (o <= 64) {  // the k-step count of the first product fitted to o in steps of 8
-    if (o <= 40) return launch<4, 10>(o, Q, nx, xo, z, Rx, Gt, s);
-    if (o <= 48) return launch<4, 12>(o, Q, nx, xo, z, Rx, Gt, s);
-    if (o <= 56) return launch<4, 14>(o, Q, nx, xo, z, Rx, Gt, s);
-    return launch<4>(o, Q, nx, xo, z, Rx, Gt, s);
+    if (o <= 40) return launch<4, 10>(f32, o, Q, nx, xo, z, Rx, Gt, s);
+    if (o <= 48) return launch<4, 12>(f32, o, Q, nx, xo, z, Rx, Gt, s);
+    if (o <= 56) return launch<4, 14>(f32, o, Q, nx, xo, z, Rx, Gt, s);
+    return launch<4>(f32, o, Q, nx, xo, z, Rx, Gt, s);
   }
-  if (o <= 128) return launch<8>(o, Q, nx, xo, z, Rx, Gt, s);
+  if (o <= 128) return launch<8>(f32, o, Q, nx, xo, z, Rx, Gt, s);
   return hipErrorInvalidValue;
 }
 

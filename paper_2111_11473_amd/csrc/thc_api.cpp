@@ -775,8 +775,8 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     // exchange parts (Alg. 7): fused on chip when o fits the kernel's tile, else two GEMMs per X chunk
     if (exch_supported(o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE)) {
       Scope sc(ctx, "exch");
-      HIPCHK(exch_fused(o, Q, P, xo, ctx->z, ctx->Rx, ctx->Gt, s));
-      HIPCHK(exch_fused(o, Q, P, xo, ctx->z, ctx->Sx, ctx->Gts, s));
+      HIPCHK(exch_fused(o, Q, P, xo, ctx->z, ctx->Rx, ctx->Gt, ctx->mixed, s));
+      HIPCHK(exch_fused(o, Q, P, xo, ctx->z, ctx->Sx, ctx->Gts, ctx->mixed, s));
     } else
     for (int64_t X0 = 0; X0 < P; X0 += ctx->Xc) {
       const int64_t xc = std::min(ctx->Xc, P - X0);
