@@ -122,14 +122,15 @@ hipError_t mlp_infer_bf16(int64_t rows, int64_t n_in, int64_t n_out, const float
 // VALU kernel for H^XYZ += sum_I (E^XY F^XZ + E^XZ F^XY) G^YZ (kernels_h.hip).
 // E, F: [Xb/64][ldi][Pp/2][64][2] (X tile, grid point, row pair, X within the tile, row of the
 // pair); G: [I][Pp/16][Pp/8][16][8] (16 x 8 blocks); H: [Pp][Pp][Xb]; tiles from
-// h_tiles(Pp, Xb, slots).  ldi >= nI is the grid-point stride of one X tile of E and F.
+// h_tiles(Pp, Xb, slots).  ldi >= nI is the grid-point stride of one X tile of E and F.  fresh:
+// H = the sum instead of H += (every element of H is written: the tiles cover all of it).
 hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const double* E, const double* F,
                         const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
-                        hipStream_t s);
+                        bool fresh, hipStream_t s);
 // The same with E, F stored in FP32 (mixed-precision path); arithmetic and H stay FP64.
 hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
                           const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
-                          hipStream_t s);
+                          bool fresh, hipStream_t s);
 constexpr int H_GBLK = 8;  // column width of the G blocks
 std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots);
 int64_t h_slots_per_xcd();

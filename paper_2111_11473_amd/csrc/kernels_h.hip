@@ -161,11 +161,13 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
                                                                        const double* __restrict__ G,
                                                                        double* __restrict__ H,
                                                                        const uint32_t* __restrict__ tiles,
-                                                                       int rev) {
+                                                                       int flags) {
   using C = Geo<NWZ, NS, TE>;
   __shared__ __attribute__((aligned(16))) char lds[NS * C::STAGE_B];
   const uint32_t tile = tiles[blockIdx.x];
   if (tile & EMPTY) return;  // whole workgroup, before any barrier
+  const bool rev = flags & 1;    // walk the grid points backwards
+  const bool fresh = flags & 2;  // first chunk: H starts from zero instead of being read
   const int Yb = tile & 511, Zb = (tile >> 9) & 511, zs = (tile >> 18) & 3, xt = (tile >> 20) & 1023;
   const bool mirror = Yb != Zb;
   const int y0 = Yb * BY, z0 = Zb * BY + zs * C::BZ, X0 = xt * LANES;
@@ -190,7 +192,12 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
   const double* Hm = H + ((int64_t)(z0 + lz0) * Pp + y0 + ly0) * Xb + X0;
   const int64_t hw_bytes = ((int64_t)(WY - 1) * Pp + WZ) * Xb * 8;
   const int64_t hm_bytes = ((int64_t)(WZ - 1) * Pp + WY) * Xb * 8;
-  {
+  if (fresh) {
+#pragma unroll
+    for (int j = 0; j < WY; ++j)
+#pragma unroll
+      for (int k = 0; k < WZ; ++k) acc[j][k] = accm[j][k] = 0.0;
+  } else {
     const __amdgpu_buffer_rsrc_t rh = rsrc(Hw, hw_bytes);
     const __amdgpu_buffer_rsrc_t rm = rsrc(Hm, hm_bytes);
 #pragma unroll
@@ -369,7 +376,8 @@ std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb, int64_t slots) {
 
 template <int NWZ, int NS, typename TE>
 hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const TE* E, const TE* F,
-                  const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots, hipStream_t s) {
+                  const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots, bool fresh,
+                  hipStream_t s) {
   if (Pp % BY != 0 || Pp <= 0 || Pp > 8192 || Xb % LANES != 0 || Xb > (Pp + LANES - 1) / LANES * LANES || Xb <= 0 || ntiles <= 0 || ntiles > 2147483647LL ||
       nI < 0 || ldi < nI || slots < 1 || ntiles % (8 * slots) != 0)
     return hipErrorInvalidValue;
@@ -379,7 +387,7 @@ hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const TE* E, 
   const int64_t gen = 8 * slots;
   for (int64_t t0 = 0; t0 < ntiles; t0 += gen) {
     hipLaunchKernelGGL((h_kernel<NWZ, NS, TE>), dim3((unsigned)gen), dim3(Geo<NWZ, NS, TE>::NTHREADS), 0, s,
-                       (int)Pp, (int)Xb, ldi, nI, E, F, G, H, tiles + t0, (int)((t0 / gen) & 1));
+                       (int)Pp, (int)Xb, ldi, nI, E, F, G, H, tiles + t0, (int)((t0 / gen) & 1) | (fresh ? 2 : 0));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -410,14 +418,14 @@ std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots) { return ti
 
 hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const double* E, const double* F,
                         const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
-                        hipStream_t s) {
-  return launch<H_NWZ, H_NS, double>(Pp, Xb, ldi, nI, E, F, G, H, tiles, ntiles, slots, s);
+                        bool fresh, hipStream_t s) {
+  return launch<H_NWZ, H_NS, double>(Pp, Xb, ldi, nI, E, F, G, H, tiles, ntiles, slots, fresh, s);
 }
 
 hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
                           const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
-                          hipStream_t s) {
-  return launch<H_NWZ, H_NS32, float>(Pp, Xb, ldi, nI, E, F, G, H, tiles, ntiles, slots, s);
+                          bool fresh, hipStream_t s) {
+  return launch<H_NWZ, H_NS32, float>(Pp, Xb, ldi, nI, E, F, G, H, tiles, ntiles, slots, fresh, s);
 }
 
 }  // namespace thc

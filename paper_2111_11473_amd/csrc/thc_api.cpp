@@ -735,10 +735,10 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
           sc.launches = ctx->nhtiles / (8 * ctx->hslots);  // one dispatch per generation of tiles
           if (ctx->mixed)
             HIPCHK(h_accumulate32(Pp, Xb, ctx->Ic, ic, ctx->Ec32, ctx->Fc32, ctx->Gc, ctx->Hb, ctx->htiles,
-                                  ctx->nhtiles, ctx->hslots, s));
+                                  ctx->nhtiles, ctx->hslots, I0 == 0, s));
           else
             HIPCHK(h_accumulate(Pp, Xb, ctx->Ic, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles,
-                                ctx->nhtiles, ctx->hslots, s));
+                                ctx->nhtiles, ctx->hslots, I0 == 0, s));
         }
       }
       // I^X_ia = sum_YZ y_i^Z y_a^Y H^XYZ ; sigma^XW += sum_ia y_i^W y_a^W I^X_ia  (Alg. 6)
@@ -746,7 +746,6 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       RCHK(gemm(ctx, batched(mk(o, xb, P, Yo, P, false, ctx->Hb, Xb, false, ctx->R1, Xb), P, 0, Pp * Xb, o * Xb)));
       RCHK(gemm(ctx, batched(mk(v, xb, P, Yv, P, false, ctx->R1, o * Xb, false, ctx->I6, Xb), o, 0, Xb, v * Xb)));
       RCHK(gemm(ctx, mk(xb, P, ov, ctx->I6, Xb, true, ctx->Bkr, P, false, ctx->sig + X0 * P, P, 1.0, 1.0)));
-      RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
     }
   }
 
