@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
     for (int j = 0; j < TJ; ++j) acc[i][j] = ACC{0, 0, 0, 0};
 
   const int lr = lane & 15, lk = lane >> 4;
-  // nk: k of the slab that hold data (the rest are zeros); a k-step of 4 is skipped when past it
+  // nk: how many k of the slab hold data (the rest are zeros); k-steps of 4 past them are skipped
   auto compute = [&](int buf, int nk = BK) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {

@@ -12,15 +12,15 @@
 // slices of Rx^X and xo and the 64 x 16 slice of z for the next J block are prefetched into
 // registers while the current one is used from LDS.
 // The slices are fetched with buffer loads whose out-of-range lanes read zero (k >= o, J >= Q,
-// I >= Q), so the padded k-steps multiply zeros and the loop has no branches; two LDS buffers, one
-// barrier per J block.
+// I >= Q), so the padded k-steps that remain multiply zeros and the loop has no branches; two LDS
+// buffers, one barrier per J block.
 // Layouts (row-major): xo [o][Q]; z [Q][Q]; Rx, Gt [X][o][Q].  Requires o <= 16 OB.
 //
 // F32 (the mixed-precision path): the slices are rounded to FP32 on their way into LDS and both
 // products run on v_mfma_f32_16x16x4f32 with FP32 accumulation.  There output element r of a
-// lane is row 4 (lane / 16) + r, so the lane holds Ft rows J = 4 lk + r and k-step r of the second
-// product takes J in that order (row lk of the step is J = 4 lk + r); the A operand, xo[i][J], is
-// read in the same order.  The FP32 LDS rows are padded so that the four lane groups of a read
+// lane is row 4 (lane / 16) + r, so lane (lk = lane / 16) holds Ft rows J = 4 lk + r and k-step r
+// of the second product takes J in that order (row lk of the step is J = 4 lk + r); the A operand,
+// xo[i][J], is read in the same order.  The FP32 LDS rows are padded so that the four lane groups of a read
 // fall on distinct banks.
 #include <type_traits>
 

@@ -34,9 +34,10 @@
 // generation starts on the points its predecessor read last (still in the last-level cache).
 // One workgroup per tile measured faster than a persistent grid walking the table.
 // Layouts (Y, Z ranks zero-padded to Pp, a multiple of 16; X restricted to a block of Xb ranks, a
-// multiple of 64 and at most Pp rounded up to 64): E, F: [Xb/64][ldi][Pp/2][64][2] (E_I^XY at [X/64][I][Y/2][X%64][Y%2]);
-// G: [I][Pp/16][Pp/8][16][8] (G_I^YZ at [I][Y/16][Z/8][Y%16][Z%8]); H: [Pp][Pp][Xb] (H^XYZ at
-// [Y][Z][X]).
+// multiple of 64 and at most Pp rounded up to 64):
+//   E, F: [Xb/64][ldi][Pp/2][64][2] (E_I^XY at [X/64][I][Y/2][X%64][Y%2]);
+//   G: [I][Pp/16][Pp/8][16][8] (G_I^YZ at [I][Y/16][Z/8][Y%16][Z%8]);
+//   H: [Pp][Pp][Xb] (H^XYZ at [Y][Z][X]).
 #include <vector>
 
 #include "internal.h"
