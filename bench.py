@@ -114,8 +114,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        sys.exit("bench.py: this build runs the THC-CCSD hot path on one GPU only; "
-                 "multi-GPU runs are not part of it (use --gpus 1)")
+        sys.exit("bench.py: the THC-CCSD hot path runs on one GPU; multi-GPU runs are not "
+                 "implemented (use --gpus 1)")
 
     import numpy as np
     import torch

@@ -9,8 +9,8 @@ Protocol.  A system is solved from the plain MP2 guess; its per-rank-index featu
 targets (c*_P, delta*_P) become training rows.  A held-out system is solved twice: plainly, and
 from the predicted start diag(1 + c) T^0 diag(1 + c) with denominators shifted by delta; if the
 learned attempt does not converge it is rerun from the plain guess (fallback) and its iterations
-are counted in full.  Both solves use the same convergence test, so the converged residual is
-the judge.
+are counted in full.  Both solves use the same convergence test, so the converged residual
+decides whether a start was good.
 
 Run:  python -m paper_2111_11473_amd.learned --train 200 --heldout 56 --o-min 10 --o-max 24
 """
