@@ -60,7 +60,10 @@ def _state(s, Z0, seed):
                                    (4, 16, 16, 16, False, False),
                                    # enough tiles for the 128 x 128 kernel, ragged in M, N and K
                                    (20, 517, 515, 131, False, False), (40, 300, 390, 77, True, True),
-                                   (32, 260, 600, 45, True, False), (32, 600, 260, 45, False, True)])
+                                   (32, 260, 600, 45, True, False), (32, 600, 260, 45, False, True),
+                                   # at most 64 rows, long K: the 64 x 128 tiles, ragged in every dimension
+                                   (6, 50, 1000, 300, False, False), (5, 33, 700, 450, False, True),
+                                   (4, 64, 257, 130, True, False), (3, 17, 900, 1000, True, True)])
 def test_dgemm_matches_numpy(thc, shape):
     nb, M, N, K, tA, tB = shape
     _say("dgemm", shape)
