@@ -285,6 +285,7 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
   int buf = 0;
   auto consume = [&]() {
     __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(1);  // the FMAs before another wave's copies when both are ready
     const char* __restrict__ st = lds + buf * C::STAGE_B;
     const double* __restrict__ sg = (const double*)(st + C::G_B);
     const double* __restrict__ sgm = (const double*)(st + C::GM_B);
@@ -319,6 +320,7 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
     h_row<4>(acc[5], accm[5], ey[2].y, fy[2].y, ezs, fzs, g[1], gm[1]);
     h_row<8>(acc[6], accm[6], ey[3].x, fy[3].x, ezs, fzs, g[1], gm[1]);
     h_row<12>(acc[7], accm[7], ey[3].y, fy[3].y, ezs, fzs, g[1], gm[1]);
+    __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_sched_barrier(0);
   };
   // Steady state: every grid point also issues the stage D ahead, and the stage after the next
