@@ -137,6 +137,27 @@ int thc_set_state(thc_ctx* ctx, const double* Z, const double* t1);
 /* Device working memory held by the context (bytes), valid after thc_build_factors. */
 int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes);
 
+/* How the context evaluates a residual, valid after thc_build_factors: the blocking of the
+ * paper's loops (the fused pass over Cholesky vectors A of Alg. 1-3 and 8, the X-blocked and
+ * grid-chunked Alg. 6, the X-chunked Alg. 7) and the kernel paths they take. */
+typedef struct thc_plan_info {
+  int64_t a_block;        /* Cholesky vectors per fused-pass block */
+  int64_t alg1_splits;    /* K slices of the symmetric product sum_A C^A T C^A^T (Alg. 1) */
+  int64_t alg1_tile;      /* tile edge of that product on the matrix cores (64 or 128) */
+  int64_t x_block;        /* amplitude ranks X per H block (Alg. 6) */
+  int64_t x_blocks;       /* H blocks per residual */
+  int64_t i_chunk;        /* ERI grid points per H-kernel pass */
+  int64_t i_chunks;       /* H-kernel passes per H block */
+  int64_t h_generations;  /* H-kernel dispatches per pass (one per generation of resident tiles; odd
+                             generations walk the grid points backwards) */
+  int64_t h_tiles;        /* H-kernel tiles per pass (X tile x Y block x Z slice, Z >= Y) */
+  int64_t x_chunk;        /* amplitude ranks X per Alg. 7 chunk */
+  int32_t exchange_fused; /* 1: the fused Alg. 7 exchange kernel, 0: its two-GEMM form */
+  int32_t lvv_resident;   /* 1: the vv Cholesky block is held in device memory */
+  uint64_t device_bytes;  /* device working memory */
+} thc_plan_info;
+int thc_plan(const thc_ctx* ctx, thc_plan_info* out);
+
 /* Kernel timing with HIP events on the context stream.  thc_profile(ctx, 1) starts recording
  * (and clears earlier records); thc_profile_get synchronizes and returns, for the kernel
  * class `name` ("h_kernel", "gemm", "misc", or "residual" for whole residual evaluations),

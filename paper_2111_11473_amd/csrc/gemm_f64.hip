@@ -497,7 +497,24 @@ hipError_t launch_btile(const Gemm& g, int64_t kchunk, hipStream_t s) {
   return hipGetLastError();
 }
 
+// 128 x 128 tiles need enough of them and a K slice long enough to amortize their prologue and
+// epilogue; short-K products run on 64 x 64 tiles, up to eight workgroups per CU.
+bool big_tiles(const Gemm& g, int64_t kchunk) {
+  const int64_t t128 = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch * g.ksplit;
+  return g.M >= 96 && g.N >= 96 && t128 >= 480 && kchunk > 64;
+}
+
 }  // namespace
+
+int gemm_tile_edge_split(const Gemm& g) {
+  const int64_t ks = g.ksplit < 1 ? 1 : g.ksplit;
+  int64_t kchunk = (g.K + ks - 1) / ks;
+  kchunk = ((kchunk + BK - 1) / BK) * BK;
+  if (kchunk == 0) kchunk = BK;
+  Gemm h = g;
+  h.ksplit = (int)ks;
+  return big_tiles(h, kchunk) ? 128 : 64;
+}
 
 hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   Gemm g = g0;
@@ -563,10 +580,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   int64_t kchunk = (g.K + g.ksplit - 1) / g.ksplit;
   kchunk = ((kchunk + BK - 1) / BK) * BK;
   if (kchunk == 0) kchunk = BK;
-  const int64_t t128 = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch * g.ksplit;
-  // 128 x 128 tiles need enough of them and a K long enough to amortize their prologue and
-  // epilogue; short-K products run on 64 x 64 tiles, up to eight workgroups per CU
-  const bool big = g.M >= 96 && g.N >= 96 && t128 >= 480 && kchunk > 64;
+  const bool big = big_tiles(g, kchunk);
   if (big && (g.M + 127) / 128 > 65535) return hipErrorInvalidValue;
   if (!big && (g.M + 63) / 64 > 65535) return hipErrorInvalidValue;
   if (g.bf16x3) return big ? launch_btile<128, 128>(g, kchunk, s) : launch_btile<64, 64>(g, kchunk, s);

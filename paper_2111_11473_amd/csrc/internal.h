@@ -47,6 +47,9 @@ struct Gemm {
 };
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
+// Tile edge (128 or 64) that gemm_f64 runs a product on when its K split is given explicitly
+// (g.ksplit; no batch folding or automatic split applies, as for the symmetric upper products).
+int gemm_tile_edge_split(const Gemm& g);
 
 // Elementwise / reduction kernels (kernels_misc.hip).
 hipError_t k_form_C(int64_t P, int64_t nb, const double* Bvv, const double* Boo, const double* Go,

@@ -89,7 +89,8 @@ struct thc_ctx {
   float *Ec32 = nullptr, *Fc32 = nullptr;  // FP32 H-kernel operands (mixed precision only)
   bool has_shift = false;
   uint32_t* htiles = nullptr;  // H-kernel tile table
-  int64_t nhtiles = 0, hslots = 0;
+  int64_t nhtiles = 0, hslots = 0, hfilled = 0;  // table length (with empty slots), slots per XCD, tiles
+  int alg1_tile = 64;          // tile edge of the symmetric Alg. 1 product
   double *R1 = nullptr, *I6 = nullptr;
   // Alg. 7
   double *U7 = nullptr, *S7 = nullptr, *R7 = nullptr, *Rx = nullptr, *Sx = nullptr, *Cx = nullptr, *Dx = nullptr;
@@ -386,6 +387,14 @@ int plan_and_alloc(thc_ctx* ctx) {
   // at two per CU), counting the tiles on and above the diagonal (the product is symmetric)
   const int64_t nt128 = (P + 127) / 128, t128 = nt128 * (nt128 + 1) / 2;
   ctx->KS = std::max<int64_t>(1, std::min<int64_t>(16, 512 / t128));
+  {
+    Gemm g;  // the first block's sum_A C^A T C^A^T, as residual_impl issues it
+    g.M = g.N = P;
+    g.K = nb * P;
+    g.ksplit = (int)ctx->KS;
+    g.upper = true;
+    ctx->alg1_tile = gemm_tile_edge_split(g);
+  }
   // H block over X: whole rank when it fits in ~40 GB
   int64_t Xb = op.x_block;
   if (Xb <= 0) {
@@ -477,6 +486,8 @@ int plan_and_alloc(thc_ctx* ctx) {
     RCHK(alloc(ctx, &tb, (tiles.size() + 1) / 2));
     ctx->htiles = reinterpret_cast<uint32_t*>(tb);
     ctx->nhtiles = (int64_t)tiles.size();
+    ctx->hfilled = 0;
+    for (uint32_t t : tiles) ctx->hfilled += (t & 0x80000000u) ? 0 : 1;
     RCHK(h2d(ctx, ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t)));
   }
   if (op.precision >= 1) {  // FP32 E, F for the mixed-precision H-kernel
@@ -945,36 +956,28 @@ int mlp_reserve(thc_mlp* ctx, int64_t rows) {
   return THC_OK;
 }
 
-// forward in FP32: xn, z1, h1, z2, h2, yn (normalized outputs)
-int mlp_fwd(thc_mlp* ctx, const float* X, int64_t R) {
+// Activations of one FP32 forward pass of R rows.
+struct MlpActs {
+  float *xn, *z1, *h1, *z2, *h2, *yn;
+};
+
+// forward in FP32 into a: xn, z1, h1, z2, h2, yn (normalized outputs)
+int mlp_fwd_into(thc_mlp* ctx, const float* X, int64_t R, const MlpActs& a) {
   const int64_t ni = ctx->n_in, w = ctx->w, no = ctx->n_out;
   const float *W1 = ctx->p, *b1 = W1 + ni * w, *W2 = b1 + w, *b2 = W2 + w * w, *W3 = b2 + w, *b3 = W3 + w * no;
   hipStream_t s = ctx->stream;
-  HIPCHK(mlp_normalize(R, ni, X, ctx->mu_in, ctx->sd_in, ctx->xn, s));
-  HIPCHK(mlp_sgemm(false, false, 1, R, w, ni, ctx->xn, ni, W1, w, ctx->h1, w, b1, ctx->z1, w, s));
-  HIPCHK(mlp_sgemm(false, false, 1, R, w, w, ctx->h1, w, W2, w, ctx->h2, w, b2, ctx->z2, w, s));
-  HIPCHK(mlp_sgemm(false, false, 2, R, no, w, ctx->h2, w, W3, no, ctx->yn, no, b3, nullptr, 0, s));
+  HIPCHK(mlp_normalize(R, ni, X, ctx->mu_in, ctx->sd_in, a.xn, s));
+  HIPCHK(mlp_sgemm(false, false, 1, R, w, ni, a.xn, ni, W1, w, a.h1, w, b1, a.z1, w, s));
+  HIPCHK(mlp_sgemm(false, false, 1, R, w, w, a.h1, w, W2, w, a.h2, w, b2, a.z2, w, s));
+  HIPCHK(mlp_sgemm(false, false, 2, R, no, w, a.h2, w, W3, no, a.yn, no, b3, nullptr, 0, s));
   return THC_OK;
 }
 
-// loss and gradient (into ctx->g) of the mean squared error on normalized targets
-int mlp_bwd(thc_mlp* ctx, const float* X, const float* T, int64_t R) {
-  const int64_t ni = ctx->n_in, w = ctx->w, no = ctx->n_out;
-  const float *W2 = ctx->p + ni * w + w, *W3 = W2 + w * w + w;
-  float *gW1 = ctx->g, *gb1 = gW1 + ni * w, *gW2 = gb1 + w, *gb2 = gW2 + w * w, *gW3 = gb2 + w, *gb3 = gW3 + w * no;
-  hipStream_t s = ctx->stream;
-  RCHK(mlp_fwd(ctx, X, R));
-  HIPCHK(mlp_mse_grad(R, no, ctx->yn, T, ctx->mu_out, ctx->sd_out, ctx->dy, ctx->part, MLP_PARTS, ctx->loss, s));
-  HIPCHK(mlp_sgemm(true, false, 0, w, no, R, ctx->h2, w, ctx->dy, no, gW3, no, nullptr, nullptr, 0, s));
-  HIPCHK(mlp_colsum(R, no, ctx->dy, gb3, s));
-  HIPCHK(mlp_sgemm(false, true, 3, R, w, no, ctx->dy, no, W3, no, ctx->d2, w, nullptr, ctx->z2, w, s));
-  HIPCHK(mlp_sgemm(true, false, 0, w, w, R, ctx->h1, w, ctx->d2, w, gW2, w, nullptr, nullptr, 0, s));
-  HIPCHK(mlp_colsum(R, w, ctx->d2, gb2, s));
-  HIPCHK(mlp_sgemm(false, true, 3, R, w, w, ctx->d2, w, W2, w, ctx->d1, w, nullptr, ctx->z1, w, s));
-  HIPCHK(mlp_sgemm(true, false, 0, ni, w, R, ctx->xn, ni, ctx->d1, w, gW1, w, nullptr, nullptr, 0, s));
-  HIPCHK(mlp_colsum(R, w, ctx->d1, gb1, s));
-  return THC_OK;
+// forward in FP32 into the network's own activation buffers
+int mlp_fwd(thc_mlp* ctx, const float* X, int64_t R) {
+  return mlp_fwd_into(ctx, X, R, MlpActs{ctx->xn, ctx->z1, ctx->h1, ctx->z2, ctx->h2, ctx->yn});
 }
+
 }  // namespace
 
 extern "C" {
@@ -1347,6 +1350,27 @@ int thc_history(const thc_ctx* ctx, int max, double* energy, double* rnorm, doub
 int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes) {
   if (!ctx || !bytes) return THC_EINVAL;
   *bytes = ctx->bytes;
+  return THC_OK;
+}
+
+int thc_plan(const thc_ctx* ctx, thc_plan_info* out) {
+  if (!ctx || !out) return THC_EINVAL;
+  if (!ctx->built) return THC_ESTATE;
+  thc_plan_info p{};
+  p.a_block = ctx->nb;
+  p.alg1_splits = ctx->KS;
+  p.alg1_tile = ctx->alg1_tile;
+  p.x_block = ctx->Xb;
+  p.x_blocks = (ctx->P + ctx->Xb - 1) / ctx->Xb;
+  p.i_chunk = ctx->Ic;
+  p.i_chunks = (ctx->Q + ctx->Ic - 1) / ctx->Ic;
+  p.h_generations = ctx->nhtiles / (8 * ctx->hslots);
+  p.h_tiles = ctx->hfilled;
+  p.x_chunk = ctx->Xc;
+  p.exchange_fused = exch_supported(ctx->o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE);
+  p.lvv_resident = 1;
+  p.device_bytes = ctx->bytes;
+  *out = p;
   return THC_OK;
 }
 

@@ -106,6 +106,10 @@ CONFIGS = {
     "occ46": Config("occ46", 46, 24, 120, 110, 260, 30.0, 1015),
     "occ53": Config("occ53", 53, 20, 110, 100, 240, 30.0, 1016),
     "occ60": Config("occ60", 60, 18, 110, 100, 240, 30.0, 1017),
+    # a rank large enough for the benchmark's kernel paths with an oracle that still runs in
+    # seconds: 704-padded H ranks (about 43 H-kernel generations, so the backward grid-point walk
+    # of odd generations), 128 x 128 tiles for the split symmetric Alg. 1 product
+    "wide": Config("wide", 8, 100, 100, 700, 780, 30.0, 1020),
     # degenerate sizes: one occupied orbital; a pair basis and ERI grid as large as the o v
     # pairs (complete: THC-CCSD is then CD-CCSD)
     "one_occ": Config("one_occ", 1, 9, 12, 7, 9, 30.0, 1014),

@@ -29,7 +29,7 @@ TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TER
 SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_history",
            "thc_history_precision",
            "thc_energy",
-           "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
+           "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
            "thc_last_error", "thc_destroy",
            "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
            "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
@@ -43,6 +43,13 @@ class Options(C.Structure):
                 ("singles", C.c_int32), ("diis_max", C.c_int32), ("tol_energy", C.c_double),
                 ("a_block", C.c_int64), ("i_chunk", C.c_int64), ("x_block", C.c_int64), ("x_chunk", C.c_int64),
                 ("precision", C.c_int32), ("flags", C.c_int32)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("a_block", C.c_int64), ("alg1_splits", C.c_int64), ("alg1_tile", C.c_int64),
+                ("x_block", C.c_int64), ("x_blocks", C.c_int64), ("i_chunk", C.c_int64), ("i_chunks", C.c_int64),
+                ("h_generations", C.c_int64), ("h_tiles", C.c_int64), ("x_chunk", C.c_int64),
+                ("exchange_fused", C.c_int32), ("lvv_resident", C.c_int32), ("device_bytes", C.c_uint64)]
 
 
 class ThcError(RuntimeError):
@@ -74,6 +81,7 @@ def load(path: str = LIB_PATH):
     lib.thc_get_state.argtypes = [VP, P, P]
     lib.thc_set_state.argtypes = [VP, P, P]
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
+    lib.thc_plan.argtypes = [VP, C.POINTER(PlanInfo)]
     lib.thc_profile.argtypes = [VP, C.c_int]
     lib.thc_profile_get.argtypes = [VP, C.c_char_p, C.POINTER(D), C.POINTER(I64)]
     lib.thc_profile_flops.argtypes = [VP, C.POINTER(D), C.POINTER(D), C.POINTER(D)]
@@ -260,6 +268,12 @@ class THC:
         b = C.c_size_t(0)
         self._check(self.lib.thc_memory_bytes(self.ctx, C.byref(b)), "thc_memory_bytes")
         return b.value
+
+    def plan(self):
+        """The residual's blocking and kernel paths (a dict of PlanInfo's fields)."""
+        p = PlanInfo()
+        self._check(self.lib.thc_plan(self.ctx, C.byref(p)), "thc_plan")
+        return {name: getattr(p, name) for name, _ in PlanInfo._fields_}
 
     # -- learned guess ------------------------------------------------------------------
     def guess_features(self):

@@ -104,13 +104,7 @@ def test_mp2_guess_and_energy(thc, name):
     assert abs(e_gpu - e_ref) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["small", "tiny", "medium", "occ40", "occ46", "occ53", "occ60", "occ70", "one_occ", "complete"])
-def test_residual_terms_match_oracle(thc, name):
-    """Each term group of the projected residual (Alg. 1-10) against the dense oracle, at a
-    state with t1 != 0 (T1-dressed integrals exercised)."""
-    cfg = synth.CONFIGS[name]
-    _say("terms", name)
-    s, ctx, Z0 = _make(thc, cfg)
+def _check_terms(thc, cfg, s, ctx, Z0):
     Z, t1 = _state(s, Z0, 3)
     z, _ = oracle.eri_fit(s["L"], cfg.o, s["xo"], s["xv"])
     V = oracle.eri_thc_dense(s["xo"], s["xv"], z)
@@ -136,6 +130,33 @@ def test_residual_terms_match_oracle(thc, name):
     ctx.set_state(Zd, t1d)
     e_ref = ccsd.energy(s["L"], t1, oracle.amplitudes(s["Xo"], s["Xv"], Z))
     assert abs(ctx.energy() - e_ref) < 1e-10 * max(1.0, abs(e_ref))
+
+
+@pytest.mark.parametrize("name", ["small", "tiny", "medium", "occ40", "occ46", "occ53", "occ60", "occ70", "one_occ", "complete"])
+def test_residual_terms_match_oracle(thc, name):
+    """Each term group of the projected residual (Alg. 1-10) against the dense oracle, at a
+    state with t1 != 0 (T1-dressed integrals exercised)."""
+    cfg = synth.CONFIGS[name]
+    _say("terms", name)
+    s, ctx, Z0 = _make(thc, cfg)
+    _check_terms(thc, cfg, s, ctx, Z0)
+
+
+@pytest.mark.parametrize("i_chunk", [0, 200])
+def test_wide_rank_paths_match_oracle(thc, i_chunk):
+    """Every term group at a rank (nP = 700) that takes the kernel paths of the benchmark
+    workload, against the dense oracle: the H-kernel over many generations of resident tiles (odd
+    ones walking the grid points backwards), several grid-point chunks (i_chunk = 200: the passes
+    after the first accumulate into H instead of starting it), and the symmetric Alg. 1 product
+    on 128 x 128 tiles with its K split."""
+    cfg = synth.CONFIGS["wide"]
+    _say("terms wide i_chunk", i_chunk)
+    s, ctx, Z0 = _make(thc, cfg, i_chunk=i_chunk)
+    plan = ctx.plan()
+    _say("  plan", plan)
+    assert plan["h_generations"] >= 2 and plan["alg1_tile"] == 128 and plan["alg1_splits"] >= 2
+    assert plan["i_chunks"] == (1 if i_chunk == 0 else 4)
+    _check_terms(thc, cfg, s, ctx, Z0)
 
 
 @pytest.mark.parametrize("singles", [True, False])
