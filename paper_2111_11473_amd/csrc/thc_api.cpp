@@ -978,6 +978,25 @@ int mlp_fwd(thc_mlp* ctx, const float* X, int64_t R) {
   return mlp_fwd_into(ctx, X, R, MlpActs{ctx->xn, ctx->z1, ctx->h1, ctx->z2, ctx->h2, ctx->yn});
 }
 
+// loss and gradient (into ctx->g) of the mean squared error on normalized targets
+int mlp_bwd(thc_mlp* ctx, const float* X, const float* T, int64_t R) {
+  const int64_t ni = ctx->n_in, w = ctx->w, no = ctx->n_out;
+  const float *W2 = ctx->p + ni * w + w, *W3 = W2 + w * w + w;
+  float *gW1 = ctx->g, *gb1 = gW1 + ni * w, *gW2 = gb1 + w, *gb2 = gW2 + w * w, *gW3 = gb2 + w, *gb3 = gW3 + w * no;
+  hipStream_t s = ctx->stream;
+  RCHK(mlp_fwd(ctx, X, R));
+  HIPCHK(mlp_mse_grad(R, no, ctx->yn, T, ctx->mu_out, ctx->sd_out, ctx->dy, ctx->part, MLP_PARTS, ctx->loss, s));
+  HIPCHK(mlp_sgemm(true, false, 0, w, no, R, ctx->h2, w, ctx->dy, no, gW3, no, nullptr, nullptr, 0, s));
+  HIPCHK(mlp_colsum(R, no, ctx->dy, gb3, s));
+  HIPCHK(mlp_sgemm(false, true, 3, R, w, no, ctx->dy, no, W3, no, ctx->d2, w, nullptr, ctx->z2, w, s));
+  HIPCHK(mlp_sgemm(true, false, 0, w, w, R, ctx->h1, w, ctx->d2, w, gW2, w, nullptr, nullptr, 0, s));
+  HIPCHK(mlp_colsum(R, w, ctx->d2, gb2, s));
+  HIPCHK(mlp_sgemm(false, true, 3, R, w, w, ctx->d2, w, W2, w, ctx->d1, w, nullptr, ctx->z1, w, s));
+  HIPCHK(mlp_sgemm(true, false, 0, ni, w, R, ctx->xn, ni, ctx->d1, w, gW1, w, nullptr, nullptr, 0, s));
+  HIPCHK(mlp_colsum(R, w, ctx->d1, gb1, s));
+  return THC_OK;
+}
+
 }  // namespace
 
 extern "C" {
