@@ -235,6 +235,17 @@ int thc_mlp_forward(thc_mlp* net, const float* X, int64_t rows, float* Y);
 int thc_mlp_loss_grad(thc_mlp* net, const float* X, const float* T, int64_t rows, float* loss, float* grad);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the loss above. */
 int thc_mlp_train_step(thc_mlp* net, const float* X, const float* T, int64_t rows, float lr, float* loss);
+/* The FP32 forward pass above without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops): the same kernels and result as
+ * thc_mlp_forward, with the activations in a fixed device array of THC_MLP_SCRATCH_BYTES per GPU
+ * (held until the process ends) instead of buffers the network allocates.  Row limit: about
+ * THC_MLP_SCRATCH_BYTES / (4 (n_in + 2 width + n_out)), less the padding that starts each of the
+ * four activation buffers on a 256-byte boundary (16 008 rows for 10 -> 256 -> 2); more rows
+ * return THC_EINVAL with the limit in thc_mlp_last_error and launch nothing.  The array
+ * is shared by every call on a GPU and keeps the last call's contents (nothing in it has to start
+ * at zero): calls that overlap on one GPU (two streams or two threads) race. */
+#define THC_MLP_SCRATCH_BYTES (32u << 20)
+int thc_mlp_forward_noalloc(thc_mlp* net, const float* X, int64_t rows, float* Y);
 /* BF16 inference on MFMA with FP32 accumulation (width 256, n_in <= 16, n_out <= 16). */
 int thc_mlp_infer(thc_mlp* net, const float* X, int64_t rows, float* Y);
 const char* thc_mlp_last_error(const thc_mlp* net);

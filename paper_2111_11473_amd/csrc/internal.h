@@ -100,6 +100,12 @@ hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const 
 
 // Learned-guess network kernels (mlp.hip).  sgemm epilogues: 0 none, 1 bias + SiLU (pre-activation
 // to Z), 2 bias, 3 times SiLU'(Z).
+// Floats in the per-device scratch array of the allocation-free forward pass (32 MiB).
+constexpr int64_t MLP_SCRATCH_FLOATS = int64_t(1) << 23;
+// Device address of that array on the current device (looked up once per device, then cached).
+hipError_t mlp_scratch_resolve(float** out);
+// epi: 0 none, 1 bias + SiLU keeping the pre-activation in Z, 2 bias, 3 times SiLU'(Z),
+// 4 bias + SiLU without Z
 hipError_t mlp_sgemm(bool tA, bool tB, int epi, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                      const float* B, int64_t ldb, float* C, int64_t ldc, const float* bias, float* Z, int64_t ldz,
                      hipStream_t s);

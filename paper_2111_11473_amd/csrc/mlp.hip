@@ -4,8 +4,9 @@
 //
 // Training pieces:
 //   sgemm        C = op(A) op(B) on 64 x 64 tiles (FP32 VALU, LDS-staged), with fused epilogues:
-//                bias + SiLU (keeps the pre-activation for the backward pass), bias only, or a
-//                product with SiLU'(Z) (the backward pass through an activation)
+//                bias + SiLU (keeps the pre-activation for the backward pass, or not in a pass
+//                that is only a forward one), bias only, or a product with SiLU'(Z) (the backward
+//                pass through an activation)
 //   normalize    x_n = (x - mu) / sd per input column
 //   mse_grad     dY = 2 (y_n - (t - mu) / sd) / (rows n_out) and per-block partial loss sums
 //   colsum       bias gradients
@@ -15,6 +16,8 @@
 // keeping the activations in LDS.
 // Parameter layout (FP32, one flat vector): W1 [n_in][w], b1 [w], W2 [w][w], b2 [w], W3 [w][n_out],
 // b3 [n_out].
+#include <mutex>
+
 #include "internal.h"
 
 namespace thc {
@@ -85,6 +88,8 @@ __global__ __launch_bounds__(TPB) void sgemm_kernel(int64_t M, int64_t N, int64_
         x += bias[n];
         Z[m * ldz + n] = x;
         x = silu_f(x);
+      } else if (EPI == 4) {  // bias + SiLU, pre-activation not kept (forward pass only)
+        x = silu_f(x + bias[n]);
       } else if (EPI == 2) {  // bias only
         x += bias[n];
       } else if (EPI == 3) {  // times SiLU'(Z)
@@ -356,6 +361,36 @@ unsigned nblk(int64_t n) {
 
 }  // namespace
 
+// Scratch of the allocation-free FP32 forward pass: the activations of one call live in this
+// file-scope device array (MLP_SCRATCH_FLOATS floats, 32 MiB), which every GPU the library runs on
+// holds until the process ends.  In host code `scratch` is only a stand-in for the symbol, not a
+// device address: kernels get the address that mlp_scratch_resolve looked up for the device.
+static __device__ __align__(256) float scratch[MLP_SCRATCH_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float* scratch_at[MAX_DEVICES] = {};  // device address of `scratch` per device id, once resolved
+}  // namespace
+
+hipError_t mlp_scratch_resolve(float** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_at[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_at[dev] = static_cast<float*>(p);
+  }
+  *out = scratch_at[dev];
+  return hipSuccess;
+}
+
 hipError_t mlp_sgemm(bool tA, bool tB, int epi, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                      const float* B, int64_t ldb, float* C, int64_t ldc, const float* bias, float* Z, int64_t ldz,
                      hipStream_t s) {
@@ -364,7 +399,8 @@ hipError_t mlp_sgemm(bool tA, bool tB, int epi, int64_t M, int64_t N, int64_t K,
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
 #define SG(TA, TB, E) hipLaunchKernelGGL((sgemm_kernel<TA, TB, E>), grid, dim3(TPB), 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, Z, ldz)
   if (!tA && !tB) {
-    if (epi == 1) SG(false, false, 1); else if (epi == 2) SG(false, false, 2); else SG(false, false, 0);
+    if (epi == 1) SG(false, false, 1); else if (epi == 2) SG(false, false, 2); else if (epi == 4) SG(false, false, 4);
+    else SG(false, false, 0);
   } else if (tA && !tB) {
     SG(true, false, 0);
   } else if (!tA && tB) {

@@ -923,6 +923,8 @@ struct thc_mlp {
   short* wb = nullptr;
   float* bb = nullptr;
   bool packed = false;
+  float* scratch = nullptr;            // device address of the allocation-free pass's scratch
+  hipError_t scratch_err = hipSuccess;  // why it could not be looked up, if it could not
   std::vector<void*> allocs, acts;
 };
 
@@ -971,6 +973,20 @@ int mlp_fwd_into(thc_mlp* ctx, const float* X, int64_t R, const MlpActs& a) {
   HIPCHK(mlp_sgemm(false, false, 1, R, w, w, a.h1, w, W2, w, a.h2, w, b2, a.z2, w, s));
   HIPCHK(mlp_sgemm(false, false, 2, R, no, w, a.h2, w, W3, no, a.yn, no, b3, nullptr, 0, s));
   return THC_OK;
+}
+
+// Rows of one allocation-free forward pass that fit the scratch array: xn, h1, h2 and yn, each
+// starting on a 64-float (256-byte) boundary.
+int64_t mlp_scratch_floats(const thc_mlp* ctx, int64_t R) {
+  auto up = [](int64_t n) { return (n + 63) / 64 * 64; };
+  return up(R * ctx->n_in) + 2 * up(R * ctx->w) + up(R * ctx->n_out);
+}
+
+int64_t mlp_scratch_rows(const thc_mlp* ctx) {
+  const int64_t per = ctx->n_in + 2 * ctx->w + ctx->n_out;
+  int64_t r = MLP_SCRATCH_FLOATS / per;
+  while (r > 0 && mlp_scratch_floats(ctx, r) > MLP_SCRATCH_FLOATS) --r;
+  return r;
 }
 
 // forward in FP32 into the network's own activation buffers
@@ -1591,6 +1607,9 @@ int thc_mlp_create(int64_t n_in, int64_t width, int64_t n_out, uint64_t seed, vo
     delete ctx;
     return rc;
   }
+  // the allocation-free forward pass's scratch on this device (looked up once per device)
+  ctx->scratch_err = mlp_scratch_resolve(&ctx->scratch);
+  if (ctx->scratch_err != hipSuccess) (void)hipGetLastError();
   *out = ctx;
   return THC_OK;
 }
@@ -1653,6 +1672,40 @@ int thc_mlp_forward(thc_mlp* ctx, const float* X, int64_t rows, float* Y) {
   RCHK(mlp_reserve(ctx, rows));
   RCHK(mlp_fwd(ctx, X, rows));
   HIPCHK(mlp_denorm(rows, ctx->n_out, ctx->yn, ctx->mu_out, ctx->sd_out, Y, ctx->stream));
+  return THC_OK;
+}
+
+int thc_mlp_forward_noalloc(thc_mlp* ctx, const float* X, int64_t rows, float* Y) {
+  if (!ctx || !X || !Y || rows < 0) return THC_EINVAL;
+  if (rows == 0) return THC_OK;
+  if (!ctx->scratch) {
+    ctx->err = std::string("thc_mlp_forward_noalloc: the scratch array's device address could not be looked up: ") +
+               hipGetErrorString(ctx->scratch_err);
+    return THC_EDEVICE;
+  }
+  const int64_t cap = mlp_scratch_rows(ctx);
+  if (rows > cap) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "thc_mlp_forward_noalloc: %lld rows exceed the scratch capacity of %lld rows for this network "
+             "(%lld MiB of activations)",
+             (long long)rows, (long long)cap, (long long)(MLP_SCRATCH_FLOATS * 4 >> 20));
+    ctx->err = buf;
+    return THC_EINVAL;
+  }
+  auto up = [](int64_t n) { return (n + 63) / 64 * 64; };
+  const int64_t ni = ctx->n_in, w = ctx->w, no = ctx->n_out;
+  float* xn = ctx->scratch;
+  float* h1 = xn + up(rows * ni);
+  float* h2 = h1 + up(rows * w);
+  float* yn = h2 + up(rows * w);
+  const float *W1 = ctx->p, *b1 = W1 + ni * w, *W2 = b1 + w, *b2 = W2 + w * w, *W3 = b2 + w, *b3 = W3 + w * no;
+  hipStream_t s = ctx->stream;
+  HIPCHK(mlp_normalize(rows, ni, X, ctx->mu_in, ctx->sd_in, xn, s));
+  HIPCHK(mlp_sgemm(false, false, 4, rows, w, ni, xn, ni, W1, w, h1, w, b1, nullptr, 0, s));
+  HIPCHK(mlp_sgemm(false, false, 4, rows, w, w, h1, w, W2, w, h2, w, b2, nullptr, 0, s));
+  HIPCHK(mlp_sgemm(false, false, 2, rows, no, w, h2, w, W3, no, yn, no, b3, nullptr, 0, s));
+  HIPCHK(mlp_denorm(rows, no, yn, ctx->mu_out, ctx->sd_out, Y, s));
   return THC_OK;
 }
 

@@ -33,7 +33,7 @@ SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_term
            "thc_last_error", "thc_destroy",
            "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
            "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
-           "thc_mlp_forward", "thc_mlp_loss_grad", "thc_mlp_train_step", "thc_mlp_infer", "thc_mlp_last_error",
+           "thc_mlp_forward", "thc_mlp_forward_noalloc", "thc_mlp_loss_grad", "thc_mlp_train_step", "thc_mlp_infer", "thc_mlp_last_error",
            "thc_mlp_destroy"]
 GUESS_FEATURES = 10
 
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.thc_mlp_get_params.argtypes = [VP, P]
     lib.thc_mlp_set_params.argtypes = [VP, P]
     lib.thc_mlp_forward.argtypes = [VP, P, I64, P]
+    lib.thc_mlp_forward_noalloc.argtypes = [VP, P, I64, P]
     lib.thc_mlp_loss_grad.argtypes = [VP, P, P, I64, FP, P]
     lib.thc_mlp_train_step.argtypes = [VP, P, P, I64, C.c_float, FP]
     lib.thc_mlp_infer.argtypes = [VP, P, I64, P]
@@ -386,6 +387,16 @@ class MLP:
         r = self._rows(X)
         Y = torch.empty((r, self.n_out), dtype=torch.float32, device="cuda")
         self._check(self.lib.thc_mlp_forward(self.net, _fptr(X, name="X"), r, _fptr(Y)), "thc_mlp_forward")
+        return Y
+
+    def forward_noalloc(self, X, Y=None):
+        """FP32 forward pass into Y (allocated here if not given) with the library allocating
+        nothing: activations in its fixed per-GPU scratch array."""
+        r = self._rows(X)
+        if Y is None:
+            Y = torch.empty((r, self.n_out), dtype=torch.float32, device="cuda")
+        self._check(self.lib.thc_mlp_forward_noalloc(self.net, _fptr(X, name="X"), r, _fptr(Y, r * self.n_out, "Y")),
+                    "thc_mlp_forward_noalloc")
         return Y
 
     def infer(self, X):
