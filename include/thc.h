@@ -75,6 +75,10 @@ typedef struct thc_options {
 /* Alg. 7 exchange contraction: by default fused on chip (no Q x Q intermediate) when o <= 128;
  * this flag forces the two-GEMM form with its x_chunk-blocked Q x Q intermediate instead. */
 #define THC_FLAG_UNFUSED_EXCHANGE (1 << 0)
+/* Synthetic inputs only (thc_set_synthetic): the vv block of the Cholesky vectors is not held in
+ * device memory but regenerated for each block of the fused pass over Cholesky vectors (the
+ * default when it does not fit the memory plan). */
+#define THC_FLAG_STREAM_LVV (1 << 1)
 
 /* Creates a context bound to the current HIP device and to `stream` (hipStream_t; NULL = the
  * default stream).  Allocates nothing on the device yet.  *out receives the context.
@@ -92,8 +96,39 @@ int thc_create(const thc_options* opt, void* stream, thc_ctx** out);
  *   eps [n]         orbital energies (the Fock matrix is diag(eps))
  *   X   [o*nP + v*nP + o*nQ + v*nQ]  Xo[o][nP] | Xv[v][nP] | xo[o][nQ] | xv[v][nQ]
  *   Z   [nP][nP]    out: the MP2-guess core (may be NULL)
+ * L, eps and X are NULL after thc_set_synthetic (the inputs are generated on the device).
  * Allocates the device working memory (all of it; nothing is allocated later). */
 int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const double* X, double* Z);
+
+/* Seeded synthetic inputs generated on the device instead of caller arrays (the workloads'
+ * stand-in for molecules): eps_o ~ U[-1.5, -0.3], eps_v ~ U[0.1, 5.0] (each sorted ascending),
+ * L^K_pq = gamma N(0,1) e^(-K/decay) symmetric in (p, q), Xo, Xv ~ N(0,1)/sqrt(nP),
+ * xo, xv ~ N(0,1)/sqrt(nQ), from counter-based SplitMix64 draws (Steele, Lea & Flood 2014) with
+ * Box-Muller normals; stream s of seed S gives the same values, bit for bit, as the Python
+ * generator of the package (streams: 0 eps_o, 1 eps_v, 2 L (draw K n^2 + p n + q, p <= q),
+ * 3 Xo, 4 Xv, 5 xo, 6 xv; all row-major).  gamma > 0 is used as given; otherwise it is fixed by
+ * gamma^2 lambda_max(L_ov L_ov^T) = coupling (2 (eps_LUMO - eps_HOMO)), lambda_max by 200 steps
+ * of power iteration on the nL x nL Gram matrix of the unscaled ov block from the normalized
+ * all-ones vector.  Call before thc_build_factors, which then takes NULL for L, eps and X. */
+typedef struct thc_synth_spec {
+  uint64_t seed;
+  double decay;    /* decay length of the Cholesky vectors (> 0) */
+  double coupling; /* the gamma rule's fraction of the smallest pair gap (> 0 when gamma <= 0) */
+  double gamma;    /* > 0: this scale; <= 0: the rule */
+} thc_synth_spec;
+int thc_set_synthetic(thc_ctx* ctx, const thc_synth_spec* spec);
+/* The global scale gamma of the synthetic Cholesky vectors (host), valid after thc_build_factors. */
+int thc_synth_gamma(const thc_ctx* ctx, double* gamma);
+
+/* The generator itself, for callers that want the same inputs in their own buffers (device
+ * arrays; work on `stream`).  thc_synth_normals: out[i] = (N(0,1) draw first + i of
+ * (seed, stream_id)) / divisor, i < count.  thc_synth_cholesky: vectors K0 .. K0 + nK - 1 as
+ * whole n x n matrices, L[nK][n][n], times gamma.  thc_synth_energies: eps[o + v] (HOST array). */
+int thc_synth_normals(uint64_t seed, int32_t stream_id, uint64_t first, int64_t count, double divisor, double* out,
+                      void* stream);
+int thc_synth_cholesky(uint64_t seed, int64_t n, int64_t K0, int64_t nK, double decay, double gamma, double* L,
+                       void* stream);
+int thc_synth_energies(uint64_t seed, int64_t o, int64_t v, double* eps);
 
 /* Residual of a state (pure: the context state is not changed).
  *   Z      [nP][nP] amplitude core (symmetric), raw collocation basis

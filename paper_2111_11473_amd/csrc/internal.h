@@ -91,6 +91,20 @@ hipError_t k_mp2_denom(int64_t rows0, int64_t rows, int64_t ov, int64_t v, const
 hipError_t k_fill(int64_t n, double val, double* x, hipStream_t s);
 hipError_t k_set_diag(int64_t n, const double* d, double* X, int64_t ld, hipStream_t s);
 
+// Synthetic inputs on the device (synth_gen.hip; values bit-identical to the Python generator).
+// out[i] = N(0,1) draw first + i of (seed, stream) / divisor.
+hipError_t synth_normals(uint64_t seed, uint64_t stream, uint64_t first, int64_t count, double divisor, double* out,
+                         hipStream_t s);
+// Rows [r0, r0 + nr) x columns [c0, c0 + nc) of Cholesky vectors K0 .. K0 + nK - 1 (n x n each),
+// times gamma, into out[nK][nr][nc].
+hipError_t synth_chol_block(uint64_t seed, int64_t n, int64_t K0, int64_t nK, int64_t r0, int64_t nr, int64_t c0,
+                            int64_t nc, double decay, double gamma, double* out, hipStream_t s);
+hipError_t synth_scale(int64_t n, double a, double* x, hipStream_t s);
+// x = y / sqrt(*dot)
+hipError_t synth_normalize(int64_t n, const double* y, const double* dot, double* x, hipStream_t s);
+// Orbital energies (host): o occupied then v virtual, each sorted ascending.
+void synth_energies(uint64_t seed, int64_t o, int64_t v, double* eps);
+
 // Fused exchange contraction Gt^X = xo (z o (xo^T Rx^X))^T for X = 0..nx-1 (kernels_exch.hip);
 // xo [o][Q], z [Q][Q], Rx and Gt [nx][o][Q].  Supported for 1 <= o <= 128.  f32: operands rounded
 // to FP32, FP32 MFMA and accumulation (the mixed-precision path); else FP64 throughout.

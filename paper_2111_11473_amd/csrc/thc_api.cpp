@@ -24,6 +24,9 @@ using namespace thc;
 namespace {
 
 constexpr int64_t GEMM_WS = int64_t(1) << 22;  // 32 MB
+// generator streams of the synthetic inputs (the order of the Python generator)
+constexpr uint64_t thc_synth_stream_xo_amp = 3, thc_synth_stream_xv_amp = 4, thc_synth_stream_xo_eri = 5,
+                   thc_synth_stream_xv_eri = 6;
 
 struct ProfRec {
   std::string name;
@@ -46,6 +49,11 @@ struct thc_ctx {
   bool built = false;
 
   int64_t o = 0, v = 0, n = 0, nL = 0, P = 0, Q = 0, Pp = 0, ov = 0;
+  // synthetic inputs generated on the device (thc_set_synthetic)
+  bool synth = false;
+  thc_synth_spec spec{};
+  double gamma = 0.0;         // global scale of the Cholesky vectors in use
+  bool lvv_resident = true;   // the vv Cholesky block is held; else regenerated per fused-pass block
   int64_t nb = 0, KS = 1, Xb = 0, Ic = 0, Xc = 0;
 
   std::vector<void*> allocs;
@@ -411,11 +419,21 @@ int plan_and_alloc(thc_ctx* ctx) {
   ctx->Xc = std::min(Xc, P);
   const int64_t PP = P * P;
 
+  // vv block of the Cholesky vectors: held (caller inputs always), or, for synthetic inputs,
+  // regenerated block by block in the fused pass when asked or when holding it would leave less
+  // than a quarter of the free device memory for the rest
+  ctx->lvv_resident = true;
+  if (ctx->synth) {
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) { ctx->err = "hipMemGetInfo failed"; return THC_EDEVICE; }
+    ctx->lvv_resident = !(op.flags & THC_FLAG_STREAM_LVV) && 8.0 * (double)nL * v * v < 0.75 * (double)freeb - 8.0e9;
+  }
+  const int64_t nlvv = ctx->lvv_resident ? nL : nb;
   struct A { double** p; size_t n; };
   const int64_t dm = ctx->opt.diis_max;
   ctx->Ic = 0;  // the chunk-sized entries are sized below, from what the rest leaves free
   auto make_list = [&]() -> std::vector<A> { return {
-      {&ctx->Loo, (size_t)(nL * o * o)}, {&ctx->Lov, (size_t)(nL * ov)}, {&ctx->Lvv, (size_t)(nL * v * v)},
+      {&ctx->Loo, (size_t)(nL * o * o)}, {&ctx->Lov, (size_t)(nL * ov)}, {&ctx->Lvv, (size_t)(nlvv * v * v)},
       {&ctx->eps, (size_t)n}, {&ctx->Yo, (size_t)(o * P)}, {&ctx->Yv, (size_t)(v * P)},
       {&ctx->xo, (size_t)(o * Q)}, {&ctx->xv, (size_t)(v * Q)}, {&ctx->Go, (size_t)PP}, {&ctx->Gv, (size_t)PP},
       {&ctx->S, (size_t)PP}, {&ctx->z, (size_t)(Q * Q)}, {&ctx->Bq, (size_t)(Q * ov)}, {&ctx->Bkr, (size_t)(ov * P)},
@@ -541,7 +559,9 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     const int64_t nb = std::min(ctx->nb, nL - A0);
     const double* Loo = ctx->Loo + A0 * o * o;
     const double* Lov = ctx->Lov + A0 * ov;
-    const double* Lvv = ctx->Lvv + A0 * v * v;
+    const double* Lvv = ctx->lvv_resident ? ctx->Lvv + A0 * v * v : ctx->Lvv;
+    if (!ctx->lvv_resident)  // the block's vv Cholesky panels from the generator
+      MISC(synth_chol_block(ctx->spec.seed, n, A0, nb, o, v, o, v, ctx->spec.decay, ctx->gamma, ctx->Lvv, s));
     const double* Lhoo = Loo;  // dressed blocks (Eq. 27); the undressed ones in CCD mode
     if (singles) {
       // tmpoo[A] = Lov t1^T (o x o), also in the [i][A][k] layout for the Fock K-term
@@ -1021,7 +1041,7 @@ int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
   if (!opt || !out) return THC_EINVAL;
   *out = nullptr;
   if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
-      opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) || (opt->flags & ~THC_FLAG_UNFUSED_EXCHANGE) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
+      opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) || (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV)) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
       opt->x_chunk < 0)
     return THC_EINVAL;
   // the metric S = B^T B (nP x nP) and the ERI-grid Gram (nQ x nQ) have rank at most o v
@@ -1040,23 +1060,133 @@ int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
   return THC_OK;
 }
 
+namespace {
+// Synthetic inputs generated into the library layout (the twin of the Python generator): orbital
+// energies on the host, factors and Cholesky blocks on the device, and the global scale gamma
+// (given, or from lambda_max(L_ov L_ov^T) by power iteration on the nL x nL Gram matrix).
+int generate_inputs(thc_ctx* ctx) {
+  hipStream_t s = ctx->stream;
+  const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
+  const thc_synth_spec& sp = ctx->spec;
+  std::vector<double> e(n);
+  synth_energies(sp.seed, o, v, e.data());
+  RCHK(h2d(ctx, ctx->eps, e.data(), n * sizeof(double)));
+  const double sP = std::sqrt((double)P), sQ = std::sqrt((double)Q);
+  MISC(synth_normals(sp.seed, thc_synth_stream_xo_amp, 0, o * P, sP, ctx->Yo, s));
+  MISC(synth_normals(sp.seed, thc_synth_stream_xv_amp, 0, v * P, sP, ctx->Yv, s));
+  MISC(synth_normals(sp.seed, thc_synth_stream_xo_eri, 0, o * Q, sQ, ctx->xo, s));
+  MISC(synth_normals(sp.seed, thc_synth_stream_xv_eri, 0, v * Q, sQ, ctx->xv, s));
+  // unscaled oo and ov blocks, then gamma
+  MISC(synth_chol_block(sp.seed, n, 0, nL, 0, o, 0, o, sp.decay, 1.0, ctx->Loo, s));
+  MISC(synth_chol_block(sp.seed, n, 0, nL, 0, o, o, v, sp.decay, 1.0, ctx->Lov, s));
+  double gamma = sp.gamma;
+  if (!(gamma > 0.0)) {
+    double *G = nullptr, *x = nullptr, *y = nullptr;
+    std::vector<void*> tmp;
+    auto talloc = [&](double** p, size_t cnt) {
+      void* q = nullptr;
+      if (hipMalloc(&q, cnt * sizeof(double)) != hipSuccess) return false;
+      tmp.push_back(q);
+      *p = (double*)q;
+      return true;
+    };
+    auto tfree = [&]() { for (void* q : tmp) (void)hipFree(q); };
+    if (!talloc(&G, (size_t)(nL * nL)) || !talloc(&x, (size_t)nL) || !talloc(&y, (size_t)nL)) {
+      tfree();
+      ctx->err = "allocation for the gamma rule failed";
+      return THC_ENOMEM;
+    }
+    int rc = gemm(ctx, mk(nL, nL, ov, ctx->Lov, ov, false, ctx->Lov, ov, true, G, nL));
+    if (rc == THC_OK) {
+      std::vector<double> ones((size_t)nL, 1.0 / std::sqrt((double)nL));
+      rc = h2d(ctx, x, ones.data(), nL * sizeof(double));
+    }
+    for (int it = 0; it < 200 && rc == THC_OK; ++it) {
+      if (k_gemv(nL, nL, G, nL, x, y, s) != hipSuccess || k_dot(nL, y, y, ctx->scal + 60, s) != hipSuccess ||
+          synth_normalize(nL, y, ctx->scal + 60, x, s) != hipSuccess) {
+        ctx->err = "gamma rule: kernel launch failed";
+        rc = THC_EDEVICE;
+      }
+    }
+    double lam2 = 0.0;
+    if (rc == THC_OK) rc = d2h(ctx, &lam2, ctx->scal + 60, sizeof(double));
+    tfree();
+    RCHK(rc);
+    const double lam = std::sqrt(lam2);
+    const double dmin = 2.0 * (e[o] - e[o - 1]);
+    if (!(lam > 0.0) || !(dmin > 0.0)) { ctx->err = "gamma rule: degenerate inputs"; return THC_ENUMERIC; }
+    gamma = std::sqrt(sp.coupling * dmin / lam);
+  }
+  ctx->gamma = gamma;
+  MISC(synth_scale(nL * o * o, gamma, ctx->Loo, s));
+  MISC(synth_scale(nL * ov, gamma, ctx->Lov, s));
+  if (ctx->lvv_resident) MISC(synth_chol_block(sp.seed, n, 0, nL, o, v, o, v, sp.decay, gamma, ctx->Lvv, s));
+  return THC_OK;
+}
+}  // namespace
+
+int thc_set_synthetic(thc_ctx* ctx, const thc_synth_spec* spec) {
+  if (!ctx) return THC_EINVAL;
+  if (!spec || !(spec->decay > 0.0) || (!(spec->gamma > 0.0) && !(spec->coupling > 0.0))) {
+    ctx->err = "thc_set_synthetic: decay must be positive, and coupling too unless gamma is given";
+    return THC_EINVAL;
+  }
+  if (ctx->built) { ctx->err = "factors already built for this context"; return THC_ESTATE; }
+  ctx->synth = true;
+  ctx->spec = *spec;
+  return THC_OK;
+}
+
+int thc_synth_gamma(const thc_ctx* ctx, double* gamma) {
+  if (!ctx || !gamma) return THC_EINVAL;
+  if (!ctx->built) return THC_ESTATE;
+  *gamma = ctx->synth ? ctx->gamma : 0.0;
+  return THC_OK;
+}
+
+int thc_synth_normals(uint64_t seed, int32_t stream_id, uint64_t first, int64_t count, double divisor, double* out,
+                      void* stream) {
+  if (stream_id < 0 || stream_id > 6 || count < 0 || (count > 0 && !out) || divisor == 0.0) return THC_EINVAL;
+  return synth_normals(seed, (uint64_t)stream_id, first, count, divisor, out, (hipStream_t)stream) == hipSuccess
+             ? THC_OK
+             : THC_EDEVICE;
+}
+
+int thc_synth_cholesky(uint64_t seed, int64_t n, int64_t K0, int64_t nK, double decay, double gamma, double* L,
+                       void* stream) {
+  if (n < 1 || K0 < 0 || nK < 0 || !(decay > 0.0) || (nK > 0 && !L)) return THC_EINVAL;
+  return synth_chol_block(seed, n, K0, nK, 0, n, 0, n, decay, gamma, L, (hipStream_t)stream) == hipSuccess
+             ? THC_OK
+             : THC_EDEVICE;
+}
+
+int thc_synth_energies(uint64_t seed, int64_t o, int64_t v, double* eps) {
+  if (o < 1 || v < 1 || !eps) return THC_EINVAL;
+  synth_energies(seed, o, v, eps);
+  return THC_OK;
+}
+
 int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const double* X, double* Zout) {
   if (!ctx) return THC_EINVAL;
-  if (!L || !eps || !X) { ctx->err = "null input"; return THC_EINVAL; }
+  if (!ctx->synth && (!L || !eps || !X)) { ctx->err = "null input"; return THC_EINVAL; }
   if (ctx->built) { ctx->err = "factors already built for this context"; return THC_ESTATE; }
   hipStream_t s = ctx->stream;
   RCHK(plan_and_alloc(ctx));
   const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
   const int64_t PP = P * P;
-  // integrals and factors into the library layout
-  MISC(k_copy2d(nL, o, o, L, n, n * n, ctx->Loo, o, o * o, false, s));
-  MISC(k_copy2d(nL, o, v, L + o, n, n * n, ctx->Lov, v, ov, false, s));
-  MISC(k_copy2d(nL, v, v, L + o * n + o, n, n * n, ctx->Lvv, v, v * v, false, s));
-  HIPCHK(hipMemcpyAsync(ctx->eps, eps, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(ctx->Yo, X, o * P * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(ctx->Yv, X + o * P, v * P * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(ctx->xo, X + (o + v) * P, o * Q * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(ctx->xv, X + (o + v) * P + o * Q, v * Q * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (ctx->synth) {
+    RCHK(generate_inputs(ctx));
+  } else {
+    // integrals and factors into the library layout
+    MISC(k_copy2d(nL, o, o, L, n, n * n, ctx->Loo, o, o * o, false, s));
+    MISC(k_copy2d(nL, o, v, L + o, n, n * n, ctx->Lov, v, ov, false, s));
+    MISC(k_copy2d(nL, v, v, L + o * n + o, n, n * n, ctx->Lvv, v, v * v, false, s));
+    HIPCHK(hipMemcpyAsync(ctx->eps, eps, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->Yo, X, o * P * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->Yv, X + o * P, v * P * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->xo, X + (o + v) * P, o * Q * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->xv, X + (o + v) * P + o * Q, v * Q * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
 
   // Grams and metric (Eq. 10): S = (Xo^T Xo) o (Xv^T Xv); Khatri-Rao B[(ia)][X]
   RCHK(gemm(ctx, mk(P, P, o, ctx->Yo, P, true, ctx->Yo, P, false, ctx->Go, P)));
@@ -1403,7 +1533,7 @@ int thc_plan(const thc_ctx* ctx, thc_plan_info* out) {
   p.h_tiles = ctx->hfilled;
   p.x_chunk = ctx->Xc;
   p.exchange_fused = exch_supported(ctx->o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE);
-  p.lvv_resident = 1;
+  p.lvv_resident = ctx->lvv_resident ? 1 : 0;
   p.device_bytes = ctx->bytes;
   *out = p;
   return THC_OK;

@@ -7,7 +7,12 @@ oracle and the GPU library can be fed identical inputs.  Nothing here imports ei
 Generator: a counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA 2014).  For a key k
 derived from (seed, stream), draw i is the SplitMix64 output function applied to the
 state k + (i+1)*0x9E3779B97F4A7C15.  Uniforms take the top 53 bits, normals come from the
-Box-Muller transform of two consecutive uniforms (cosine branch only).
+Box-Muller transform of two consecutive uniforms (cosine branch only).  The logarithm, cosine
+and exponential inside are evaluated here from fixed sequences of IEEE additions,
+multiplications and divisions (exact range reductions, truncated series with the coefficients
+as exact binary constants), not through a math library, so that the library's device twin of
+this generator (csrc/synth_core.h, compiled without contraction into fused multiply-adds)
+reproduces every value bit for bit.
 
 Value distributions (paper Sec. II, Eq. 1 ordering N_o < N_v < N_CD ~ N_THC ~ N_aux):
   eps_o ~ U[-1.5, -0.3] Eh, eps_v ~ U[0.1, 5.0] Eh, each sorted ascending;
@@ -60,12 +65,90 @@ def uniform(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
     return (b.astype(np.float64) + 0.5) * (1.0 / 9007199254740992.0)
 
 
+_H = float.fromhex
+_LN2 = _H("0x1.62e42fefa39efp-1")
+_LN2_HI = _H("0x1.62e42fee00000p-1")     # top 32 bits of ln 2: n * _LN2_HI is exact for |n| < 2^21
+_LN2_LO = _H("0x1.a39ef00000000p-33")    # ln 2 - _LN2_HI
+_INV_LN2 = _H("0x1.71547652b82fep+0")
+_SQRT_HALF = _H("0x1.6a09e667f3bcdp-1")
+_TWO_PI = _H("0x1.921fb54442d18p+2")
+# 1/(2k+1), k = 0..10 (atanh series of the logarithm)
+_ATANH = [_H(c) for c in ("0x1.0000000000000p+0", "0x1.5555555555555p-2", "0x1.999999999999ap-3",
+                          "0x1.2492492492492p-3", "0x1.c71c71c71c71cp-4", "0x1.745d1745d1746p-4",
+                          "0x1.3b13b13b13b14p-4", "0x1.1111111111111p-4", "0x1.e1e1e1e1e1e1ep-5",
+                          "0x1.af286bca1af28p-5", "0x1.8618618618618p-5")]
+# (-1)^k/(2k)! and (-1)^k/(2k+1)!, k = 0..9 (cosine and sine series)
+_COS = [_H(c) for c in ("0x1.0000000000000p+0", "-0x1.0000000000000p-1", "0x1.5555555555555p-5",
+                        "-0x1.6c16c16c16c17p-10", "0x1.a01a01a01a01ap-16", "-0x1.27e4fb7789f5cp-22",
+                        "0x1.1eed8eff8d898p-29", "-0x1.93974a8c07c9dp-37", "0x1.ae7f3e733b81fp-45",
+                        "-0x1.6827863b97d97p-53")]
+_SIN = [_H(c) for c in ("0x1.0000000000000p+0", "-0x1.5555555555555p-3", "0x1.1111111111111p-7",
+                        "-0x1.a01a01a01a01ap-13", "0x1.71de3a556c734p-19", "-0x1.ae64567f544e4p-26",
+                        "0x1.6124613a86d09p-33", "-0x1.ae7f3e733b81fp-41", "0x1.952c77030ad4ap-49",
+                        "-0x1.2f49b46814157p-57")]
+# 1/k!, k = 0..14 (exponential series)
+_EXP = [_H(c) for c in ("0x1.0000000000000p+0", "0x1.0000000000000p+0", "0x1.0000000000000p-1",
+                        "0x1.5555555555555p-3", "0x1.5555555555555p-5", "0x1.1111111111111p-7",
+                        "0x1.6c16c16c16c17p-10", "0x1.a01a01a01a01ap-13", "0x1.a01a01a01a01ap-16",
+                        "0x1.71de3a556c734p-19", "0x1.27e4fb7789f5cp-22", "0x1.ae64567f544e4p-26",
+                        "0x1.1eed8eff8d898p-29", "0x1.6124613a86d09p-33", "0x1.93974a8c07c9dp-37")]
+
+
+def _horner(coef, x):
+    p = np.full_like(x, coef[-1])
+    for c in coef[-2::-1]:
+        p = p * x + c
+    return p
+
+
+def gen_log(u: np.ndarray) -> np.ndarray:
+    """ln u for u > 0: u = m 2^e with m in [sqrt(1/2), sqrt(2)) (exact), then
+    e ln 2 + 2 atanh((m - 1)/(m + 1)) by its series (|s| < 0.172, 11 terms)."""
+    m, e = np.frexp(np.asarray(u, dtype=np.float64))
+    small = m < _SQRT_HALF
+    m = np.where(small, m * 2.0, m)
+    e = (e - small.astype(e.dtype)).astype(np.float64)
+    s = (m - 1.0) / (m + 1.0)
+    return e * _LN2 + 2.0 * (s * _horner(_ATANH, s * s))
+
+
+def gen_cos_turns(t: np.ndarray) -> np.ndarray:
+    """cos(2 pi t) for t in [0, 1): the reductions to a quarter of an eighth turn are exact
+    (Sterbenz), then the cosine or sine series on |x| <= pi/4 (10 terms)."""
+    t = np.asarray(t, dtype=np.float64)
+    a = np.where(t >= 0.5, 1.0 - t, t)          # cos(2 pi t) = cos(2 pi (1 - t)), a in [0, 1/2]
+    neg = a > 0.25
+    a = np.where(neg, 0.5 - a, a)               # cos(2 pi a) = -cos(2 pi (1/2 - a)), a in [0, 1/4]
+    use_sin = a > 0.125
+    a = np.where(use_sin, 0.25 - a, a)          # cos(2 pi a) = sin(2 pi (1/4 - a)), a in [0, 1/8]
+    x = a * _TWO_PI
+    x2 = x * x
+    c = _horner(_COS, x2)
+    sn = x * _horner(_SIN, x2)
+    r = np.where(use_sin, sn, c)
+    return np.where(neg, -r, r)
+
+
+def gen_exp(x: np.ndarray) -> np.ndarray:
+    """e^x for moderate x: x = n ln 2 + r with n = floor(x / ln 2 + 1/2) (two-part ln 2), the
+    series of e^r (|r| <= 0.35, 15 terms), scaled by 2^n exactly."""
+    x = np.asarray(x, dtype=np.float64)
+    n = np.floor(x * _INV_LN2 + 0.5)
+    r = (x - n * _LN2_HI) - n * _LN2_LO
+    return np.ldexp(_horner(_EXP, r), n.astype(np.int64))
+
+
 def normal(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
     """Standard normals; normal i consumes uniforms 2i and 2i+1 (Box-Muller, cosine branch)."""
     idx = np.asarray(idx, dtype=np.uint64)
     u1 = uniform(seed, stream, idx * np.uint64(2))
     u2 = uniform(seed, stream, idx * np.uint64(2) + np.uint64(1))
-    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    return np.sqrt(-2.0 * gen_log(u1)) * gen_cos_turns(u2)
+
+
+def decay_factor(K, decay: float) -> np.ndarray:
+    """e^(-K/decay) of Cholesky vector K."""
+    return gen_exp(-np.asarray(K, dtype=np.float64) / float(decay))
 
 
 @dataclass(frozen=True)
@@ -137,7 +220,7 @@ def cholesky_unscaled(cfg: Config, dtype=np.float64) -> np.ndarray:
     flat = (iu * n + ju).astype(np.uint64)
     out = np.empty((cfg.nL, n, n), dtype=dtype)
     for K in range(cfg.nL):
-        vals = normal(cfg.seed, STREAM_L, np.uint64(K * n * n) + flat) * np.exp(-K / cfg.decay)
+        vals = normal(cfg.seed, STREAM_L, np.uint64(K * n * n) + flat) * decay_factor(K, cfg.decay)
         m = out[K]
         m[iu, ju] = vals
         m[ju, iu] = vals

@@ -29,7 +29,8 @@ TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TER
 SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_history",
            "thc_history_precision",
            "thc_energy",
-           "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
+           "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan",
+           "thc_set_synthetic", "thc_synth_gamma", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
            "thc_last_error", "thc_destroy",
            "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
            "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
@@ -50,6 +51,14 @@ class PlanInfo(C.Structure):
                 ("x_block", C.c_int64), ("x_blocks", C.c_int64), ("i_chunk", C.c_int64), ("i_chunks", C.c_int64),
                 ("h_generations", C.c_int64), ("h_tiles", C.c_int64), ("x_chunk", C.c_int64),
                 ("exchange_fused", C.c_int32), ("lvv_resident", C.c_int32), ("device_bytes", C.c_uint64)]
+
+
+class SynthSpec(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("decay", C.c_double), ("coupling", C.c_double), ("gamma", C.c_double)]
+
+
+FLAG_UNFUSED_EXCHANGE = 1 << 0
+FLAG_STREAM_LVV = 1 << 1
 
 
 class ThcError(RuntimeError):
@@ -82,6 +91,11 @@ def load(path: str = LIB_PATH):
     lib.thc_set_state.argtypes = [VP, P, P]
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
     lib.thc_plan.argtypes = [VP, C.POINTER(PlanInfo)]
+    lib.thc_set_synthetic.argtypes = [VP, C.POINTER(SynthSpec)]
+    lib.thc_synth_gamma.argtypes = [VP, C.POINTER(D)]
+    lib.thc_synth_normals.argtypes = [C.c_uint64, C.c_int32, C.c_uint64, I64, D, P, VP]
+    lib.thc_synth_cholesky.argtypes = [C.c_uint64, I64, I64, I64, D, D, P, VP]
+    lib.thc_synth_energies.argtypes = [C.c_uint64, I64, I64, C.POINTER(D)]
     lib.thc_profile.argtypes = [VP, C.c_int]
     lib.thc_profile_get.argtypes = [VP, C.c_char_p, C.POINTER(D), C.POINTER(I64)]
     lib.thc_profile_flops.argtypes = [VP, C.POINTER(D), C.POINTER(D), C.POINTER(D)]
@@ -164,6 +178,37 @@ def dgemm(A, B, C_out, transA=False, transB=False, alpha=1.0, beta=0.0):
     return C_out
 
 
+def synth_normals(seed, stream_id, first, count, divisor=1.0):
+    """Normals first .. first + count - 1 of generator stream stream_id, divided by divisor, made
+    on the GPU (the same values as synth.normal)."""
+    lib = load()
+    out = torch.empty(count, dtype=torch.float64, device="cuda")
+    rc = lib.thc_synth_normals(C.c_uint64(seed), stream_id, C.c_uint64(first), count, divisor, _ptr(out), _stream())
+    if rc != 0:
+        raise ThcError(rc, "thc_synth_normals failed")
+    return out
+
+
+def synth_cholesky(seed, n, K0, nK, decay, gamma):
+    """Cholesky vectors K0 .. K0 + nK - 1 (nK x n x n, times gamma) made on the GPU."""
+    lib = load()
+    out = torch.empty((nK, n, n), dtype=torch.float64, device="cuda")
+    rc = lib.thc_synth_cholesky(C.c_uint64(seed), n, K0, nK, decay, gamma, _ptr(out), _stream())
+    if rc != 0:
+        raise ThcError(rc, "thc_synth_cholesky failed")
+    return out
+
+
+def synth_energies(seed, o, v):
+    """Orbital energies (o occupied, v virtual, each sorted) from the library's generator (host)."""
+    lib = load()
+    e = (C.c_double * (o + v))()
+    rc = lib.thc_synth_energies(C.c_uint64(seed), o, v, e)
+    if rc != 0:
+        raise ThcError(rc, "thc_synth_energies failed")
+    return list(e)
+
+
 class THC:
     """One THC-CCSD problem on the current GPU (all tensors float64, CUDA, contiguous)."""
 
@@ -207,6 +252,22 @@ class THC:
                                         _ptr(X, o * self.nP + v * self.nP + (o + v) * self.nQ, "X"), _ptr(Z))
         self._check(rc, "thc_build_factors")
         return Z
+
+    def set_synthetic(self, seed, decay, coupling=0.2, gamma=0.0):
+        """Inputs generated on the GPU by the library (thc_set_synthetic); then build_synthetic()."""
+        spec = SynthSpec(seed, decay, coupling, gamma)
+        self._check(self.lib.thc_set_synthetic(self.ctx, C.byref(spec)), "thc_set_synthetic")
+
+    def build_synthetic(self):
+        """thc_build_factors on the generated inputs; returns the MP2-guess core Z0."""
+        Z = torch.empty((self.nP, self.nP), dtype=torch.float64, device="cuda")
+        self._check(self.lib.thc_build_factors(self.ctx, None, None, None, _ptr(Z)), "thc_build_factors")
+        return Z
+
+    def synth_gamma(self):
+        g = C.c_double(0.0)
+        self._check(self.lib.thc_synth_gamma(self.ctx, C.byref(g)), "thc_synth_gamma")
+        return g.value
 
     # -- residual -----------------------------------------------------------------------
     def residual(self, Z, t1=None, mask=TERM_ALL, norms=False):
