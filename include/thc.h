@@ -70,9 +70,11 @@ typedef struct thc_options {
                                split-BF16 products (hi hi + hi lo + lo hi on BF16 MFMA, FP32
                                accumulation); the fused exchange stays FP32 MFMA */
   int32_t flags;            /* THC_FLAG_* bits; 0 = defaults */
+  int64_t x7_chunk;         /* amplitude ranks X per chunk of the Alg. 7 intermediates (R^X, S^X
+                             * half-transformed, exchange outputs); 0 = automatic */
 } thc_options;
 
-/* Alg. 7 exchange contraction: by default fused on chip (no Q x Q intermediate) when o <= 128;
+/* Alg. 7 exchange contraction: by default fused on chip (no Q x Q intermediate) when o <= 200;
  * this flag forces the two-GEMM form with its x_chunk-blocked Q x Q intermediate instead. */
 #define THC_FLAG_UNFUSED_EXCHANGE (1 << 0)
 /* Synthetic inputs only (thc_set_synthetic): the vv block of the Cholesky vectors is not held in
@@ -186,7 +188,9 @@ typedef struct thc_plan_info {
   int64_t h_generations;  /* H-kernel dispatches per pass (one per generation of resident tiles; odd
                              generations walk the grid points backwards) */
   int64_t h_tiles;        /* H-kernel tiles per pass (X tile x Y block x Z slice, Z >= Y) */
-  int64_t x_chunk;        /* amplitude ranks X per Alg. 7 chunk */
+  int64_t x_chunk;        /* amplitude ranks X per batch of the two-GEMM exchange (Q x Q intermediates) */
+  int64_t x7_chunk;       /* amplitude ranks X per chunk of the Alg. 7 intermediates */
+  int64_t x7_chunks;      /* such chunks per residual */
   int32_t exchange_fused; /* 1: the fused Alg. 7 exchange kernel, 0: its two-GEMM form */
   int32_t lvv_resident;   /* 1: the vv Cholesky block is held in device memory */
   uint64_t device_bytes;  /* device working memory */

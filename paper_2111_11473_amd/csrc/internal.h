@@ -106,7 +106,7 @@ hipError_t synth_normalize(int64_t n, const double* y, const double* dot, double
 void synth_energies(uint64_t seed, int64_t o, int64_t v, double* eps);
 
 // Fused exchange contraction Gt^X = xo (z o (xo^T Rx^X))^T for X = 0..nx-1 (kernels_exch.hip);
-// xo [o][Q], z [Q][Q], Rx and Gt [nx][o][Q].  Supported for 1 <= o <= 128.  f32: operands rounded
+// xo [o][Q], z [Q][Q], Rx and Gt [nx][o][Q].  Supported for 1 <= o <= 200.  f32: operands rounded
 // to FP32, FP32 MFMA and accumulation (the mixed-precision path); else FP64 throughout.
 bool exch_supported(int64_t o);
 hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx,

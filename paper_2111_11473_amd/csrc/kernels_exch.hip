@@ -14,7 +14,9 @@
 // The slices are fetched with buffer loads whose out-of-range lanes read zero (k >= o, J >= Q,
 // I >= Q), so the padded k-steps that remain multiply zeros and the loop has no branches; two LDS
 // buffers, one barrier per J block.
-// Layouts (row-major): xo [o][Q]; z [Q][Q]; Rx, Gt [X][o][Q].  Requires o <= 16 OB.
+// Layouts (row-major): xo [o][Q]; z [Q][Q]; Rx, Gt [X][o][Q].  Requires o <= 16 OB; instantiated
+// up to OB = 13 with 50 first-product k-steps (o <= 200), where the FP64 accumulators and operands
+// fill the 512 registers a lane has at one wave per SIMD and the two LDS buffers take 123 KB.
 //
 // F32 (the mixed-precision path): the slices are rounded to FP32 on their way into LDS and both
 // products run on v_mfma_f32_16x16x4f32 with FP32 accumulation.  There output element r of a
@@ -197,7 +199,7 @@ hipError_t launch(bool f32, int64_t o, int64_t Q, int64_t nx, const double* xo, 
 
 }  // namespace
 
-bool exch_supported(int64_t o) { return o >= 1 && o <= 128; }
+bool exch_supported(int64_t o) { return o >= 1 && o <= 200; }
 
 hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const double* z, const double* Rx,
                       double* Gt, bool f32, hipStream_t s) {
@@ -211,6 +213,9 @@ hipError_t exch_fused(int64_t o, int64_t Q, int64_t nx, const double* xo, const 
     return launch<4>(f32, o, Q, nx, xo, z, Rx, Gt, s);
   }
   if (o <= 128) return launch<8>(f32, o, Q, nx, xo, z, Rx, Gt, s);
+  // 13 row blocks: 52 accumulators and up to 52 first-product operands per lane, held in the
+  // combined vector and accumulation registers at one wave per SIMD (FP64: 467 of 512)
+  if (o <= 200) return launch<13, 50>(f32, o, Q, nx, xo, z, Rx, Gt, s);
   return hipErrorInvalidValue;
 }
 

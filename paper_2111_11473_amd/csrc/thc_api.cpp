@@ -54,7 +54,7 @@ struct thc_ctx {
   thc_synth_spec spec{};
   double gamma = 0.0;         // global scale of the Cholesky vectors in use
   bool lvv_resident = true;   // the vv Cholesky block is held; else regenerated per fused-pass block
-  int64_t nb = 0, KS = 1, Xb = 0, Ic = 0, Xc = 0;
+  int64_t nb = 0, KS = 1, Xb = 0, Ic = 0, Xc = 0, X7 = 0;
 
   std::vector<void*> allocs;
   size_t bytes = 0;
@@ -417,6 +417,11 @@ int plan_and_alloc(thc_ctx* ctx) {
   int64_t Xc = op.x_chunk;
   if (Xc <= 0) Xc = std::max<int64_t>(1, (int64_t)(2.0e9 / (8.0 * (double)Q * Q)));
   ctx->Xc = std::min(Xc, P);
+  // Alg. 7 chunk of X rows: every row when the chunked intermediates (U, Rx, Sx, Gt, Gt~, G, G~:
+  // o P + 4 o Q + 2 o v per row) fit in ~24 GB
+  int64_t X7 = op.x7_chunk;
+  if (X7 <= 0) X7 = std::max<int64_t>(1, (int64_t)(24.0e9 / (8.0 * (double)(o * P + 4 * o * Q + 2 * ov))));
+  X7 = ctx->X7 = std::min(X7, P);
   const int64_t PP = P * P;
 
   // vv block of the Cholesky vectors: held (caller inputs always), or, for synthetic inputs,
@@ -463,11 +468,11 @@ int plan_and_alloc(thc_ctx* ctx) {
       {&ctx->C6, (size_t)(o * Xb * Pp)}, {&ctx->D6, (size_t)(v * Xb * Pp)}, {&ctx->Ec, (size_t)(ctx->Ic * Xb * Pp)},
       {&ctx->Fc, (size_t)(ctx->Ic * Xb * Pp)}, {&ctx->Gc, (size_t)(ctx->Ic * Pp * Pp)}, {&ctx->GYc, (size_t)(ctx->Ic * o * P)},
       {&ctx->Hb, (size_t)(Xb * Pp * Pp)}, {&ctx->R1, (size_t)(Xb * Pp * o)}, {&ctx->I6, (size_t)(Xb * ov)},
-      // Alg. 7
-      {&ctx->U7, (size_t)(P * o * P)}, {&ctx->S7, (size_t)(P * ov)}, {&ctx->R7, (size_t)(P * ov)},
-      {&ctx->Rx, (size_t)(P * o * Q)}, {&ctx->Sx, (size_t)(P * o * Q)}, {&ctx->Cx, (size_t)(P * Q)}, {&ctx->Dx, (size_t)(P * Q)},
-      {&ctx->F7, (size_t)(exch_supported(o) && !(op.flags & THC_FLAG_UNFUSED_EXCHANGE) ? 1 : ctx->Xc * Q * Q)}, {&ctx->Gt, (size_t)(P * o * Q)}, {&ctx->Gts, (size_t)(P * o * Q)},
-      {&ctx->G7, (size_t)(P * ov)}, {&ctx->G7s, (size_t)(P * ov)},
+      // Alg. 7 (the P x o x Q and P x o x P intermediates by chunks of X7 rows)
+      {&ctx->U7, (size_t)(X7 * o * P)}, {&ctx->S7, (size_t)(P * ov)}, {&ctx->R7, (size_t)(P * ov)},
+      {&ctx->Rx, (size_t)(X7 * o * Q)}, {&ctx->Sx, (size_t)(X7 * o * Q)}, {&ctx->Cx, (size_t)(P * Q)}, {&ctx->Dx, (size_t)(P * Q)},
+      {&ctx->F7, (size_t)(exch_supported(o) && !(op.flags & THC_FLAG_UNFUSED_EXCHANGE) ? 1 : ctx->Xc * Q * Q)}, {&ctx->Gt, (size_t)(X7 * o * Q)}, {&ctx->Gts, (size_t)(X7 * o * Q)},
+      {&ctx->G7, (size_t)(X7 * ov)}, {&ctx->G7s, (size_t)(X7 * ov)},
       {&ctx->gws, (size_t)GEMM_WS},
   }; };
   // Grid-point chunk of the H accumulation (E, F, G for Ic points): every chunk reads and
@@ -781,51 +786,61 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   }
 
   // ---------------- Alg. 7: T2^2 rings (Eq. 35-37) ------------------------------------------
+  // Rows X of the P x o x Q intermediates are taken in chunks of X7 (the paper's split of Alg. 7
+  // over X); S^X and R^X are held for every X (the products with them need every row).
   ctx->section = "gemm@alg7";
   if (mask & THC_TERM_EQ35) {
+    const int64_t X7 = ctx->X7;
     // S^X_ia = - sum_YZ y_i^Y y_a^Z Gv[X][Y] Go[X][Z] T[Y][Z]  (Alg. 7)
-    {
-      Gemm g = batched(mk(o, P, P, Yo, P, false, T, P, false, ctx->U7, P), P, 0, 0, o * P);
-      g.kscaleA = ctx->Gv; g.ksA = 1; g.sksA = P;
+    for (int64_t X0 = 0; X0 < P; X0 += X7) {
+      const int64_t xc = std::min(X7, P - X0);
+      Gemm g = batched(mk(o, P, P, Yo, P, false, T, P, false, ctx->U7, P), xc, 0, 0, o * P);
+      g.kscaleA = ctx->Gv + X0 * P; g.ksA = 1; g.sksA = P;
       RCHK(gemm(ctx, g));
-      Gemm h = batched(mk(o, v, P, ctx->U7, P, false, Yv, P, true, ctx->S7, v, -1.0, 0.0), P, o * P, 0, ov);
-      h.kscaleB = ctx->Go; h.ksB = 1; h.sksB = P;
+      Gemm h = batched(mk(o, v, P, ctx->U7, P, false, Yv, P, true, ctx->S7 + X0 * ov, v, -1.0, 0.0), xc, o * P, 0, ov);
+      h.kscaleB = ctx->Go + X0 * P; h.ksB = 1; h.sksB = P;
       RCHK(gemm(ctx, h));
     }
     // R^X = 2 sum_Y y_i^Y y_a^Y (S T)[X][Y] + S^X  (Alg. 7, Eq. 36)
     MISC(k_copy2d(1, 1, P * ov, ctx->S7, P * ov, 0, ctx->R7, P * ov, 0, false, s));
     RCHK(gemm(ctx, mk(P, ov, P, ctx->ST, P, false, ctx->Bkr, P, true, ctx->R7, ov, 2.0, 1.0)));
-    // half-transformed: Rx[X][i][J] = sum_a R[X][i][a] x_a^J (and Sx)
-    RCHK(gemm(ctx, mk(P * o, Q, v, ctx->R7, v, false, xv, Q, false, ctx->Rx, Q)));
-    RCHK(gemm(ctx, mk(P * o, Q, v, ctx->S7, v, false, xv, Q, false, ctx->Sx, Q)));
-    // C^XI = sum_ia x_i^I x_a^I R^X_ia ; D = C z ; sigma += 2 c_D C D^T  (Alg. 7, Eq. 37)
-    MISC(k_diag_eri(P, Q, o, xo, ctx->Rx, ctx->Cx, s));
+    const bool fused = exch_supported(o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE);
+    for (int64_t X0 = 0; X0 < P; X0 += X7) {
+      const int64_t xc = std::min(X7, P - X0);
+      // half-transformed: Rx[X][i][J] = sum_a R[X][i][a] x_a^J (and Sx)
+      RCHK(gemm(ctx, mk(xc * o, Q, v, ctx->R7 + X0 * ov, v, false, xv, Q, false, ctx->Rx, Q)));
+      RCHK(gemm(ctx, mk(xc * o, Q, v, ctx->S7 + X0 * ov, v, false, xv, Q, false, ctx->Sx, Q)));
+      // C^XI = sum_ia x_i^I x_a^I R^X_ia  (Alg. 7, Eq. 37)
+      MISC(k_diag_eri(xc, Q, o, xo, ctx->Rx, ctx->Cx + X0 * Q, s));
+      // exchange parts (Alg. 7): fused on chip when o fits the kernel's tile, else two GEMMs per X
+      if (fused) {
+        Scope sc(ctx, "exch");
+        HIPCHK(exch_fused(o, Q, xc, xo, ctx->z, ctx->Rx, ctx->Gt, ctx->mixed, s));
+        HIPCHK(exch_fused(o, Q, xc, xo, ctx->z, ctx->Sx, ctx->Gts, ctx->mixed, s));
+      } else {
+        for (int64_t x0 = 0; x0 < xc; x0 += ctx->Xc) {
+          const int64_t xn = std::min(ctx->Xc, xc - x0);
+          for (int pass = 0; pass < 2; ++pass) {
+            const double* src = pass == 0 ? ctx->Rx : ctx->Sx;
+            double* dst = pass == 0 ? ctx->Gt : ctx->Gts;
+            // F^IJ = z^IJ sum_i x_i^I Rx[X][i][J]
+            Gemm g = batched(mk(Q, Q, o, xo, Q, true, src + x0 * o * Q, Q, false, ctx->F7, Q), xn, 0, o * Q, Q * Q);
+            g.hmul = ctx->z; g.ldh = Q; g.sH = 0;
+            RCHK(gemm(ctx, g));
+            // Gt[X][i][I] = sum_J x_i^J F^IJ
+            RCHK(gemm(ctx, batched(mk(o, Q, Q, xo, Q, false, ctx->F7, Q, true, dst + x0 * o * Q, Q), xn, 0, Q * Q, o * Q)));
+          }
+        }
+      }
+      // G^X_ia = sum_I Gt[X][i][I] x_a^I ; sigma[X] += c_D ( - G R^T + G~ S^T )
+      RCHK(gemm(ctx, mk(xc * o, v, Q, ctx->Gt, Q, false, xv, Q, true, ctx->G7, v)));
+      RCHK(gemm(ctx, mk(xc * o, v, Q, ctx->Gts, Q, false, xv, Q, true, ctx->G7s, v)));
+      RCHK(gemm(ctx, mk(xc, P, ov, ctx->G7, ov, false, ctx->R7, ov, true, ctx->sig + X0 * P, P, -C_D, 1.0)));
+      RCHK(gemm(ctx, mk(xc, P, ov, ctx->G7s, ov, false, ctx->S7, ov, true, ctx->sig + X0 * P, P, C_D, 1.0)));
+    }
+    // D = C z ; sigma += 2 c_D C D^T  (Alg. 7, Eq. 37)
     RCHK(gemm(ctx, mk(P, Q, Q, ctx->Cx, Q, false, ctx->z, Q, false, ctx->Dx, Q)));
     RCHK(gemm(ctx, mk(P, P, Q, ctx->Cx, Q, false, ctx->Dx, Q, true, ctx->sig, P, 2.0 * C_D, 1.0)));
-    // exchange parts (Alg. 7): fused on chip when o fits the kernel's tile, else two GEMMs per X chunk
-    if (exch_supported(o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE)) {
-      Scope sc(ctx, "exch");
-      HIPCHK(exch_fused(o, Q, P, xo, ctx->z, ctx->Rx, ctx->Gt, ctx->mixed, s));
-      HIPCHK(exch_fused(o, Q, P, xo, ctx->z, ctx->Sx, ctx->Gts, ctx->mixed, s));
-    } else
-    for (int64_t X0 = 0; X0 < P; X0 += ctx->Xc) {
-      const int64_t xc = std::min(ctx->Xc, P - X0);
-      for (int pass = 0; pass < 2; ++pass) {
-        const double* src = pass == 0 ? ctx->Rx : ctx->Sx;
-        double* dst = pass == 0 ? ctx->Gt : ctx->Gts;
-        // F^IJ = z^IJ sum_i x_i^I Rx[X][i][J]
-        Gemm g = batched(mk(Q, Q, o, xo, Q, true, src + X0 * o * Q, Q, false, ctx->F7, Q), xc, 0, o * Q, Q * Q);
-        g.hmul = ctx->z; g.ldh = Q; g.sH = 0;
-        RCHK(gemm(ctx, g));
-        // Gt[X][i][I] = sum_J x_i^J F^IJ
-        RCHK(gemm(ctx, batched(mk(o, Q, Q, xo, Q, false, ctx->F7, Q, true, dst + X0 * o * Q, Q), xc, 0, Q * Q, o * Q)));
-      }
-    }
-    // G^X_ia = sum_I Gt[X][i][I] x_a^I ; sigma += c_D ( - G R^T + G~ S^T )
-    RCHK(gemm(ctx, mk(P * o, v, Q, ctx->Gt, Q, false, xv, Q, true, ctx->G7, v)));
-    RCHK(gemm(ctx, mk(P * o, v, Q, ctx->Gts, Q, false, xv, Q, true, ctx->G7s, v)));
-    RCHK(gemm(ctx, mk(P, P, ov, ctx->G7, ov, false, ctx->R7, ov, true, ctx->sig, P, -C_D, 1.0)));
-    RCHK(gemm(ctx, mk(P, P, ov, ctx->G7s, ov, false, ctx->S7, ov, true, ctx->sig, P, C_D, 1.0)));
   }
 
   // ---------------- singles residual (Alg. 8, Alg. 10) ---------------------------------------
@@ -1042,7 +1057,7 @@ int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
   *out = nullptr;
   if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
       opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) || (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV)) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
-      opt->x_chunk < 0)
+      opt->x_chunk < 0 || opt->x7_chunk < 0)
     return THC_EINVAL;
   // the metric S = B^T B (nP x nP) and the ERI-grid Gram (nQ x nQ) have rank at most o v
   if (opt->nP > opt->o * opt->v || opt->nQ > opt->o * opt->v) return THC_EINVAL;
@@ -1532,6 +1547,8 @@ int thc_plan(const thc_ctx* ctx, thc_plan_info* out) {
   p.h_generations = ctx->nhtiles / (8 * ctx->hslots);
   p.h_tiles = ctx->hfilled;
   p.x_chunk = ctx->Xc;
+  p.x7_chunk = ctx->X7;
+  p.x7_chunks = (ctx->P + ctx->X7 - 1) / ctx->X7;
   p.exchange_fused = exch_supported(ctx->o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE);
   p.lvv_resident = ctx->lvv_resident ? 1 : 0;
   p.device_bytes = ctx->bytes;

@@ -189,6 +189,9 @@ CONFIGS = {
     "occ46": Config("occ46", 46, 24, 120, 110, 260, 30.0, 1015),
     "occ53": Config("occ53", 53, 20, 110, 100, 240, 30.0, 1016),
     "occ60": Config("occ60", 60, 18, 110, 100, 240, 30.0, 1017),
+    # o in (128, 200]: the exchange kernel's 13-row-block instantiation (o = 136 keeps the
+    # oracle's o^4 block at 2.7 GB)
+    "occ136": Config("occ136", 136, 4, 24, 120, 300, 30.0, 1021),
     # a rank large enough for the benchmark's kernel paths with an oracle that still runs in
     # seconds: 704-padded H ranks (about 43 H-kernel generations, so the backward grid-point walk
     # of odd generations), 128 x 128 tiles for the split symmetric Alg. 1 product

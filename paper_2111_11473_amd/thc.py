@@ -43,13 +43,14 @@ class Options(C.Structure):
     _fields_ = [("o", C.c_int64), ("v", C.c_int64), ("nL", C.c_int64), ("nP", C.c_int64), ("nQ", C.c_int64),
                 ("singles", C.c_int32), ("diis_max", C.c_int32), ("tol_energy", C.c_double),
                 ("a_block", C.c_int64), ("i_chunk", C.c_int64), ("x_block", C.c_int64), ("x_chunk", C.c_int64),
-                ("precision", C.c_int32), ("flags", C.c_int32)]
+                ("precision", C.c_int32), ("flags", C.c_int32), ("x7_chunk", C.c_int64)]
 
 
 class PlanInfo(C.Structure):
     _fields_ = [("a_block", C.c_int64), ("alg1_splits", C.c_int64), ("alg1_tile", C.c_int64),
                 ("x_block", C.c_int64), ("x_blocks", C.c_int64), ("i_chunk", C.c_int64), ("i_chunks", C.c_int64),
                 ("h_generations", C.c_int64), ("h_tiles", C.c_int64), ("x_chunk", C.c_int64),
+                ("x7_chunk", C.c_int64), ("x7_chunks", C.c_int64),
                 ("exchange_fused", C.c_int32), ("lvv_resident", C.c_int32), ("device_bytes", C.c_uint64)]
 
 
@@ -57,7 +58,6 @@ class SynthSpec(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("decay", C.c_double), ("coupling", C.c_double), ("gamma", C.c_double)]
 
 
-FLAG_UNFUSED_EXCHANGE = 1 << 0
 FLAG_STREAM_LVV = 1 << 1
 
 
@@ -213,12 +213,12 @@ class THC:
     """One THC-CCSD problem on the current GPU (all tensors float64, CUDA, contiguous)."""
 
     def __init__(self, o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0,
-                 x_block=0, x_chunk=0, flags=0, precision=0):
+                 x_block=0, x_chunk=0, flags=0, precision=0, x7_chunk=0):
         self.lib = load()
         self.o, self.v, self.nL, self.nP, self.nQ = o, v, nL, nP, nQ
         self.singles = bool(singles)
         opt = Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
-                      precision, flags)
+                      precision, flags, x7_chunk)
         h = C.c_void_p()
         rc = self.lib.thc_create(C.byref(opt), _stream(), C.byref(h))
         if rc != 0:

@@ -48,7 +48,7 @@ def _make(thc, cfg, **kw):
 
 
 @pytest.mark.parametrize("precision", [1, 2])
-@pytest.mark.parametrize("name", ["tiny", "medium", "occ40", "occ53", "occ70"])
+@pytest.mark.parametrize("name", ["tiny", "medium", "occ40", "occ53", "occ70", "occ136"])
 def test_mixed_residual_terms_within_bound(thc, name, precision):
     cfg = synth.CONFIGS[name]
     _say("terms", name, "precision", precision)

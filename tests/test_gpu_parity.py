@@ -132,7 +132,8 @@ def _check_terms(thc, cfg, s, ctx, Z0):
     assert abs(ctx.energy() - e_ref) < 1e-10 * max(1.0, abs(e_ref))
 
 
-@pytest.mark.parametrize("name", ["small", "tiny", "medium", "occ40", "occ46", "occ53", "occ60", "occ70", "one_occ", "complete"])
+@pytest.mark.parametrize("name", ["small", "tiny", "medium", "occ40", "occ46", "occ53", "occ60", "occ70", "occ136",
+                                  "one_occ", "complete"])
 def test_residual_terms_match_oracle(thc, name):
     """Each term group of the projected residual (Alg. 1-10) against the dense oracle, at a
     state with t1 != 0 (T1-dressed integrals exercised)."""
@@ -175,15 +176,20 @@ def test_converged_energy_matches_oracle(thc, singles):
 
 
 def test_small_blocks_and_chunks(thc):
-    """The same residual with tiny fused-pass blocks, ERI chunks, H blocks and the two-GEMM
-    Alg. 7 exchange in small X chunks (several blocks with ragged tails in every loop) against
-    the default plan (fused exchange)."""
+    """The same residual with tiny fused-pass blocks, ERI chunks, H blocks, Alg. 7 row chunks and
+    the two-GEMM Alg. 7 exchange in small X batches (several blocks with ragged tails in every
+    loop), and with Alg. 7 row chunks on the fused exchange, against the default plan."""
     cfg = synth.CONFIGS["medium"]
     _say("blocking medium")
     s, ctx, Z0 = _make(thc, cfg)
-    _, ctx2, _ = _make(thc, cfg, a_block=8, i_chunk=13, x_block=64, x_chunk=9, flags=thc.FLAG_UNFUSED_EXCHANGE)
+    assert ctx.plan()["x7_chunks"] == 1
+    _, ctx2, _ = _make(thc, cfg, a_block=8, i_chunk=13, x_block=64, x_chunk=9, x7_chunk=37,
+                       flags=thc.FLAG_UNFUSED_EXCHANGE)
+    assert ctx2.plan()["x7_chunks"] == 5
+    _, ctx3, _ = _make(thc, cfg, x7_chunk=50)
     Z, t1 = _state(s, Z0, 5)
     a, a1 = ctx.residual(_dev(Z), _dev(t1))
-    b, b1 = ctx2.residual(_dev(Z), _dev(t1))
-    assert np.abs(_host(a) - _host(b)).max() < 1e-12 * np.abs(_host(a)).max()
-    assert np.abs(_host(a1) - _host(b1)).max() < 1e-12 * np.abs(_host(a1)).max()
+    for c in (ctx2, ctx3):
+        b, b1 = c.residual(_dev(Z), _dev(t1))
+        assert np.abs(_host(a) - _host(b)).max() < 1e-12 * np.abs(_host(a)).max()
+        assert np.abs(_host(a1) - _host(b1)).max() < 1e-12 * np.abs(_host(a1)).max()
