@@ -88,6 +88,14 @@ typedef struct thc_options {
  * matrix of the ERI grid would be singular), or options out of range; nothing is created then. */
 int thc_create(const thc_options* opt, void* stream, thc_ctx** out);
 
+/* As thc_create, with all device working memory taken from the caller's workspace: the library
+ * then never allocates device memory (set-up scratch included).  dev_workspace: device pointer,
+ * 256-byte aligned, ws_bytes long, owned by the caller and kept alive until thc_destroy.  The
+ * plan (blocking of the paper's loops) is sized to ws_bytes; thc_plan_query gives the bytes a
+ * plan needs.  THC_ENOMEM from thc_build_factors if no plan fits. */
+int thc_create_with_workspace(const thc_options* opt, void* dev_workspace, size_t ws_bytes, void* stream,
+                              thc_ctx** out);
+
 /* Set-up (paper Eq. 9-14, 17-20; Alg. 6): copies the integrals and factors, forms the
  * Gram matrices o = Xo^T Xo, v = Xv^T Xv and the metric S = o (Hadamard) v, fits the ERI core
  * z = xi^T xi by least squares against the ovov Cholesky block, forms B_ia^I, solves the
@@ -196,6 +204,12 @@ typedef struct thc_plan_info {
   uint64_t device_bytes;  /* device working memory */
 } thc_plan_info;
 int thc_plan(const thc_ctx* ctx, thc_plan_info* out);
+/* The plan thc_build_factors would make for these options within budget_bytes of device memory
+ * (synthetic != 0: inputs from thc_set_synthetic), without creating a context or touching device
+ * memory; device_bytes is the working memory it needs (the workspace size for
+ * thc_create_with_workspace).  The H-kernel generation count uses the current device, or the
+ * MI355X's 64 resident tiles per XCD when there is none.  THC_ENOMEM if nothing fits. */
+int thc_plan_query(const thc_options* opt, int synthetic, uint64_t budget_bytes, thc_plan_info* out);
 
 /* Kernel timing with HIP events on the context stream.  thc_profile(ctx, 1) starts recording
  * (and clears earlier records); thc_profile_get synchronizes and returns, for the kernel

@@ -58,6 +58,11 @@ struct thc_ctx {
 
   std::vector<void*> allocs;
   size_t bytes = 0;
+  void* ws = nullptr;            // caller's device workspace (thc_create_with_workspace), or null
+  size_t ws_bytes = 0;
+  double* arena = nullptr;       // every buffer of the context lies in here
+  double* setup_scratch = nullptr;  // scratch of the set-up (overlays the Alg. 6 region)
+  size_t setup_len = 0;             // doubles
 
   // factors (device)
   double *Loo = nullptr, *Lov = nullptr, *Lvv = nullptr, *eps = nullptr;
@@ -271,22 +276,6 @@ Gemm batched(Gemm g, int64_t batch, int64_t sA, int64_t sB, int64_t sC) {
     HIPCHK(expr);                       \
   } while (0)
 
-int alloc(thc_ctx* ctx, double** p, size_t count) {
-  if (count == 0) count = 1;
-  void* q = nullptr;
-  if (hipMalloc(&q, count * sizeof(double)) != hipSuccess) {
-    char buf[160];
-    snprintf(buf, sizeof buf, "hipMalloc of %zu bytes failed (held: %zu bytes)", count * sizeof(double), ctx->bytes);
-    ctx->err = buf;
-    (void)hipGetLastError();
-    return THC_ENOMEM;
-  }
-  ctx->allocs.push_back(q);
-  ctx->bytes += count * sizeof(double);
-  *p = (double*)q;
-  return THC_OK;
-}
-
 int zero(thc_ctx* ctx, double* p, size_t count) {
   MISC(k_fill((int64_t)count, 0.0, p, ctx->stream));
   return THC_OK;
@@ -380,64 +369,36 @@ int check_finite_host(thc_ctx* ctx, const double* x, size_t n, const char* what)
 }
 
 // ---------------------------------------------------------------------------------------
-// Working-memory plan.
-int plan_and_alloc(thc_ctx* ctx) {
-  const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
-  // Y, Z ranks of the H accumulation padded to its 16-wide blocks; X ranks to its 64-lane tiles
-  const int64_t Pp = ctx->Pp = ((P + 15) / 16) * 16;
-  const int64_t P64 = ((P + 63) / 64) * 64;
-  const thc_options& op = ctx->opt;
-  // fused-pass block: four nb x P^2 panels within ~4 GB
-  int64_t nb = op.a_block > 0 ? op.a_block : std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(4.0e9 / (32.0 * P * P))));
-  nb = std::min(nb, nL);
-  ctx->nb = nb;
-  // split of the N_L P-deep sum of Alg. 1: at most 512 workgroups of 128 x 128 tiles (one round
-  // at two per CU), counting the tiles on and above the diagonal (the product is symmetric)
-  const int64_t nt128 = (P + 127) / 128, t128 = nt128 * (nt128 + 1) / 2;
-  ctx->KS = std::max<int64_t>(1, std::min<int64_t>(16, 512 / t128));
-  {
-    Gemm g;  // the first block's sum_A C^A T C^A^T, as residual_impl issues it
-    g.M = g.N = P;
-    g.K = nb * P;
-    g.ksplit = (int)ctx->KS;
-    g.upper = true;
-    ctx->alg1_tile = gemm_tile_edge_split(g);
-  }
-  // H block over X: whole rank when it fits in ~40 GB
-  int64_t Xb = op.x_block;
-  if (Xb <= 0) {
-    const double hb = 40.0e9 / (8.0 * (double)Pp * Pp);
-    Xb = std::min<int64_t>(P64, std::max<int64_t>(64, ((int64_t)hb / 64) * 64));
-  }
-  if (Xb % 64 != 0 || Xb > P64) {
-    ctx->err = "x_block must be a multiple of 64 and at most the rank rounded up to 64";
-    return THC_EINVAL;
-  }
-  ctx->Xb = Xb;
-  int64_t Xc = op.x_chunk;
-  if (Xc <= 0) Xc = std::max<int64_t>(1, (int64_t)(2.0e9 / (8.0 * (double)Q * Q)));
-  ctx->Xc = std::min(Xc, P);
-  // Alg. 7 chunk of X rows: every row when the chunked intermediates (U, Rx, Sx, Gt, Gt~, G, G~:
-  // o P + 4 o Q + 2 o v per row) fit in ~24 GB
-  int64_t X7 = op.x7_chunk;
-  if (X7 <= 0) X7 = std::max<int64_t>(1, (int64_t)(24.0e9 / (8.0 * (double)(o * P + 4 * o * Q + 2 * ov))));
-  X7 = ctx->X7 = std::min(X7, P);
-  const int64_t PP = P * P;
+// Working-memory plan.  Every device buffer of a context is a piece of one arena (one
+// allocation, or the caller's workspace): the persistent buffers (factors, state, DIIS, the
+// fused pass's block buffers, S and R of Alg. 7), the Alg. 6 region (the H block, its E, F, G
+// grid-point chunk and the C, D operands), which the set-up also uses as its scratch before the
+// first residual, and the chunk buffers of Alg. 7.  The plan picks the H block Xb (multiple of
+// 64), the grid-point chunk Ic and the Alg. 7 row chunk X7 so the arena fits the budget: Ic near
+// 256 or more (each chunk reads and writes the H block once: H traffic per residual is
+// 16 P Pp^2 Q / Ic bytes, independent of Xb), then the largest Xb (each H block recomputes the
+// G chunks, the paper's redundancy).
+constexpr double MEM_CAP = 270.0e9;   // at most this much device memory without a workspace
+constexpr size_t ALIGN_D = 32;       // buffers start on 256-byte boundaries
 
-  // vv block of the Cholesky vectors: held (caller inputs always), or, for synthetic inputs,
-  // regenerated block by block in the fused pass when asked or when holding it would leave less
-  // than a quarter of the free device memory for the rest
-  ctx->lvv_resident = true;
-  if (ctx->synth) {
-    size_t freeb = 0, totalb = 0;
-    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) { ctx->err = "hipMemGetInfo failed"; return THC_EDEVICE; }
-    ctx->lvv_resident = !(op.flags & THC_FLAG_STREAM_LVV) && 8.0 * (double)nL * v * v < 0.75 * (double)freeb - 8.0e9;
-  }
+struct BufSpec {
+  double** p;
+  size_t n;  // doubles
+};
+
+size_t aligned(size_t n) { return (std::max<size_t>(n, 1) + ALIGN_D - 1) / ALIGN_D * ALIGN_D; }
+
+double list_bytes(const std::vector<BufSpec>& l) {
+  double b = 0.0;
+  for (const auto& a : l) b += 8.0 * (double)aligned(a.n);
+  return b;
+}
+
+std::vector<BufSpec> persistent_list(thc_ctx* ctx) {
+  const int64_t o = ctx->o, v = ctx->v, n = ctx->n, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
+  const int64_t PP = P * P, nb = ctx->nb, dm = ctx->opt.diis_max;
   const int64_t nlvv = ctx->lvv_resident ? nL : nb;
-  struct A { double** p; size_t n; };
-  const int64_t dm = ctx->opt.diis_max;
-  ctx->Ic = 0;  // the chunk-sized entries are sized below, from what the rest leaves free
-  auto make_list = [&]() -> std::vector<A> { return {
+  return {
       {&ctx->Loo, (size_t)(nL * o * o)}, {&ctx->Lov, (size_t)(nL * ov)}, {&ctx->Lvv, (size_t)(nlvv * v * v)},
       {&ctx->eps, (size_t)n}, {&ctx->Yo, (size_t)(o * P)}, {&ctx->Yv, (size_t)(v * P)},
       {&ctx->xo, (size_t)(o * Q)}, {&ctx->xv, (size_t)(v * Q)}, {&ctx->Go, (size_t)PP}, {&ctx->Gv, (size_t)PP},
@@ -458,72 +419,220 @@ int plan_and_alloc(thc_ctx* ctx) {
       {&ctx->sig28, (size_t)(ctx->KS * PP)}, {&ctx->C3, (size_t)PP}, {&ctx->Abar, (size_t)(P * nL)},
       {&ctx->At, (size_t)(P * nL)}, {&ctx->Hh, (size_t)(P * nL)}, {&ctx->xioo, (size_t)(o * o)},
       {&ctx->xivv, (size_t)(v * v)}, {&ctx->s38, (size_t)ov}, {&ctx->dvecA, (size_t)nL}, {&ctx->trK, (size_t)nL},
-      {&ctx->ej, (size_t)nL}, {&ctx->ek, (size_t)(nL * 64)}, {&ctx->Fin, (size_t)(n * n)}, {&ctx->Fh, (size_t)(n * n)}, {&ctx->Jov, (size_t)ov}, {&ctx->Jvo, (size_t)ov},
+      {&ctx->ej, (size_t)nL}, {&ctx->ek, (size_t)(nL * 64)}, {&ctx->Fin, (size_t)(n * n)}, {&ctx->Fh, (size_t)(n * n)},
+      {&ctx->Jov, (size_t)ov}, {&ctx->Jvo, (size_t)ov},
       // assembly
       {&ctx->ST, (size_t)PP}, {&ctx->Dt, (size_t)(P * nL)}, {&ctx->K29, (size_t)(P * nL)}, {&ctx->Qm, (size_t)PP},
       {&ctx->ot, (size_t)PP}, {&ctx->vt, (size_t)PP}, {&ctx->E9, (size_t)PP}, {&ctx->tmpoP, (size_t)(o * P)},
       {&ctx->tmpvP, (size_t)(v * P)}, {&ctx->Fxoo, (size_t)(o * o)}, {&ctx->Fxvv, (size_t)(v * v)},
       {&ctx->Tf, (size_t)P}, {&ctx->fd, (size_t)P},
-      // Alg. 6
-      {&ctx->C6, (size_t)(o * Xb * Pp)}, {&ctx->D6, (size_t)(v * Xb * Pp)}, {&ctx->Ec, (size_t)(ctx->Ic * Xb * Pp)},
-      {&ctx->Fc, (size_t)(ctx->Ic * Xb * Pp)}, {&ctx->Gc, (size_t)(ctx->Ic * Pp * Pp)}, {&ctx->GYc, (size_t)(ctx->Ic * o * P)},
-      {&ctx->Hb, (size_t)(Xb * Pp * Pp)}, {&ctx->R1, (size_t)(Xb * Pp * o)}, {&ctx->I6, (size_t)(Xb * ov)},
-      // Alg. 7 (the P x o x Q and P x o x P intermediates by chunks of X7 rows)
-      {&ctx->U7, (size_t)(X7 * o * P)}, {&ctx->S7, (size_t)(P * ov)}, {&ctx->R7, (size_t)(P * ov)},
-      {&ctx->Rx, (size_t)(X7 * o * Q)}, {&ctx->Sx, (size_t)(X7 * o * Q)}, {&ctx->Cx, (size_t)(P * Q)}, {&ctx->Dx, (size_t)(P * Q)},
-      {&ctx->F7, (size_t)(exch_supported(o) && !(op.flags & THC_FLAG_UNFUSED_EXCHANGE) ? 1 : ctx->Xc * Q * Q)}, {&ctx->Gt, (size_t)(X7 * o * Q)}, {&ctx->Gts, (size_t)(X7 * o * Q)},
-      {&ctx->G7, (size_t)(X7 * ov)}, {&ctx->G7s, (size_t)(X7 * ov)},
+      // Alg. 7 quantities needed for every X
+      {&ctx->S7, (size_t)(P * ov)}, {&ctx->R7, (size_t)(P * ov)}, {&ctx->Cx, (size_t)(P * Q)}, {&ctx->Dx, (size_t)(P * Q)},
       {&ctx->gws, (size_t)GEMM_WS},
-  }; };
-  // Grid-point chunk of the H accumulation (E, F, G for Ic points): every chunk reads and
-  // writes the whole H block once, so chunks are large -- up to 16 GB, and at most half of the
-  // device memory the rest of the plan leaves free.  (Measured at the fp64 size, with the
-  // H-kernel launched one generation at a time: 367 ms per residual at 318 points per chunk,
-  // 356 at 636, 361 at 1250.)
+  };
+}
+
+// Alg. 6 region for an H block of Xb ranks and grid-point chunks of Ic points (FP32 copies of
+// E, F in the mixed-precision path).
+std::vector<BufSpec> region6_list(thc_ctx* ctx, double** e32, double** f32) {
+  const int64_t o = ctx->o, v = ctx->v, P = ctx->P, Pp = ctx->Pp, ov = ctx->ov, Xb = ctx->Xb, Ic = ctx->Ic;
+  std::vector<BufSpec> l = {
+      {&ctx->C6, (size_t)(o * Xb * Pp)}, {&ctx->D6, (size_t)(v * Xb * Pp)}, {&ctx->Ec, (size_t)(Ic * Xb * Pp)},
+      {&ctx->Fc, (size_t)(Ic * Xb * Pp)}, {&ctx->Gc, (size_t)(Ic * Pp * Pp)}, {&ctx->GYc, (size_t)(Ic * o * P)},
+      {&ctx->Hb, (size_t)(Xb * Pp * Pp)}, {&ctx->R1, (size_t)(Xb * Pp * o)}, {&ctx->I6, (size_t)(Xb * ov)}};
+  if (ctx->opt.precision >= 1) {
+    l.push_back({e32, (size_t)((Ic * Xb * Pp + 1) / 2)});
+    l.push_back({f32, (size_t)((Ic * Xb * Pp + 1) / 2)});
+  }
+  return l;
+}
+
+std::vector<BufSpec> alg7_list(thc_ctx* ctx) {
+  const int64_t o = ctx->o, P = ctx->P, Q = ctx->Q, ov = ctx->ov, X7 = ctx->X7;
+  const bool fused = exch_supported(o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE);
+  return {{&ctx->U7, (size_t)(X7 * o * P)}, {&ctx->Rx, (size_t)(X7 * o * Q)}, {&ctx->Sx, (size_t)(X7 * o * Q)},
+          {&ctx->F7, (size_t)(fused ? 1 : ctx->Xc * Q * Q)}, {&ctx->Gt, (size_t)(X7 * o * Q)},
+          {&ctx->Gts, (size_t)(X7 * o * Q)}, {&ctx->G7, (size_t)(X7 * ov)}, {&ctx->G7s, (size_t)(X7 * ov)}};
+}
+
+// Doubles of device scratch the set-up (thc_build_factors) holds at once.
+size_t setup_doubles(const thc_ctx* ctx) {
+  const int64_t o = ctx->o, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
+  const int64_t CBn = (std::max(Q, P) + CB - 1) / CB;
+  const int64_t rc0 = std::max<int64_t>(1, std::min<int64_t>(ov, (int64_t)(1.0e9 / (8.0 * ov))));
+  size_t d = 0;
+  for (int64_t c : {Q * Q, Q * Q, CBn * CB * CB, Q * nL, std::min<int64_t>(nL, 256) * o * Q,
+                    std::max(Q, P) * std::max<int64_t>(std::max(nL, P), CB), CB * std::max(std::max(nL, P), Q),
+                    P * P, P * P, P * P, rc0 * ov, rc0 * P})
+    d += aligned((size_t)c);
+  if (ctx->synth) d += aligned((size_t)(nL * nL)) + 2 * aligned((size_t)nL);  // the gamma rule
+  return d;
+}
+
+// Tiles of the H-kernel table (X tile, Y block, Z block >= Y block, Z slice) and its length with
+// the empty slots that complete the last generation.
+void tile_counts(int64_t Pp, int64_t Xb, int64_t slots, int64_t* tiles, int64_t* entries) {
+  const int64_t nB = Pp / 16, nX = Xb / 64;
+  int64_t lin = 0;
+  for (int64_t yb = 0; yb < nB; ++yb) lin += (nB - yb) * 2;
+  lin *= nX;
+  const int64_t runs = (lin + slots - 1) / slots;
+  *tiles = lin;
+  *entries = ((runs + 7) / 8) * 8 * slots;
+}
+
+size_t tile_table_doubles(int64_t Pp, int64_t Xb, int64_t slots) {
+  int64_t t = 0, e = 0;
+  tile_counts(Pp, Xb, slots, &t, &e);
+  return aligned((size_t)((e + 1) / 2));
+}
+
+// Picks the blocking (nb, KS, Xb, Ic, X7, the residency of the vv block) for a budget of device
+// bytes and fills ctx->plan_bytes; THC_ENOMEM if even the smallest blocking does not fit.
+int choose_plan(thc_ctx* ctx, double budget, int64_t slots) {
+  const int64_t o = ctx->o, v = ctx->v, nL = ctx->nL, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
+  const int64_t Pp = ctx->Pp = ((P + 15) / 16) * 16;  // Y, Z ranks of H padded to its 16-wide blocks
+  const int64_t P64 = ((P + 63) / 64) * 64;           // X ranks padded to its 64-lane tiles
+  const thc_options& op = ctx->opt;
+  // fused-pass block: four nb x P^2 panels within ~4 GB
+  int64_t nb = op.a_block > 0 ? op.a_block : std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(4.0e9 / (32.0 * P * P))));
+  ctx->nb = nb = std::min(nb, nL);
+  // split of the N_L P-deep sum of Alg. 1: at most 512 workgroups of 128 x 128 tiles (one round
+  // at two per CU), counting the tiles on and above the diagonal (the product is symmetric)
+  const int64_t nt128 = (P + 127) / 128, t128 = nt128 * (nt128 + 1) / 2;
+  ctx->KS = std::max<int64_t>(1, std::min<int64_t>(16, 512 / t128));
+  {
+    Gemm g;  // the first block's sum_A C^A T C^A^T, as residual_impl issues it
+    g.M = g.N = P;
+    g.K = nb * P;
+    g.ksplit = (int)ctx->KS;
+    g.upper = true;
+    ctx->alg1_tile = gemm_tile_edge_split(g);
+  }
+  // the vv Cholesky block: held (caller inputs always); synthetic inputs regenerate it block by
+  // block in the fused pass when asked or when it would take more than 40% of the budget
+  ctx->lvv_resident = !ctx->synth || (!(op.flags & THC_FLAG_STREAM_LVV) && 8.0 * (double)nL * v * v < 0.4 * budget);
+  int64_t Xc = op.x_chunk;
+  if (Xc <= 0) Xc = std::max<int64_t>(1, (int64_t)(2.0e9 / (8.0 * (double)Q * Q)));
+  ctx->Xc = std::min(Xc, P);
+  // Alg. 7 row chunk: every row when the chunked intermediates (U, Rx, Sx, Gt, Gt~, G, G~:
+  // o P + 4 o Q + 2 o v per row) fit in min(24 GB, a tenth of the budget)
+  int64_t X7 = op.x7_chunk;
+  const double per7 = 8.0 * (double)(o * P + 4 * o * Q + 2 * ov);
+  if (X7 <= 0) X7 = std::max<int64_t>(1, (int64_t)(std::min(24.0e9, 0.1 * budget) / per7));
+  ctx->X7 = std::min(X7, P);
+  const double pers = list_bytes(persistent_list(ctx));
+  const double a7 = list_bytes(alg7_list(ctx));
+  const double setup = 8.0 * (double)setup_doubles(ctx);
+  // H block and grid-point chunk
+  auto fixed6 = [&](int64_t Xb) { return 8.0 * (double)Xb * ((double)Pp * (o + v + Pp + o) + (double)ov); };
+  auto per_i = [&](int64_t Xb) {
+    return 8.0 * (2.0 * (double)Xb * Pp + (double)Pp * Pp + (double)o * P) + (op.precision >= 1 ? 8.0 * (double)Xb * Pp : 0.0);
+  };
+  if (op.x_block > 0 && (op.x_block % 64 != 0 || op.x_block > P64)) {
+    ctx->err = "x_block must be a multiple of 64 and at most the rank rounded up to 64";
+    return THC_EINVAL;
+  }
+  const int64_t ic_min = op.i_chunk > 0 ? std::min(op.i_chunk, Q) : std::min<int64_t>(Q, 256);
+  int64_t Xb = 0;
+  double rem = 0.0;
+  for (int64_t xb = op.x_block > 0 ? op.x_block : P64; xb >= 64; xb -= 64) {
+    const double tiles = 8.0 * (double)tile_table_doubles(Pp, xb, slots);
+    rem = budget - pers - a7 - tiles - fixed6(xb);
+    const double r6 = fixed6(xb) + per_i(xb) * (double)ic_min;
+    if (rem >= per_i(xb) * (double)ic_min && rem + r6 - std::max(r6, setup) >= 0.0) {
+      Xb = xb;
+      break;
+    }
+    if (op.x_block > 0) break;
+  }
+  if (Xb == 0) {
+    char buf[300];
+    snprintf(buf, sizeof buf,
+             "the working memory does not fit %.1f GB: %.1f GB persistent (factors, state, fused-pass blocks), "
+             "%.1f GB Alg. 7 chunks, and an H block of 64 ranks with %lld grid points needs %.1f GB more",
+             budget / 1e9, pers / 1e9, a7 / 1e9, (long long)ic_min, (fixed6(64) + per_i(64) * ic_min) / 1e9);
+    ctx->err = buf;
+    return THC_ENOMEM;
+  }
+  ctx->Xb = Xb;
   int64_t Ic = op.i_chunk;
-  if (Ic <= 0) {
-    double fixed = 0.0;
-    for (auto& a : make_list()) fixed += 8.0 * (double)a.n;
+  if (Ic <= 0) Ic = std::max<int64_t>(1, (int64_t)(std::min(rem, std::max(16.0e9, 256.0 * per_i(Xb))) / per_i(Xb)));
+  ctx->Ic = std::min(Ic, Q);
+  return THC_OK;
+}
+
+// The plan for the context's budget (its workspace, else the device's free memory up to
+// MEM_CAP), then the arena and every buffer in it.
+int plan_and_alloc(thc_ctx* ctx) {
+  ctx->hslots = h_slots_per_xcd();
+  if (ctx->hslots < 1) { ctx->err = "cannot query the device for the H-kernel launch"; return THC_EDEVICE; }
+  double budget = (double)ctx->ws_bytes;
+  if (!ctx->ws) {
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) { ctx->err = "hipMemGetInfo failed"; return THC_EDEVICE; }
-    const double per_i = 8.0 * (2.0 * (double)Xb * Pp + (double)Pp * Pp + (double)o * P) +
-                         (op.precision >= 1 ? 4.0 * 2.0 * (double)Xb * Pp : 0.0);
-    const double budget = std::min(16.0e9, std::max(2.0e9, 0.5 * ((double)freeb - fixed)));
-    Ic = std::max<int64_t>(1, (int64_t)(budget / per_i));
+    budget = std::min(MEM_CAP, (double)freeb - 2.0e9);
   }
-  ctx->Ic = std::min(Ic, Q);
-  const std::vector<A> list = make_list();
-  for (auto& a : list) RCHK(alloc(ctx, a.p, a.n));
-  // zero-padded operands of the H-kernel: padding must stay zero
+  RCHK(choose_plan(ctx, budget, ctx->hslots));
+  const std::vector<uint32_t> tiles = h_tiles(ctx->Pp, ctx->Xb, ctx->hslots);
+  double *e32 = nullptr, *f32 = nullptr, *tb = nullptr;
+  std::vector<BufSpec> pers = persistent_list(ctx);
+  pers.push_back({&tb, (tiles.size() + 1) / 2});
+  const std::vector<BufSpec> r6 = region6_list(ctx, &e32, &f32), a7 = alg7_list(ctx);
+  size_t np = 0, n6 = 0, n7 = 0;
+  for (const auto& a : pers) np += aligned(a.n);
+  for (const auto& a : r6) n6 += aligned(a.n);
+  for (const auto& a : a7) n7 += aligned(a.n);
+  const size_t nsetup = setup_doubles(ctx);
+  const size_t total = np + std::max(n6, nsetup) + n7;
+  if (ctx->ws) {
+    if (8.0 * (double)total > (double)ctx->ws_bytes) { ctx->err = "workspace too small for the plan"; return THC_ENOMEM; }
+    ctx->arena = (double*)ctx->ws;
+  } else {
+    void* q = nullptr;
+    if (hipMalloc(&q, total * sizeof(double)) != hipSuccess) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "hipMalloc of the %.2f GB working memory failed", 8.0 * (double)total / 1e9);
+      ctx->err = buf;
+      (void)hipGetLastError();
+      return THC_ENOMEM;
+    }
+    ctx->allocs.push_back(q);
+    ctx->arena = (double*)q;
+  }
+  ctx->bytes = total * sizeof(double);
+  double* at = ctx->arena;
+  for (const auto& a : pers) { *a.p = at; at += aligned(a.n); }
+  ctx->setup_scratch = at;  // the set-up's scratch overlays the Alg. 6 region
+  ctx->setup_len = std::max(n6, nsetup);
+  for (const auto& a : r6) { *a.p = at; at += aligned(a.n); }
+  at = ctx->setup_scratch + std::max(n6, nsetup);
+  for (const auto& a : a7) { *a.p = at; at += aligned(a.n); }
+  ctx->Ec32 = reinterpret_cast<float*>(e32);
+  ctx->Fc32 = reinterpret_cast<float*>(f32);
+  ctx->htiles = reinterpret_cast<uint32_t*>(tb);
+  ctx->nhtiles = (int64_t)tiles.size();
+  ctx->hfilled = 0;
+  for (uint32_t t : tiles) ctx->hfilled += (t & 0x80000000u) ? 0 : 1;
+  RCHK(h2d(ctx, ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t)));
+  ctx->diisB.assign((size_t)std::max<int64_t>(ctx->opt.diis_max, 1) * std::max<int64_t>(ctx->opt.diis_max, 1), 0.0);
+  return THC_OK;
+}
+
+// The Alg. 6 operands whose padding must stay zero, cleared once the set-up no longer uses the
+// region as scratch.
+int clear_region6(thc_ctx* ctx) {
+  const int64_t o = ctx->o, v = ctx->v, Pp = ctx->Pp, Xb = ctx->Xb, Ic = ctx->Ic;
   RCHK(zero(ctx, ctx->C6, o * Xb * Pp));
   RCHK(zero(ctx, ctx->D6, v * Xb * Pp));
-  RCHK(zero(ctx, ctx->Gc, ctx->Ic * Pp * Pp));
+  RCHK(zero(ctx, ctx->Gc, Ic * Pp * Pp));
   RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
-  RCHK(zero(ctx, ctx->Ec, ctx->Ic * Xb * Pp));
-  RCHK(zero(ctx, ctx->Fc, ctx->Ic * Xb * Pp));
-  {
-    ctx->hslots = h_slots_per_xcd();
-    if (ctx->hslots < 1) { ctx->err = "cannot query the device for the H-kernel launch"; return THC_EDEVICE; }
-    const std::vector<uint32_t> tiles = h_tiles(Pp, Xb, ctx->hslots);
-    double* tb = nullptr;
-    RCHK(alloc(ctx, &tb, (tiles.size() + 1) / 2));
-    ctx->htiles = reinterpret_cast<uint32_t*>(tb);
-    ctx->nhtiles = (int64_t)tiles.size();
-    ctx->hfilled = 0;
-    for (uint32_t t : tiles) ctx->hfilled += (t & 0x80000000u) ? 0 : 1;
-    RCHK(h2d(ctx, ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t)));
+  RCHK(zero(ctx, ctx->Ec, Ic * Xb * Pp));
+  RCHK(zero(ctx, ctx->Fc, Ic * Xb * Pp));
+  if (ctx->Ec32) {
+    RCHK(zero(ctx, reinterpret_cast<double*>(ctx->Ec32), (Ic * Xb * Pp + 1) / 2));
+    RCHK(zero(ctx, reinterpret_cast<double*>(ctx->Fc32), (Ic * Xb * Pp + 1) / 2));
   }
-  if (op.precision >= 1) {  // FP32 E, F for the mixed-precision H-kernel
-    const int64_t nf = ctx->Ic * Xb * Pp;
-    double *e32 = nullptr, *f32 = nullptr;
-    RCHK(alloc(ctx, &e32, (size_t)((nf + 1) / 2)));
-    RCHK(alloc(ctx, &f32, (size_t)((nf + 1) / 2)));
-    RCHK(zero(ctx, e32, (nf + 1) / 2));
-    RCHK(zero(ctx, f32, (nf + 1) / 2));
-    ctx->Ec32 = reinterpret_cast<float*>(e32);
-    ctx->Fc32 = reinterpret_cast<float*>(f32);
-  }
-  ctx->diisB.assign((size_t)std::max<int64_t>(dm, 1) * std::max<int64_t>(dm, 1), 0.0);
   return THC_OK;
 }
 
@@ -1052,15 +1161,76 @@ int mlp_bwd(thc_mlp* ctx, const float* X, const float* T, int64_t R) {
 
 extern "C" {
 
+namespace {
+bool options_valid(const thc_options* opt) {
+  if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
+      opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) ||
+      (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV)) != 0 || opt->a_block < 0 ||
+      opt->i_chunk < 0 || opt->x_block < 0 || opt->x_chunk < 0 || opt->x7_chunk < 0)
+    return false;
+  // the metric S = B^T B (nP x nP) and the ERI-grid Gram (nQ x nQ) have rank at most o v
+  return opt->nP <= opt->o * opt->v && opt->nQ <= opt->o * opt->v;
+}
+
+void fill_plan_info(const thc_ctx* ctx, int64_t tiles, int64_t entries, int64_t slots, double bytes, thc_plan_info* out) {
+  thc_plan_info p{};
+  p.a_block = ctx->nb;
+  p.alg1_splits = ctx->KS;
+  p.alg1_tile = ctx->alg1_tile;
+  p.x_block = ctx->Xb;
+  p.x_blocks = (ctx->P + ctx->Xb - 1) / ctx->Xb;
+  p.i_chunk = ctx->Ic;
+  p.i_chunks = (ctx->Q + ctx->Ic - 1) / ctx->Ic;
+  p.h_generations = entries / (8 * slots);
+  p.h_tiles = tiles;
+  p.x_chunk = ctx->Xc;
+  p.x7_chunk = ctx->X7;
+  p.x7_chunks = (ctx->P + ctx->X7 - 1) / ctx->X7;
+  p.exchange_fused = exch_supported(ctx->o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE);
+  p.lvv_resident = ctx->lvv_resident ? 1 : 0;
+  p.device_bytes = (uint64_t)bytes;
+  *out = p;
+}
+}  // namespace
+
+int thc_create_with_workspace(const thc_options* opt, void* dev_workspace, size_t ws_bytes, void* stream,
+                              thc_ctx** out) {
+  if (!opt || !out || !dev_workspace || ws_bytes == 0 || ((uintptr_t)dev_workspace % 256) != 0) return THC_EINVAL;
+  const int rc = thc_create(opt, stream, out);
+  if (rc != THC_OK) return rc;
+  (*out)->ws = dev_workspace;
+  (*out)->ws_bytes = ws_bytes;
+  return THC_OK;
+}
+
+int thc_plan_query(const thc_options* opt, int synthetic, uint64_t budget_bytes, thc_plan_info* out) {
+  if (!opt || !out || !options_valid(opt) || budget_bytes == 0) return THC_EINVAL;
+  thc_ctx c;
+  c.opt = *opt;
+  c.o = opt->o; c.v = opt->v; c.n = opt->o + opt->v; c.nL = opt->nL;
+  c.P = opt->nP; c.Q = opt->nQ; c.ov = opt->o * opt->v;
+  c.synth = synthetic != 0;
+  int64_t slots = h_slots_per_xcd();  // from the current device when there is one
+  if (slots < 1) {
+    (void)hipGetLastError();
+    slots = 64;  // 32 CUs per XCD, two H-kernel workgroups per CU (MI355X)
+  }
+  const int rc = choose_plan(&c, (double)budget_bytes, slots);
+  if (rc != THC_OK) return rc;
+  double *e32 = nullptr, *f32 = nullptr;
+  const double pers = list_bytes(persistent_list(&c)), r6 = list_bytes(region6_list(&c, &e32, &f32));
+  const double a7 = list_bytes(alg7_list(&c)), setup = 8.0 * (double)setup_doubles(&c);
+  int64_t tiles = 0, entries = 0;
+  tile_counts(c.Pp, c.Xb, slots, &tiles, &entries);
+  fill_plan_info(&c, tiles, entries, slots, pers + 8.0 * (double)tile_table_doubles(c.Pp, c.Xb, slots) +
+                                               std::max(r6, setup) + a7, out);
+  return THC_OK;
+}
+
 int thc_create(const thc_options* opt, void* stream, thc_ctx** out) {
   if (!opt || !out) return THC_EINVAL;
   *out = nullptr;
-  if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
-      opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) || (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV)) != 0 || opt->a_block < 0 || opt->i_chunk < 0 || opt->x_block < 0 ||
-      opt->x_chunk < 0 || opt->x7_chunk < 0)
-    return THC_EINVAL;
-  // the metric S = B^T B (nP x nP) and the ERI-grid Gram (nQ x nQ) have rank at most o v
-  if (opt->nP > opt->o * opt->v || opt->nQ > opt->o * opt->v) return THC_EINVAL;
+  if (!options_valid(opt)) return THC_EINVAL;
   thc_ctx* ctx = new (std::nothrow) thc_ctx();
   if (!ctx) return THC_ENOMEM;
   ctx->opt = *opt;
@@ -1096,21 +1266,11 @@ int generate_inputs(thc_ctx* ctx) {
   MISC(synth_chol_block(sp.seed, n, 0, nL, 0, o, o, v, sp.decay, 1.0, ctx->Lov, s));
   double gamma = sp.gamma;
   if (!(gamma > 0.0)) {
-    double *G = nullptr, *x = nullptr, *y = nullptr;
-    std::vector<void*> tmp;
-    auto talloc = [&](double** p, size_t cnt) {
-      void* q = nullptr;
-      if (hipMalloc(&q, cnt * sizeof(double)) != hipSuccess) return false;
-      tmp.push_back(q);
-      *p = (double*)q;
-      return true;
-    };
-    auto tfree = [&]() { for (void* q : tmp) (void)hipFree(q); };
-    if (!talloc(&G, (size_t)(nL * nL)) || !talloc(&x, (size_t)nL) || !talloc(&y, (size_t)nL)) {
-      tfree();
-      ctx->err = "allocation for the gamma rule failed";
-      return THC_ENOMEM;
-    }
+    // the rule's Gram matrix and vectors at the start of the set-up scratch
+    double* G = ctx->setup_scratch;
+    double* x = G + aligned((size_t)(nL * nL));
+    double* y = x + aligned((size_t)nL);
+    auto tfree = [&]() {};
     int rc = gemm(ctx, mk(nL, nL, ov, ctx->Lov, ov, false, ctx->Lov, ov, true, G, nL));
     if (rc == THC_OK) {
       std::vector<double> ones((size_t)nL, 1.0 / std::sqrt((double)nL));
@@ -1209,18 +1369,16 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
   MISC(k_hadamard(PP, ctx->Go, ctx->Gv, 1.0, 0.0, ctx->S, s));
   MISC(k_kr(o, v, P, ctx->Yo, ctx->Yv, ctx->Bkr, s));
 
-  // scratch for the set-up: reuse big work buffers (sized >= what is needed below)
-  std::vector<void*> scratch;
+  // scratch for the set-up: pieces of the set-up region of the arena (sized by setup_doubles for
+  // exactly the pieces taken below)
+  size_t sused = ctx->synth ? aligned((size_t)(nL * nL)) + 2 * aligned((size_t)nL) : 0;  // the gamma rule's
   auto salloc = [&](size_t cnt) -> double* {
-    void* q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(cnt, 1) * sizeof(double)) != hipSuccess) return nullptr;
-    scratch.push_back(q);
-    return (double*)q;
+    if (sused + aligned(cnt) > ctx->setup_len) return nullptr;
+    double* q = ctx->setup_scratch + sused;
+    sused += aligned(cnt);
+    return q;
   };
-  auto sfree = [&]() {
-    for (void* q : scratch) (void)hipFree(q);
-    scratch.clear();
-  };
+  auto sfree = [&]() {};
   int rc = THC_OK;
   do {
     // ---- ERI fit (Eq. 19-20): G_Q xi^T = M, M^IA = sum_ia x_i^I x_a^I L_ia^A, z = xi^T xi ----
@@ -1316,6 +1474,8 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
   } while (0);
   sfree();
   if (rc != THC_OK) return rc;
+  RCHK(clear_region6(ctx));
+  HIPCHK(hipStreamSynchronize(s));
   ctx->built = true;
   ctx->diis_n = 0;
   ctx->diis_head = 0;
@@ -1536,23 +1696,7 @@ int thc_memory_bytes(const thc_ctx* ctx, size_t* bytes) {
 int thc_plan(const thc_ctx* ctx, thc_plan_info* out) {
   if (!ctx || !out) return THC_EINVAL;
   if (!ctx->built) return THC_ESTATE;
-  thc_plan_info p{};
-  p.a_block = ctx->nb;
-  p.alg1_splits = ctx->KS;
-  p.alg1_tile = ctx->alg1_tile;
-  p.x_block = ctx->Xb;
-  p.x_blocks = (ctx->P + ctx->Xb - 1) / ctx->Xb;
-  p.i_chunk = ctx->Ic;
-  p.i_chunks = (ctx->Q + ctx->Ic - 1) / ctx->Ic;
-  p.h_generations = ctx->nhtiles / (8 * ctx->hslots);
-  p.h_tiles = ctx->hfilled;
-  p.x_chunk = ctx->Xc;
-  p.x7_chunk = ctx->X7;
-  p.x7_chunks = (ctx->P + ctx->X7 - 1) / ctx->X7;
-  p.exchange_fused = exch_supported(ctx->o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE);
-  p.lvv_resident = ctx->lvv_resident ? 1 : 0;
-  p.device_bytes = ctx->bytes;
-  *out = p;
+  fill_plan_info(ctx, ctx->hfilled, ctx->nhtiles, ctx->hslots, (double)ctx->bytes, out);
   return THC_OK;
 }
 

@@ -30,7 +30,7 @@ SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_term
            "thc_history_precision",
            "thc_energy",
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan",
-           "thc_set_synthetic", "thc_synth_gamma", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
+           "thc_set_synthetic", "thc_synth_gamma", "thc_create_with_workspace", "thc_plan_query", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
            "thc_last_error", "thc_destroy",
            "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
            "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
@@ -92,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
     lib.thc_plan.argtypes = [VP, C.POINTER(PlanInfo)]
     lib.thc_set_synthetic.argtypes = [VP, C.POINTER(SynthSpec)]
+    lib.thc_create_with_workspace.argtypes = [C.POINTER(Options), VP, C.c_size_t, VP, C.POINTER(VP)]
+    lib.thc_plan_query.argtypes = [C.POINTER(Options), C.c_int, C.c_uint64, C.POINTER(PlanInfo)]
     lib.thc_synth_gamma.argtypes = [VP, C.POINTER(D)]
     lib.thc_synth_normals.argtypes = [C.c_uint64, C.c_int32, C.c_uint64, I64, D, P, VP]
     lib.thc_synth_cholesky.argtypes = [C.c_uint64, I64, I64, I64, D, D, P, VP]
@@ -178,6 +180,24 @@ def dgemm(A, B, C_out, transA=False, transB=False, alpha=1.0, beta=0.0):
     return C_out
 
 
+def make_options(o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0, x_block=0,
+                 x_chunk=0, flags=0, precision=0, x7_chunk=0):
+    return Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
+                   precision, flags, x7_chunk)
+
+
+def plan_query(o, v, nL, nP, nQ, budget_bytes, synthetic=False, **kw):
+    """The blocking and working memory the library would plan within budget_bytes (a dict of
+    PlanInfo's fields); needs no GPU."""
+    lib = load()
+    opt = make_options(o, v, nL, nP, nQ, **kw)
+    p = PlanInfo()
+    rc = lib.thc_plan_query(C.byref(opt), int(bool(synthetic)), C.c_uint64(int(budget_bytes)), C.byref(p))
+    if rc != 0:
+        raise ThcError(rc, "thc_plan_query: no plan fits")
+    return {name: getattr(p, name) for name, _ in PlanInfo._fields_}
+
+
 def synth_normals(seed, stream_id, first, count, divisor=1.0):
     """Normals first .. first + count - 1 of generator stream stream_id, divided by divisor, made
     on the GPU (the same values as synth.normal)."""
@@ -213,14 +233,23 @@ class THC:
     """One THC-CCSD problem on the current GPU (all tensors float64, CUDA, contiguous)."""
 
     def __init__(self, o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0,
-                 x_block=0, x_chunk=0, flags=0, precision=0, x7_chunk=0):
+                 x_block=0, x_chunk=0, flags=0, precision=0, x7_chunk=0, workspace=None):
+        """workspace: None (the library allocates its working memory), or a CUDA tensor whose
+        memory the library uses instead (thc_create_with_workspace; kept referenced here)."""
         self.lib = load()
         self.o, self.v, self.nL, self.nP, self.nQ = o, v, nL, nP, nQ
         self.singles = bool(singles)
-        opt = Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
-                      precision, flags, x7_chunk)
+        opt = make_options(o, v, nL, nP, nQ, singles, diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
+                           flags, precision, x7_chunk)
         h = C.c_void_p()
-        rc = self.lib.thc_create(C.byref(opt), _stream(), C.byref(h))
+        self.workspace = workspace
+        if workspace is None:
+            rc = self.lib.thc_create(C.byref(opt), _stream(), C.byref(h))
+        else:
+            if not isinstance(workspace, torch.Tensor) or workspace.device.type != "cuda" or not workspace.is_contiguous():
+                raise TypeError("workspace must be a contiguous CUDA tensor")
+            rc = self.lib.thc_create_with_workspace(C.byref(opt), C.c_void_p(workspace.data_ptr()),
+                                                    workspace.numel() * workspace.element_size(), _stream(), C.byref(h))
         if rc != 0:
             raise ThcError(rc, "thc_create failed")
         self.ctx = h

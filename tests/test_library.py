@@ -59,10 +59,32 @@ def test_create_rejects_invalid_options(lib, field, value):
     larger than the o v pairs (singular metric / Gram matrix), out-of-range options."""
     from paper_2111_11473_amd import thc
     base = dict(o=10, v=40, nL=150, nP=120, nQ=300, singles=1, diis_max=8, tol_energy=1e-8, a_block=0,
-                i_chunk=0, x_block=0, x_chunk=0, precision=0, flags=0)
+                i_chunk=0, x_block=0, x_chunk=0, precision=0, flags=0, x7_chunk=0)
     base[field] = value
     opt = thc.Options(**base)
     lib.thc_create.argtypes = [ctypes.POINTER(thc.Options), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
     h = ctypes.c_void_p()
     assert lib.thc_create(ctypes.byref(opt), None, ctypes.byref(h)) == -1  # THC_EINVAL
     assert not h.value
+
+
+def test_memory_plans_of_the_workloads():
+    """The working-memory planner (host only): the fp64 workload (o=50 v=450 nL=1500 nP=1000
+    nQ=2500) runs as one H block and one Alg. 7 chunk in ~41 GB; the mixed-precision workload
+    (o=200 v=1800 nL=6000 nP=4000 nQ=10000, synthetic inputs) fits 270 GB with the vv Cholesky block
+    regenerated per fused-pass block, H blocks of 512 ranks with 256-point grid chunks and Alg. 7 in
+    row chunks; the ~2500-basis-function workload (o=350 v=2150 nL=10000 nP=7000 nQ=17500) does not
+    fit with FP64 intermediates (its B_ia^I alone is 105 GB)."""
+    from paper_2111_11473_amd import synth, thc
+    c = synth.CONFIGS["fp64"]
+    p = thc.plan_query(c.o, c.v, c.nL, c.nP, c.nQ, 270e9)
+    assert (p["x_blocks"], p["i_chunk"], p["x7_chunks"], p["lvv_resident"]) == (1, 638, 1, 1)
+    assert 35e9 < p["device_bytes"] < 45e9
+    c = synth.CONFIGS["mixed"]
+    for prec in (0, 1):
+        p = thc.plan_query(c.o, c.v, c.nL, c.nP, c.nQ, 270e9, synthetic=True, precision=prec)
+        assert p["device_bytes"] <= 270e9 and p["lvv_resident"] == 0 and p["exchange_fused"] == 1
+        assert p["x_block"] == 512 and p["i_chunk"] == 256 and p["x7_chunks"] > 1
+    c = synth.CONFIGS["paper"]
+    with pytest.raises(thc.ThcError, match="THC_ENOMEM"):
+        thc.plan_query(c.o, c.v, c.nL, c.nP, c.nQ, 270e9, synthetic=True, precision=1)
