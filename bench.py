@@ -143,15 +143,23 @@ def gpu_rate_on(sample_name, n_eval=10):
     return n_eval / dt
 
 
+LEG_PRECISION = {"fp64": 0, "mixed": 1, "mixed_split_bf16": 2}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="fp64")
+    ap.add_argument("--legs", default=None,
+                    help="comma list of fp64, mixed, mixed_split_bf16 (default: all three on the fp64 workload, "
+                         "mixed alone on the larger ones); the first is the headline")
+    ap.add_argument("--energy-iters", type=int, default=0,
+                    help="instead of a converge run, the energies of this many iterations from the MP2 guess")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--converge-maxit", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (a known-traffic kernel for counter scaling)")
@@ -161,13 +169,18 @@ def main():
         sys.exit("bench.py: the THC-CCSD hot path runs on one GPU; multi-GPU runs are not "
                  "implemented (use --gpus 1)")
 
-    import numpy as np
     import torch
     from paper_2111_11473_amd import synth, thc
 
     cfg = synth.CONFIGS[args.config]
+    large = cfg.name != "fp64"
+    legs = args.legs.split(",") if args.legs else (["mixed"] if large else ["fp64", "mixed", "mixed_split_bf16"])
+    if args.no_mixed:
+        legs = [g for g in legs if g == "fp64"]
+    if not legs or any(g not in LEG_PRECISION for g in legs):
+        sys.exit(f"bench.py: --legs must name some of {list(LEG_PRECISION)}")
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not large:
         cpu = cpu_baseline(cfg)
         print(f"bench: cpu baseline done ({cpu['value']:.3f} residual evals/s on '{cpu['sample_config']}')",
               file=sys.stderr, flush=True)
@@ -183,31 +196,48 @@ def main():
     if cpu is not None:
         g = gpu_rate_on("wide")
         cpu["gpu_same_sample"] = {"value": g, "unit": "residual_evals/s", "gpu_over_cpu": g / cpu["value"]}
-    s = synth.make_system(cfg)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
     P, Q, o = cfg.nP, cfg.nQ, cfg.o
+    flags = thc.FLAG_PROGRESS if large else 0
 
     def leg(precision):
-        """Timed solver steps (one residual + update each) and the converge run of one precision."""
+        """Timed solver steps (one residual + update each) and the converge (or energy) run of one
+        precision, on inputs generated on the device by the library (bit-identical to the Python
+        generator's)."""
         ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, singles=True, diis_max=8, tol_energy=1e-8,
-                      precision=precision)
-        Z0 = ctx.build_factors(dev(s["L"]), dev(s["eps"]), *(dev(s[k]) for k in ("Xo", "Xv", "xo", "xv")))
+                      precision=precision, flags=flags)
+        ctx.set_synthetic(cfg.seed, cfg.decay, cfg.coupling)
+        tb = time.perf_counter()
+        Z0 = ctx.build_synthetic()
         torch.cuda.synchronize()
+        build_s = time.perf_counter() - tb
+        print(f"bench: leg precision {precision} built in {build_s:.1f} s", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             ctx.iterate(tol=0.0, maxit=1, raise_on_notconv=False)
         torch.cuda.synchronize()
         ctx.profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        step_e = []  # energy of the amplitudes each timed step evaluated (host scalars, no extra work)
         for _ in range(args.steps):
             ctx.iterate(tol=0.0, maxit=1, raise_on_notconv=False)
+            if large:
+                step_e.append(ctx.history()[0][-1])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        print(f"bench: leg precision {precision}: {args.steps} timed steps in {dt:.1f} s", file=sys.stderr, flush=True)
         prof = {name: ctx.profile_get(name) for name in ("h_kernel", "residual", "gemm", "misc", "exch")}
         flops64, flops32, flops16 = ctx.profile_flops()
         ctx.profile(False)
         conv = None
-        if not args.no_converge:
+        if args.energy_iters > 0:
+            ctx.set_state(Z0)
+            tc = time.perf_counter()
+            it, rn, ok = ctx.iterate(tol=0.0, maxit=args.energy_iters, raise_on_notconv=False)
+            E, R, T = ctx.history()
+            conv = {"iterations": it, "energies": E, "rnorms": R, "seconds": T,
+                    "wall_s": time.perf_counter() - tc, "mixed_iterations": sum(ctx.history_precision()),
+                    "guess": "MP2 least-squares fit", "solver": "Jacobi (pseudo-canonical) + DIIS(8)"}
+        elif not args.no_converge:
             ctx.set_state(Z0)
             tc = time.perf_counter()
             it, rn, ok = ctx.iterate(tol=1e-7, maxit=args.converge_maxit, raise_on_notconv=False)
@@ -218,14 +248,19 @@ def main():
                     "solve_seconds": wall, "energies": E, "seconds": T,
                     "mixed_iterations": sum(ctx.history_precision()),
                     "guess": "MP2 least-squares fit", "solver": "Jacobi (pseudo-canonical) + DIIS(8)"}
+        plan = ctx.plan()
+        plan["build_seconds"] = build_s
+        if step_e:
+            plan["step_energies"] = step_e
+        plan["gamma"] = ctx.synth_gamma()
         ctx.close()
         torch.cuda.synchronize()
-        return dt, prof, flops64 / args.steps, (flops32 + flops16) / args.steps, conv
+        return dt, prof, flops64 / args.steps, (flops32 + flops16) / args.steps, conv, plan
 
     def to_target(conv, e_ref):
         """Iterations and seconds until the energy stays within 1e-6 Eh of e_ref."""
-        if conv is None:
-            return None
+        if conv is None or "final_energy" not in conv:
+            return conv
         E, T = conv.pop("energies"), conv.pop("seconds")
         k = len(E) - 1
         while k > 0 and abs(E[k - 1] - e_ref) < 1e-6:
@@ -236,68 +271,74 @@ def main():
         conv["seconds_to_1e-6"] = T[k]
         return conv
 
-    dt, prof, gf64, _, conv64 = leg(0)
-    h_ms, h_n = prof["h_kernel"]
-    r_ms, r_n = prof["residual"]
-    g_ms, _ = prof["gemm"]
-    m_ms, _ = prof["misc"]
-    x_ms, _ = prof["exch"]
-
     # algorithmic count of the three-way accumulation H^XYZ += (E^XY F^XZ + E^XZ F^XY) G^YZ as the
     # paper writes it: 5 flops per (X, Y, Z, I) -- two products, a sum, a product and the
     # accumulation.  The kernel issues 3.5 per (X, Y, Z, I): for Y != Z one bracket (3 flops)
     # serves both H^XYZ and H^XZY (one FMA each).
     h_flops_per_residual = 5.0 * Q * P ** 3
     h_flops_issued = 3.5 * Q * P ** 3
+    exch_flops = 2 * 4.0 * P * o * Q * Q  # two exchange passes, two products of 2 o Q^2 each per X
+
+    results = {}
+    for name in legs:
+        results[name] = leg(LEG_PRECISION[name])
+    head = legs[0]
+    dt, prof, gf64, gfm, conv_head, plan_head = results[head]
+    h_ms, h_n = prof["h_kernel"]
+    r_ms, r_n = prof["residual"]
+    g_ms, _ = prof["gemm"]
+    m_ms, _ = prof["misc"]
+    x_ms, _ = prof["exch"]
     launches_per_residual = max(1, h_n // max(1, r_n))
     flops_per_launch = h_flops_per_residual / launches_per_residual
     avg_launch_s = (h_ms / 1e3) / max(1, h_n)
     achieved = flops_per_launch / avg_launch_s / 1e12
     achieved_issued = h_flops_issued / launches_per_residual / avg_launch_s / 1e12
-    exch_flops = 2 * 4.0 * P * o * Q * Q  # two exchange passes, two products of 2 o Q^2 each per X
     g_per = g_ms / args.steps / 1e3
     x_per = x_ms / args.steps / 1e3
     t_res = r_ms / max(1, r_n) / 1e3
-    t_ideal = (h_flops_per_residual + gf64 + exch_flops) / (PEAK_FP64_VALU_TFLOPS * 1e12)
+    e_ref = None
+    if "fp64" in results and results["fp64"][4] is not None and "final_energy" in results["fp64"][4]:
+        e_ref = results["fp64"][4]["final_energy"]
 
-    def mixed_leg(precision):
-        """One mixed-precision leg: its timed steps, MFMA rate, roofline fraction and converge run."""
-        dtm, profm, gf64m, gfm, convm = leg(precision)
+    def ideal_seconds(precision, gf64_, gfm_):
+        """Every part at its peak: the H-kernel at the vector peak of its arithmetic type, the
+        exchange and contractions at the matrix peak of theirs (a split-BF16 product is three BF16
+        products), the products kept in FP64 at the FP64 peak."""
+        if precision == 0:
+            return (h_flops_per_residual + gf64_ + exch_flops) / (PEAK_FP64_VALU_TFLOPS * 1e12)
+        peak = PEAK_FP32_MFMA_TFLOPS if precision == 1 else PEAK_BF16_MFMA_TFLOPS / 3.0
+        return (h_flops_per_residual / (PEAK_FP32_VALU_TFLOPS * 1e12) + exch_flops / (PEAK_FP32_MFMA_TFLOPS * 1e12)
+                + gfm_ / (peak * 1e12) + gf64_ / (PEAK_FP64_VALU_TFLOPS * 1e12))
+
+    def mixed_summary(name):
+        precision = LEG_PRECISION[name]
+        dtm, profm, gf64m, gfm_, convm, planm = results[name]
         rm_ms, rm_n = profm["residual"]
         gm_s = profm["gemm"][0] / args.steps / 1e3
         t_res_m = rm_ms / max(1, rm_n) / 1e3
-        # ideal: the H-kernel at the FP32 vector peak, the exchange at the FP32 matrix peak, the
-        # contractions at the FP32 (BF16) matrix peak -- a split-BF16 product is three BF16
-        # products -- and the products kept in FP64 at the FP64 peak
-        peak = PEAK_FP32_MFMA_TFLOPS if precision == 1 else PEAK_BF16_MFMA_TFLOPS / 3.0
-        t_ideal_m = (h_flops_per_residual / (PEAK_FP32_VALU_TFLOPS * 1e12) + exch_flops / (PEAK_FP32_MFMA_TFLOPS * 1e12)
-                     + gfm / (peak * 1e12) + gf64m / (PEAK_FP64_VALU_TFLOPS * 1e12))
-        e_ref = conv64["final_energy"] if conv64 else None
-        if convm is not None and e_ref is not None:
+        if convm is not None and e_ref is not None and "final_energy" in convm:
             convm["energy_minus_fp64"] = convm["final_energy"] - e_ref
             convm = to_target(convm, e_ref)
-        rate = gfm / max(gm_s, 1e-12) / 1e12
+        rate = gfm_ / max(gm_s, 1e-12) / 1e12
         return {"residual_evals_per_s": args.steps / dtm, "ms_per_step": 1e3 * dtm / args.steps,
                 "residual_ms": 1e3 * t_res_m, "h_kernel_ms": profm["h_kernel"][0] / args.steps,
-                "gemm_ms": profm["gemm"][0] / args.steps,
+                "gemm_ms": profm["gemm"][0] / args.steps, "exchange_ms": profm["exch"][0] / args.steps,
                 ("gemm_fp32_mfma" if precision == 1 else "gemm_split_bf16_mfma"):
                     {"achieved": rate if precision == 1 else 3.0 * rate,
                      "peak": PEAK_FP32_MFMA_TFLOPS if precision == 1 else PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "note": "product flops" if precision == 1 else "three BF16 products per split product"},
-                "residual_roofline_frac": t_ideal_m / t_res_m,
+                "residual_roofline_frac": ideal_seconds(precision, gf64m, gfm_) / t_res_m,
                 "precision": ("FP32 MFMA contractions" if precision == 1 else
                               "compensated split-BF16 contractions (hi hi + hi lo + lo hi, FP32 accumulation)") +
                              " and FP32 H operands (FP64 accumulation), FP64 energy, denominators, fit, DIIS; "
                              "FP64 finishing iterations",
-                "converge": convm}
+                "plan": planm, "converge": convm}
 
-    mixed = mixed_bf16 = None
-    if not args.no_mixed:
-        mixed = mixed_leg(1)
-        mixed_bf16 = mixed_leg(2)
-    if conv64 is not None:
+    head_prec = LEG_PRECISION[head]
+    conv64 = results["fp64"][4] if "fp64" in results else None
+    if conv64 is not None and "final_energy" in conv64:
         conv64 = to_target(conv64, conv64["final_energy"])
-
     out = {
         "metric": "residual_evals_per_s",
         "value": args.steps / dt,
@@ -309,31 +350,42 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head_prec == 0 else ("f32+f64" if head_prec == 1 else "bf16x3+f32+f64"),
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: THC-CCSD residual + energy + Jacobi/DIIS step, o={cfg.o} v={cfg.v} "
-                               f"nL={cfg.nL} nP={cfg.nP} nQ={cfg.nQ}, seeded synthetic inputs",
-                   "o": cfg.o, "v": cfg.v, "nL": cfg.nL, "nP": cfg.nP, "nQ": cfg.nQ, "precision": "fp64",
+                               f"nL={cfg.nL} nP={cfg.nP} nQ={cfg.nQ}, seeded synthetic inputs generated on the device",
+                   "o": cfg.o, "v": cfg.v, "nL": cfg.nL, "nP": cfg.nP, "nQ": cfg.nQ, "precision": head,
                    "parallelism": "single GPU"},
-        "roofline": {"kernel": "h_kernel (three-way accumulation of Alg. 6, FP64 VALU, Y<->Z symmetric)", "bound": "alu",
+        "roofline": {"kernel": "h_kernel (three-way accumulation of Alg. 6, FP64 VALU arithmetic, Y<->Z symmetric"
+                               + ("" if head_prec == 0 else "; FP32 E, F operands") + ")", "bound": "alu",
                      "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": _traffic(cfg.name, launches_per_residual), "launches": h_n,
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+                     "traffic": _traffic(cfg.name, launches_per_residual) if head_prec == 0 else None,
+                     "launches": h_n,
                      "avg_launch_ms": 1e3 * avg_launch_s, "algorithmic_flops_per_launch": flops_per_launch,
                      "flop_count": "5 N_Q N_P^3 per residual (the accumulation as written)",
                      "issued": {"achieved": achieved_issued, "frac": achieved_issued / PEAK_FP64_VALU_TFLOPS,
                                 "flop_count": "3.5 N_Q N_P^3 (one bracket for both H^XYZ and H^XZY)"}},
-        "mfma": {"gemm_fp64": {"achieved": gf64 / max(g_per, 1e-12) / 1e12, "peak": PEAK_FP64_VALU_TFLOPS,
-                               "unit": "TFLOP/s", "flops_per_residual": gf64},
-                 "exchange_fp64": {"achieved": exch_flops / max(x_per, 1e-12) / 1e12, "peak": PEAK_FP64_VALU_TFLOPS,
-                                   "unit": "TFLOP/s", "flops_per_residual": exch_flops}},
-        "residual_roofline_frac": t_ideal / t_res,
+        "mfma": {("gemm_fp64" if head_prec == 0 else "gemm_reduced"):
+                     {"achieved": (gf64 if head_prec == 0 else gfm) / max(g_per, 1e-12) / 1e12,
+                      "peak": PEAK_FP64_VALU_TFLOPS if head_prec == 0 else PEAK_FP32_MFMA_TFLOPS,
+                      "unit": "TFLOP/s", "flops_per_residual": gf64 if head_prec == 0 else gfm},
+                 "exchange": {"achieved": exch_flops / max(x_per, 1e-12) / 1e12,
+                              "peak": PEAK_FP64_VALU_TFLOPS if head_prec == 0 else PEAK_FP32_MFMA_TFLOPS,
+                              "unit": "TFLOP/s", "flops_per_residual": exch_flops}},
+        "residual_roofline_frac": ideal_seconds(head_prec, gf64, gfm) / t_res,
         "breakdown_ms_per_step": {"residual": 1e3 * t_res, "h_kernel": h_ms / args.steps, "gemm": g_ms / args.steps,
                                   "exchange": x_ms / args.steps, "misc": m_ms / args.steps},
-        "converge": conv64,
-        "mixed": mixed,
-        "mixed_split_bf16": mixed_bf16,
+        "plan": plan_head,
+        "converge": conv64 if head == "fp64" else results[head][4],
         "cpu_baseline": cpu,
     }
+    for name in legs:
+        if name != "fp64":
+            out[name] = mixed_summary(name)
+    if "fp64" in legs and head != "fp64":
+        out["fp64"] = {"residual_evals_per_s": args.steps / results["fp64"][0], "converge": conv64,
+                       "plan": results["fp64"][5]}
     print(json.dumps(out), flush=True)
 
 

@@ -81,6 +81,9 @@ typedef struct thc_options {
  * device memory but regenerated for each block of the fused pass over Cholesky vectors (the
  * default when it does not fit the memory plan). */
 #define THC_FLAG_STREAM_LVV (1 << 1)
+/* Print a line to stderr after each block of the residual's outer loops (fused pass over
+ * Cholesky vectors, Alg. 6 H blocks, Alg. 7 row chunks), waiting for the stream each time. */
+#define THC_FLAG_PROGRESS (1 << 2)
 
 /* Creates a context bound to the current HIP device and to `stream` (hipStream_t; NULL = the
  * default stream).  Allocates nothing on the device yet.  *out receives the context.

@@ -30,6 +30,8 @@ def _flags(src: str) -> list[str]:
     # every source is compiled for gfx950 only (the .cpp files hold host code and no kernels);
     # packed FP32 instructions are disabled for every device compilation
     f += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    if src == "hostla.cpp":  # host-only set-up linear algebra: AVX2/FMA vectors of the EPYC hosts
+        f += ["-Xarch_host", "-mavx2", "-Xarch_host", "-mfma"]
     return f
 
 

@@ -464,6 +464,12 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const Gemm g, const 
   }
 }
 
+bool slab_offsets_fit(const Gemm& g, int BM, int BN) {
+  const int64_t la = 8 * (g.transA ? (int64_t)BK * g.lda + BM : (int64_t)BM * g.lda + BK);
+  const int64_t lb = 8 * (g.transB ? (int64_t)BN * g.ldb + BK : (int64_t)BK * g.ldb + BN);
+  return la < (int64_t(1) << 31) && lb < (int64_t(1) << 31);
+}
+
 template <int BM, int BN, bool F32, bool SHORT = false>
 hipError_t launch_tile(const Gemm& g, int64_t kchunk, hipStream_t s) {
   constexpr int OCC = 2;  // two workgroups per CU: one multiplies while the other loads
@@ -472,9 +478,9 @@ hipError_t launch_tile(const Gemm& g, int64_t kchunk, hipStream_t s) {
   dim3 grid((unsigned)(g.upper ? ntn * (ntn + 1) / 2 : ntn), (unsigned)(g.upper ? 1 : (g.M + BM - 1) / BM),
             (unsigned)(g.batch * g.ksplit));
   if ((uint64_t)grid.x * grid.y * grid.z >= (uint64_t(1) << 32)) return hipErrorInvalidValue;  // 32-bit tile ids
-  // byte offsets within a slab stay below 2^31 (the buffer range)
-  const int64_t la = 8 * (BM + BK) * g.lda, lb = 8 * (BN + BK) * g.ldb;
-  if (la >= (int64_t(1) << 31) || lb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  // byte offsets within a slab stay below 2^31 (the buffer range): a slab spans BK rows of a
+  // k-major operand, or BM (BN) rows of an m- (n-) major one
+  if (!slab_offsets_fit(g, BM, BN)) return hipErrorInvalidValue;
   if (!g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, false, F32, OCC, SHORT>), grid, dim3(256), 0, s, g, kchunk);
   else if (g.transA && !g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, false, F32, OCC, SHORT>), grid, dim3(256), 0, s, g, kchunk);
   else if (!g.transA && g.transB) hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, true, F32, OCC, SHORT>), grid, dim3(256), 0, s, g, kchunk);
@@ -488,8 +494,7 @@ hipError_t launch_btile(const Gemm& g, int64_t kchunk, hipStream_t s) {
   dim3 grid((unsigned)(g.upper ? ntn * (ntn + 1) / 2 : ntn), (unsigned)(g.upper ? 1 : (g.M + BM - 1) / BM),
             (unsigned)(g.batch * g.ksplit));
   if ((uint64_t)grid.x * grid.y * grid.z >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
-  const int64_t la = 8 * (BM + BK) * g.lda, lb = 8 * (BN + BK) * g.ldb;
-  if (la >= (int64_t(1) << 31) || lb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  if (!slab_offsets_fit(g, BM, BN)) return hipErrorInvalidValue;
   if (!g.transA && !g.transB) hipLaunchKernelGGL((bgemm_kernel<BM, BN, false, false>), grid, dim3(256), 0, s, g, kchunk);
   else if (g.transA && !g.transB) hipLaunchKernelGGL((bgemm_kernel<BM, BN, true, false>), grid, dim3(256), 0, s, g, kchunk);
   else if (!g.transA && g.transB) hipLaunchKernelGGL((bgemm_kernel<BM, BN, false, true>), grid, dim3(256), 0, s, g, kchunk);

@@ -48,12 +48,13 @@ void host_tri_inverse_lower(int64_t n, const double* L, double* X) {
 namespace {
 
 // Apply a function to rows [0, n) in parallel chunks.
+// (Serial below min_n items, where starting threads costs more than it saves.)
 template <class Fn>
-void parallel_rows(int64_t n, Fn fn) {
+void parallel_rows(int64_t n, Fn fn, int64_t min_n = 256) {
   unsigned nt = std::thread::hardware_concurrency();
   if (nt == 0) nt = 1;
   if (nt > 16) nt = 16;
-  if (n < 256 || nt == 1) {
+  if (n < min_n || nt == 1) {
     fn(0, n);
     return;
   }
@@ -125,25 +126,40 @@ int host_syev(int64_t n, double* A, double* w) {
   d[n - 1] = A[(n - 1) * n + n - 1];
   e[n - 1] = 0.0;
   // --- accumulate Q = H_0 ... H_{n-3}; stored transposed (row j of Zt = column j of Q) ---
+  // Zt = Q^T = H_{n-3} ... H_0 applied from the right to the identity: Zt <- Zt H_k for
+  // k = n-3 .. 0.  Rows of Zt are independent, so each thread takes blocks of 16 rows and applies
+  // every reflector to them while they stay in its cache (the reflectors stream past once per
+  // block instead of the whole matrix once per reflector).
   std::vector<double> Zt((size_t)n * n, 0.0);
   for (int64_t i = 0; i < n; ++i) Zt[(size_t)i * n + i] = 1.0;
-  // Q = H_0 (H_1 (... H_{n-3})); apply from the innermost: Q <- H_k Q acts on rows k+1.. of Q,
-  // i.e. on columns k+1.. of Zt = Q^T:  Zt <- Zt H_k.
-  for (int64_t k = n - 3; k >= 0; --k) {
-    const double* vk = &V[(size_t)k * n];
-    parallel_rows(n, [&](int64_t a, int64_t b) {
-      for (int64_t r = a; r < b; ++r) {
-        double* z = &Zt[(size_t)r * n];
-        double s = 0.0;
-        for (int64_t j = k + 1; j < n; ++j) s += z[j] * vk[j];
-        s *= 2.0;
-        if (s != 0.0)
-          for (int64_t j = k + 1; j < n; ++j) z[j] -= s * vk[j];
+  constexpr int64_t RB = 16;
+  parallel_rows((n + RB - 1) / RB, [&](int64_t a, int64_t b) {
+    for (int64_t blk = a; blk < b; ++blk) {
+      const int64_t r0 = blk * RB, r1 = std::min(n, r0 + RB);
+      for (int64_t k = n - 3; k >= 0; --k) {
+        const double* vk = &V[(size_t)k * n];
+        for (int64_t r = r0; r < r1; ++r) {
+          double* z = &Zt[(size_t)r * n];
+          double s = 0.0;
+          for (int64_t j = k + 1; j < n; ++j) s += z[j] * vk[j];
+          s *= 2.0;
+          if (s != 0.0)
+            for (int64_t j = k + 1; j < n; ++j) z[j] -= s * vk[j];
+        }
       }
-    });
-  }
+    }
+  }, 2);
   // --- implicit QL on the tridiagonal (d, e): e[i] couples i and i+1 ---
-  // Rotations combine columns i, i+1 of Q, i.e. rows i, i+1 of Zt (contiguous).
+  // The iteration itself needs only (d, e); its plane rotations (combining columns i, i+1 of Q,
+  // i.e. rows i, i+1 of Zt) are recorded in order and applied afterwards, each thread taking
+  // slices of 64 columns of Zt through the whole sequence (columns are independent, and a slice
+  // of every row stays in cache while the sweeps run over it).
+  struct Rot {
+    int64_t i;
+    double c, s;
+  };
+  std::vector<Rot> rots;
+  rots.reserve((size_t)n * 8);
   for (int64_t l = 0; l < n; ++l) {
     int iter = 0;
     for (;;) {
@@ -177,13 +193,7 @@ int host_syev(int64_t n, double* A, double* w) {
         pp = s * r;
         d[i + 1] = g + pp;
         g = c * r - b;
-        double* z0 = &Zt[(size_t)i * n];
-        double* z1 = &Zt[(size_t)(i + 1) * n];
-        for (int64_t k = 0; k < n; ++k) {
-          const double a0 = z0[k], a1 = z1[k];
-          z1[k] = s * a0 + c * a1;
-          z0[k] = c * a0 - s * a1;
-        }
+        rots.push_back({i, c, s});
       }
       if (underflow) continue;
       d[l] -= pp;
@@ -191,6 +201,21 @@ int host_syev(int64_t n, double* A, double* w) {
       e[m] = 0.0;
     }
   }
+  constexpr int64_t CW = 64;
+  parallel_rows((n + CW - 1) / CW, [&](int64_t a, int64_t b) {
+    for (int64_t sl = a; sl < b; ++sl) {
+      const int64_t k0 = sl * CW, kw = std::min(n, k0 + CW) - k0;
+      for (const Rot& q : rots) {
+        double* z0 = &Zt[(size_t)q.i * n + k0];
+        double* z1 = z0 + n;
+        for (int64_t k = 0; k < kw; ++k) {
+          const double a0 = z0[k], a1 = z1[k];
+          z1[k] = q.s * a0 + q.c * a1;
+          z0[k] = q.c * a0 - q.s * a1;
+        }
+      }
+    }
+  }, 2);
   // sort ascending, write eigenvectors into the columns of A
   std::vector<int64_t> idx(n);
   for (int64_t i = 0; i < n; ++i) idx[i] = i;

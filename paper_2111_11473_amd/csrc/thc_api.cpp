@@ -636,6 +636,16 @@ int clear_region6(thc_ctx* ctx) {
   return THC_OK;
 }
 
+// With THC_FLAG_PROGRESS: waits for the stream and prints one line to stderr (long residuals at
+// the largest workloads report each finished block of the paper's loops).
+int progress(thc_ctx* ctx, const char* what, int64_t done, int64_t total) {
+  if (!(ctx->opt.flags & THC_FLAG_PROGRESS)) return THC_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  fprintf(stderr, "thc: %s %lld/%lld\n", what, (long long)done, (long long)total);
+  fflush(stderr);
+  return THC_OK;
+}
+
 // Copies one scalar region of ctx->scal to the host.
 int read_scalars(thc_ctx* ctx, double* h, int count) {
   RCHK(d2h(ctx, h, ctx->scal, count * sizeof(double)));
@@ -673,6 +683,8 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     const int64_t nb = std::min(ctx->nb, nL - A0);
     const double* Loo = ctx->Loo + A0 * o * o;
     const double* Lov = ctx->Lov + A0 * ov;
+    if (A0 > 0 && (A0 / ctx->nb) % std::max<int64_t>(1, (nL / ctx->nb) / 8) == 0)
+      RCHK(progress(ctx, "fused Cholesky pass, vectors", A0, nL));
     const double* Lvv = ctx->lvv_resident ? ctx->Lvv + A0 * v * v : ctx->Lvv;
     if (!ctx->lvv_resident)  // the block's vv Cholesky panels from the generator
       MISC(synth_chol_block(ctx->spec.seed, n, A0, nb, o, v, o, v, ctx->spec.decay, ctx->gamma, ctx->Lvv, s));
@@ -761,6 +773,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       MISC(k_batch_sum(nb, ov, ctx->tmpov, 1.0, ctx->s38, s));
     }
   }
+  RCHK(progress(ctx, "fused Cholesky pass done, vectors", nL, nL));
   // energy partial sums: scal[0] = sum_A Atil^T T Atil, scal[1] = exchange, scal[2] = sum d_A^2,
   // scal[3] = sum tr(K_A^2)
   MISC(k_sum(nL, ctx->ej, ctx->scal + 0, s));
@@ -891,6 +904,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       RCHK(gemm(ctx, batched(mk(o, xb, P, Yo, P, false, ctx->Hb, Xb, false, ctx->R1, Xb), P, 0, Pp * Xb, o * Xb)));
       RCHK(gemm(ctx, batched(mk(v, xb, P, Yv, P, false, ctx->R1, o * Xb, false, ctx->I6, Xb), o, 0, Xb, v * Xb)));
       RCHK(gemm(ctx, mk(xb, P, ov, ctx->I6, Xb, true, ctx->Bkr, P, false, ctx->sig + X0 * P, P, 1.0, 1.0)));
+      RCHK(progress(ctx, "Alg. 6 H blocks", X0 / Xb + 1, (P + Xb - 1) / Xb));
     }
   }
 
@@ -946,6 +960,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
       RCHK(gemm(ctx, mk(xc * o, v, Q, ctx->Gts, Q, false, xv, Q, true, ctx->G7s, v)));
       RCHK(gemm(ctx, mk(xc, P, ov, ctx->G7, ov, false, ctx->R7, ov, true, ctx->sig + X0 * P, P, -C_D, 1.0)));
       RCHK(gemm(ctx, mk(xc, P, ov, ctx->G7s, ov, false, ctx->S7, ov, true, ctx->sig + X0 * P, P, C_D, 1.0)));
+      RCHK(progress(ctx, "Alg. 7 row chunks", X0 / X7 + 1, (P + X7 - 1) / X7));
     }
     // D = C z ; sigma += 2 c_D C D^T  (Alg. 7, Eq. 37)
     RCHK(gemm(ctx, mk(P, Q, Q, ctx->Cx, Q, false, ctx->z, Q, false, ctx->Dx, Q)));
@@ -1165,7 +1180,7 @@ namespace {
 bool options_valid(const thc_options* opt) {
   if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
       opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) ||
-      (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV)) != 0 || opt->a_block < 0 ||
+      (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV | THC_FLAG_PROGRESS)) != 0 || opt->a_block < 0 ||
       opt->i_chunk < 0 || opt->x_block < 0 || opt->x_chunk < 0 || opt->x7_chunk < 0)
     return false;
   // the metric S = B^T B (nP x nP) and the ERI-grid Gram (nQ x nQ) have rank at most o v
@@ -1414,6 +1429,7 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
       rc = gemm(ctx, g); if (rc) break;
     }
 
+    rc = progress(ctx, "set-up: ERI fit and B_ia^I done, steps", 1, 3); if (rc) break;
     // ---- working basis: E_mat w = e S w, E_mat = Go o (Xv^T eps_v Xv) - (Xo^T eps_o Xo) o Gv ----
     double* Sl = salloc(PP);
     double* Em = salloc(PP);
@@ -1449,6 +1465,7 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
     rc = h2d(ctx, ctx->e, hw.data(), P * sizeof(double)); if (rc) break;
     rc = trsm(ctx, Sl, P, Linv, ctx->W, P, true, tsolve); if (rc) break;   // W = L^-T V
 
+    rc = progress(ctx, "set-up: working basis done, steps", 2, 3); if (rc) break;
     // ---- MP2 guess: M = B^T t_MP2 B with t_MP2 = -(ia|jb)/Delta, T^0 = W^T M W ----
     {
       const int64_t rc0 = std::max<int64_t>(1, std::min<int64_t>(ov, (int64_t)(1.0e9 / (8.0 * ov))));
@@ -1462,6 +1479,8 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
         MISC(k_mp2_denom(r0, rr, ov, v, ctx->eps, o, tb, s));
         rc = gemm(ctx, mk(rr, P, ov, tb, ov, false, ctx->Bkr, P, false, tB, P)); if (rc) break;
         rc = gemm(ctx, mk(P, P, rr, ctx->Bkr + r0 * P, P, true, tB, P, false, tP, P, 1.0, 1.0)); if (rc) break;
+        const int64_t nchunk = (ov + rc0 - 1) / rc0, ci = r0 / rc0 + 1;
+        if (nchunk >= 8 && ci % (nchunk / 8) == 0) { rc = progress(ctx, "set-up: MP2 guess, pair rows", r0 + rr, ov); if (rc) break; }
       }
       if (rc) break;
       rc = gemm(ctx, mk(P, P, P, tP, P, false, ctx->W, P, false, Em, P)); if (rc) break;

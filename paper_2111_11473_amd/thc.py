@@ -59,6 +59,7 @@ class SynthSpec(C.Structure):
 
 
 FLAG_STREAM_LVV = 1 << 1
+FLAG_PROGRESS = 1 << 2
 
 
 class ThcError(RuntimeError):
