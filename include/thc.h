@@ -39,6 +39,7 @@ extern "C" {
 #define THC_ENUMERIC (-5)   /* NaN/Inf in a residual or energy */
 #define THC_ENOTCONV (-6)   /* iteration limit reached */
 #define THC_ESTATE (-7)     /* call out of order (e.g. residual before build_factors) */
+#define THC_EDIVERGED (-8)  /* thc_iterate diverged, restarted from the MP2 guess, and diverged again */
 
 /* Residual term groups (bit mask for thc_residual_terms), named by the paper's equations. */
 #define THC_TERM_EQ28 (1u << 0)   /* pp/hh/mixed ladders, Alg. 1 */
@@ -156,13 +157,27 @@ int thc_residual(thc_ctx* ctx, const double* Z, const double* t1, double* sigma,
 int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t mask, double* sigma,
                        double* sigma1);
 
-/* Jacobi + DIIS iterations from the current state: each iteration evaluates the residual and
- * the energy of the current amplitudes, stops when the residual norm (orthonormal basis) is
- * below tol and |dE| < tol_energy, else updates T^ -= sigma^/(e_P + e_Q),
- * t1 -= sigma1/(eps_a - eps_i) and extrapolates with DIIS.  *iters (host, may be NULL): number
- * of residual evaluations; *rnorm (host, may be NULL): last residual norm.
- * Returns THC_ENOTCONV when maxit is reached, THC_ENUMERIC on NaN/Inf. */
+/* Jacobi + DIIS iterations from the current state (the paper gives no update rule: this is the
+ * standard denominator-weighted update in the working basis where the Fock part of the projected
+ * residual is exactly diagonal, Sec. II's equations; Pulay DIIS): each iteration evaluates the
+ * residual and the energy of the current amplitudes, stops when the residual norm (orthonormal
+ * basis) is below tol and |dE| < tol_energy, else updates T^ -= sigma^/(e_P + e_Q),
+ * t1 -= sigma1/(eps_a - eps_i) and extrapolates with DIIS (the oldest vectors dropped while the
+ * error overlap matrix has a condition number above 1e12).  Divergence -- a residual norm or
+ * energy that is not finite, a norm above 10 times the smallest of the call, or three rises in a
+ * row -- restarts once from the MP2 guess with the plain denominators and an empty DIIS subspace
+ * (within the same maxit).  *iters (host, may be NULL): residual evaluations; *rnorm (host, may be
+ * NULL): last residual norm.  Returns THC_ENOTCONV when maxit is reached, THC_EDIVERGED when the
+ * restarted iteration diverges too. */
 int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm);
+
+/* Per iteration of the last thc_iterate call, THC_ITER_* bits: the residual was mixed precision;
+ * the iteration started from the MP2 guess after a divergence; DIIS dropped vectors to keep its
+ * subspace well conditioned.  flags[max] host; *count receives the number of iterations. */
+#define THC_ITER_MIXED 1
+#define THC_ITER_RESTARTED 2
+#define THC_ITER_DIIS_DROPPED 4
+int thc_history_flags(const thc_ctx* ctx, int max, int* flags, int* count);
 
 /* Per-iteration record of the last thc_iterate call (host arrays of length >= max, any may be
  * NULL): energy and residual norm of the amplitudes evaluated at each iteration and the wall

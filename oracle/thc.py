@@ -14,7 +14,8 @@ Definitions followed:
 Readings (no statement in the paper): the update is Jacobi in the generalized
 eigenbasis of the Fock part, E_mat w = e S w, where the projected Fock operator is
 exactly diagonal (denominators e_P + e_Q); DIIS is Pulay's with the preconditioned
-residual as error vector; convergence is ||(sigma^, sigma1)||_F < tol and |dE| < tol_e.
+residual as error vector, dropping its oldest vectors while their error overlap matrix has a
+condition number above 1e12; convergence is ||(sigma^, sigma1)||_F < tol and |dE| < tol_e.
 """
 from __future__ import annotations
 
@@ -153,6 +154,17 @@ class SolveResult:
     history: list = field(default_factory=list)
 
 
+def _diis_condition(vecs, errs, limit=1e12):
+    """Keeps the DIIS subspace well conditioned: drops the oldest vector (in place) while the
+    error overlap matrix of those kept has a condition number above `limit`."""
+    while len(vecs) >= 2:
+        w = np.linalg.eigvalsh(np.array([[np.dot(a, b) for b in errs] for a in errs]))
+        if w[0] > w[-1] / limit:
+            return
+        vecs.pop(0)
+        errs.pop(0)
+
+
 def _diis_extrapolate(vecs, errs):
     m = len(vecs)
     Bm = np.empty((m + 1, m + 1))
@@ -216,6 +228,7 @@ def solve(eps, L, Xo, Xv, xo=None, xv=None, Z0=None, singles=True, tol=1e-8, tol
             if len(vecs) > diis:
                 vecs.pop(0)
                 errs.pop(0)
+            _diis_condition(vecs, errs)
             if len(vecs) >= 2:
                 x = _diis_extrapolate(vecs, errs)
                 Th = x[: Th.size].reshape(Th.shape)

@@ -71,6 +71,7 @@ struct thc_ctx {
   double *W = nullptr, *e = nullptr;
   // state
   double *Th = nullptr, *t1 = nullptr, *Zs = nullptr;
+  double* Th0 = nullptr;  // the MP2 guess in the working basis: the solver's fallback start
   // DIIS ring
   double *dvec = nullptr, *derr = nullptr, *dT = nullptr, *dt1 = nullptr;
   int diis_n = 0, diis_head = 0;
@@ -113,6 +114,7 @@ struct thc_ctx {
   // per-iteration history of the last thc_iterate call
   std::vector<double> hist_e, hist_r, hist_t;
   std::vector<int> hist_mixed;  // 1 where the iteration's residual was mixed precision
+  std::vector<int> hist_flags;  // THC_ITER_* bits per iteration
 
   // profiling
   bool prof = false;
@@ -404,7 +406,8 @@ std::vector<BufSpec> persistent_list(thc_ctx* ctx) {
       {&ctx->xo, (size_t)(o * Q)}, {&ctx->xv, (size_t)(v * Q)}, {&ctx->Go, (size_t)PP}, {&ctx->Gv, (size_t)PP},
       {&ctx->S, (size_t)PP}, {&ctx->z, (size_t)(Q * Q)}, {&ctx->Bq, (size_t)(Q * ov)}, {&ctx->Bkr, (size_t)(ov * P)},
       {&ctx->W, (size_t)PP}, {&ctx->e, (size_t)P},
-      {&ctx->Th, (size_t)PP}, {&ctx->t1, (size_t)ov}, {&ctx->Zs, (size_t)PP}, {&ctx->delta, (size_t)P},
+      {&ctx->Th, (size_t)PP}, {&ctx->Th0, (size_t)PP}, {&ctx->t1, (size_t)ov}, {&ctx->Zs, (size_t)PP},
+      {&ctx->delta, (size_t)P},
       {&ctx->dvec, (size_t)(std::max<int64_t>(dm, 1) * (PP + ov))}, {&ctx->derr, (size_t)(std::max<int64_t>(dm, 1) * (PP + ov))},
       {&ctx->dT, (size_t)(PP + ov)},
       {&ctx->sig, (size_t)PP}, {&ctx->sig1, (size_t)ov}, {&ctx->sigh, (size_t)PP}, {&ctx->scal, 64},
@@ -1487,6 +1490,7 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
       rc = gemm(ctx, mk(P, P, P, ctx->W, P, true, Em, P, false, ctx->Th, P)); if (rc) break;
     }
     rc = zero(ctx, ctx->t1, ov); if (rc) break;
+    HIPCHK(hipMemcpyAsync(ctx->Th0, ctx->Th, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
     rc = raw_from_basis(ctx, ctx->Th, ctx->Zs); if (rc) break;
     if (Zout) HIPCHK(hipMemcpyAsync(Zout, ctx->Zs, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1579,6 +1583,14 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   double rn_first = -1.0, rn_prev = 0.0;
   int mixed_its = 0;
   ctx->hist_mixed.clear();
+  ctx->hist_flags.clear();
+  // divergence: a residual norm that is not finite, above 10 times the smallest of this run, or
+  // larger than its predecessor three times in a row.  The first time, the solver restarts from
+  // the MP2 guess with the plain denominators e_P + e_Q and an empty DIIS subspace; the second
+  // time it stops with THC_EDIVERGED.
+  double rn_min = -1.0, rn_last = -1.0;
+  int rises = 0;
+  bool fell_back = false, restarted = false;
   for (int it = 1; it <= maxit; ++it) {
     ctx->want_mixed = mixed_phase;
     RCHK(residual_impl(ctx, ctx->Zs, singles ? ctx->t1 : nullptr, THC_TERM_ALL));
@@ -1587,17 +1599,42 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
     RCHK(read_scalars(ctx, h, 10));
     const double E = energy_from_scalars(h, singles);
     const double rn = std::sqrt(h[8] + h[9]);
-    if (!std::isfinite(E) || !std::isfinite(rn)) {
-      ctx->err = "residual or energy is not finite";
-      if (iters) *iters = it;
-      return THC_ENUMERIC;
-    }
+    const bool finite = std::isfinite(E) && std::isfinite(rn);
     if (iters) *iters = it;
     if (rnorm) *rnorm = rn;
     ctx->hist_e.push_back(E);
     ctx->hist_r.push_back(rn);
     ctx->hist_t.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
     ctx->hist_mixed.push_back(mixed_phase ? 1 : 0);
+    ctx->hist_flags.push_back((mixed_phase ? THC_ITER_MIXED : 0) | (restarted ? THC_ITER_RESTARTED : 0));
+    restarted = false;
+    if (finite && rn_last >= 0.0) rises = rn > rn_last ? rises + 1 : 0;
+    const bool diverged = !finite || (rn_min > 0.0 && rn > 10.0 * rn_min) || rises >= 3;
+    if (finite) {
+      rn_last = rn;
+      rn_min = rn_min < 0.0 ? rn : std::min(rn_min, rn);
+    }
+    if (diverged) {
+      if (fell_back) {
+        ctx->err = finite ? "the iteration diverged again after restarting from the MP2 guess"
+                          : "residual or energy is not finite after restarting from the MP2 guess";
+        return THC_EDIVERGED;
+      }
+      fell_back = restarted = true;
+      HIPCHK(hipMemcpyAsync(ctx->Th, ctx->Th0, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
+      RCHK(zero(ctx, ctx->t1, ov));
+      RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
+      ctx->has_shift = false;
+      ctx->diis_n = 0;
+      ctx->diis_head = 0;
+      mixed_phase = ctx->opt.precision >= 1;
+      rn_first = -1.0;
+      mixed_its = 0;
+      rn_min = rn_last = -1.0;
+      rises = 0;
+      have_old = false;
+      continue;
+    }
     if (mixed_phase) {
       ++mixed_its;
       if (rn_first < 0.0) rn_first = rn;
@@ -1623,18 +1660,32 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
       HIPCHK(hipMemcpyAsync(es, ctx->dT, len * sizeof(double), hipMemcpyDeviceToDevice, s));
       ctx->diis_head = (slot + 1) % dm;
       if (ctx->diis_n < dm) ctx->diis_n++;
-      const int m = ctx->diis_n;
+      const int mfull = ctx->diis_n;
       // inner products of the new error with every stored error (device), B on the host
-      std::vector<int> slots(m);
-      for (int k = 0; k < m; ++k) slots[k] = (ctx->diis_head - m + k + 2 * dm) % dm;  // oldest first
-      for (int k = 0; k < m; ++k)
+      std::vector<int> slots(mfull);
+      for (int k = 0; k < mfull; ++k) slots[k] = (ctx->diis_head - mfull + k + 2 * dm) % dm;  // oldest first
+      for (int k = 0; k < mfull; ++k)
         MISC(k_dot(len, ctx->derr + (int64_t)slots[k] * len, es, ctx->scal + 16 + k, s));
       double bd[16];
-      RCHK(d2h(ctx, bd, ctx->scal + 16, m * sizeof(double)));
-      for (int k = 0; k < m; ++k) {
+      RCHK(d2h(ctx, bd, ctx->scal + 16, mfull * sizeof(double)));
+      for (int k = 0; k < mfull; ++k) {
         ctx->diisB[(size_t)slots[k] * dm + slot] = bd[k];
         ctx->diisB[(size_t)slot * dm + slots[k]] = bd[k];
       }
+      // conditioning: while the error overlap matrix of the kept vectors has a condition number
+      // above 1e12, the oldest vector is dropped
+      int m = ctx->diis_n;
+      while (m >= 2) {
+        std::vector<double> Bm((size_t)m * m), wv(m);
+        for (int i = 0; i < m; ++i)
+          for (int j = 0; j < m; ++j)
+            Bm[(size_t)i * m + j] = ctx->diisB[(size_t)slots[mfull - m + i] * dm + slots[mfull - m + j]];
+        if (host_syev(m, Bm.data(), wv.data()) == 0 && wv[0] > 1e-12 * wv[m - 1]) break;
+        --m;
+        ctx->hist_flags.back() |= THC_ITER_DIIS_DROPPED;
+      }
+      ctx->diis_n = m;
+      if (m < mfull) slots.erase(slots.begin(), slots.begin() + (mfull - m));
       if (m >= 2) {
         // Pulay: [B -1; -1 0] [c; l] = [0; -1], solved by Gaussian elimination with pivoting
         const int N = m + 1;
@@ -1683,6 +1734,14 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   }
   ctx->err = "iteration limit reached";
   return THC_ENOTCONV;
+}
+
+int thc_history_flags(const thc_ctx* ctx, int max, int* flags, int* count) {
+  if (!ctx || max < 0 || (max > 0 && !flags)) return THC_EINVAL;
+  const int n = (int)ctx->hist_flags.size();
+  for (int k = 0; k < std::min(n, max); ++k) flags[k] = ctx->hist_flags[k];
+  if (count) *count = n;
+  return THC_OK;
 }
 
 int thc_history_precision(const thc_ctx* ctx, int max, int* mixed, int* count) {

@@ -14,10 +14,11 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libthc.so")
 
-THC_OK, THC_EINVAL, THC_ENOMEM, THC_EDEVICE, THC_ESINGULAR, THC_ENUMERIC, THC_ENOTCONV, THC_ESTATE = (
-    0, -1, -2, -3, -4, -5, -6, -7)
+THC_OK, THC_EINVAL, THC_ENOMEM, THC_EDEVICE, THC_ESINGULAR, THC_ENUMERIC, THC_ENOTCONV, THC_ESTATE, THC_EDIVERGED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
 ERRNAMES = {0: "THC_OK", -1: "THC_EINVAL", -2: "THC_ENOMEM", -3: "THC_EDEVICE", -4: "THC_ESINGULAR",
-            -5: "THC_ENUMERIC", -6: "THC_ENOTCONV", -7: "THC_ESTATE"}
+            -5: "THC_ENUMERIC", -6: "THC_ENOTCONV", -7: "THC_ESTATE", -8: "THC_EDIVERGED"}
+ITER_MIXED, ITER_RESTARTED, ITER_DIIS_DROPPED = 1, 2, 4
 
 TERM_EQ28, TERM_EQ29, TERM_EQ31, TERM_EQ32, TERM_EQ35, TERM_EQ41, TERM_EQ38, TERM_EQ42 = (1 << k for k in range(8))
 TERM_ALL = 0xFF
@@ -27,7 +28,7 @@ TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TER
 
 # exported symbols (kept in sync with include/thc.h; checked by the tests)
 SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_history",
-           "thc_history_precision",
+           "thc_history_precision", "thc_history_flags",
            "thc_energy",
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan",
            "thc_set_synthetic", "thc_synth_gamma", "thc_create_with_workspace", "thc_plan_query", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH):
     lib.thc_history.argtypes = [VP, C.c_int, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(C.c_int)]
     lib.thc_energy.argtypes = [VP, C.POINTER(D)]
     lib.thc_history_precision.argtypes = [VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.thc_history_flags.argtypes = [VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.thc_get_state.argtypes = [VP, P, P]
     lib.thc_set_state.argtypes = [VP, P, P]
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
@@ -340,6 +342,13 @@ class THC:
         n = C.c_int(0)
         self._check(self.lib.thc_history_precision(self.ctx, max_it, f, C.byref(n)), "thc_history_precision")
         return list(f[:min(n.value, max_it)])
+
+    def history_flags(self, max_it=1000):
+        """THC_ITER_* bits of each iteration of the last iterate() call."""
+        f = (C.c_int * max_it)()
+        n = C.c_int(0)
+        self._check(self.lib.thc_history_flags(self.ctx, max_it, f, C.byref(n)), "thc_history_flags")
+        return [f[k] for k in range(min(n.value, max_it))]
 
     def energy(self):
         e = C.c_double(0.0)

@@ -1,0 +1,101 @@
+"""Failure handling of the solver (thc_iterate), each condition forced from the host: a NaN
+state, a start a hundred times the MP2 guess, an iteration limit of one, and inputs on which the
+plain iteration itself diverges (the unscaled synthetic Cholesky vectors)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2111_11473_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def thc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_11473_amd import thc as mod
+    mod.load()
+    return mod
+
+
+def _ctx(thc, cfg, gamma=0.0):
+    ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, singles=True, tol_energy=1e-10)
+    ctx.set_synthetic(cfg.seed, cfg.decay, cfg.coupling, gamma)
+    Z0 = ctx.build_synthetic()
+    return ctx, Z0
+
+
+@pytest.fixture(scope="module")
+def plain(thc):
+    cfg = synth.CONFIGS["tiny"]
+    ctx, Z0 = _ctx(thc, cfg)
+    it, rn, ok = ctx.iterate(tol=1e-9, maxit=60)
+    assert ok and not any(f & thc.ITER_RESTARTED for f in ctx.history_flags())
+    e = ctx.energy()
+    ctx.close()
+    _say("plain solve", it, e)
+    return cfg, it, e
+
+
+def test_nan_state_restarts_from_the_mp2_guess(thc, plain):
+    cfg, it_plain, e_plain = plain
+    ctx, Z0 = _ctx(thc, cfg)
+    Z = Z0.clone()
+    Z[3, 5] = float("nan")
+    ctx.set_state(Z)
+    it, rn, ok = ctx.iterate(tol=1e-9, maxit=60)
+    flags = ctx.history_flags()
+    _say("nan", it, flags)
+    assert ok
+    assert [k for k, f in enumerate(flags) if f & thc.ITER_RESTARTED] == [1]
+    assert abs(ctx.energy() - e_plain) < 1e-9
+    # after the restart the iteration is the plain one from the guess
+    assert abs((it - 1) - it_plain) <= 1
+    ctx.close()
+
+
+@pytest.mark.parametrize("factor", [100.0, 1.0e4])
+def test_far_start_reaches_the_plain_solution(thc, plain, factor):
+    """Starts 100 and 10^4 times the MP2 guess end at the plain solution: by DIIS (whose oldest
+    vectors are dropped when the subspace becomes ill-conditioned) or after one restart."""
+    cfg, it_plain, e_plain = plain
+    ctx, Z0 = _ctx(thc, cfg)
+    ctx.set_state(Z0 * factor)
+    it, rn, ok = ctx.iterate(tol=1e-9, maxit=60)
+    flags = ctx.history_flags()
+    _say("times", factor, it, flags)
+    assert ok and sum(1 for f in flags if f & thc.ITER_RESTARTED) <= 1
+    assert abs(ctx.energy() - e_plain) < 1e-9
+    ctx.close()
+
+
+def test_iteration_limit_then_continue(thc, plain):
+    cfg, it_plain, e_plain = plain
+    ctx, _ = _ctx(thc, cfg)
+    it, rn, ok = ctx.iterate(tol=1e-9, maxit=1, raise_on_notconv=False)
+    assert (it, ok) == (1, False)
+    with pytest.raises(thc.ThcError, match="THC_ENOTCONV"):
+        ctx.iterate(tol=1e-9, maxit=1)
+    it, rn, ok = ctx.iterate(tol=1e-9, maxit=60)
+    assert ok and abs(ctx.energy() - e_plain) < 1e-9
+    ctx.close()
+
+
+def test_divergence_after_restart_is_reported(thc):
+    """With the unscaled Cholesky vectors (gamma = 1: amplitudes of order ten, far past the
+    convergence radius) the plain iteration diverges from the MP2 guess, restarts once, diverges
+    again, and the call ends with THC_EDIVERGED."""
+    cfg = synth.CONFIGS["tiny"]
+    ctx, _ = _ctx(thc, cfg, gamma=1.0)
+    with pytest.raises(thc.ThcError, match="THC_EDIVERGED"):
+        ctx.iterate(tol=1e-9, maxit=60)
+    flags = ctx.history_flags()
+    _say("unscaled", len(flags), flags)
+    assert sum(1 for f in flags if f & thc.ITER_RESTARTED) == 1
+    ctx.close()

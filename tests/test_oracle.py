@@ -239,3 +239,21 @@ def test_energy_from_factors_matches_dense_energy():
     e_ref = ccsd.energy(s["L"], np.zeros((3, 6)), oracle.amplitudes(s["Xo"], s["Xv"], Z))
     e = oracle.energy_from_factors(s["L"], s["Xo"], s["Xv"], Z)
     assert abs(e - e_ref) < 1e-12 * max(1.0, abs(e_ref))
+
+
+def test_diis_drops_oldest_vectors_of_an_ill_conditioned_subspace():
+    """DIIS conditioning rule: the oldest vectors go while the error overlap matrix has a
+    condition number above 1e12 (two equal errors make it singular); a well-conditioned
+    subspace is kept whole."""
+    from oracle.thc import _diis_condition
+    rng = np.random.default_rng(0)
+    a, b, c = rng.standard_normal((3, 20))
+    vecs, errs = [1, 2, 3, 4], [a, a.copy(), b, c]
+    _diis_condition(vecs, errs)
+    assert vecs == [2, 3, 4] and len(errs) == 3
+    vecs, errs = [1, 2, 3], [a, b + 1e-9 * a, b]
+    _diis_condition(vecs, errs)
+    assert vecs == [3]
+    vecs, errs = [1, 2, 3], [a, b, c]
+    _diis_condition(vecs, errs)
+    assert vecs == [1, 2, 3]
