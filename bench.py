@@ -146,6 +146,42 @@ def gpu_rate_on(sample_name, n_eval=10):
 LEG_PRECISION = {"fp64": 0, "mixed": 1, "mixed_split_bf16": 2}
 
 
+def counter_summary(csv_dir, top=14):
+    """Per-kernel table from a rocprofv3 --pmc run of this script (--output-format csv) with the
+    counters SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_F64/F32, SQ_INSTS_VALU_FLOPS_FP64,
+    SQ_INSTS_VALU, SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT and GRBM_GUI_ACTIVE: fractions of the
+    kernel's active cycles (clock independent) and the work counted by the hardware."""
+    import collections
+    import csv
+    import glob
+    import re
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for f in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                m = re.search(r"(\w+_kernel)(<[^>]*>)?", row["Kernel_Name"])
+                k = (m.group(1) + (m.group(2) or "")) if m else row["Kernel_Name"][:40]
+                agg[k][row["Counter_Name"]] += float(row["Counter_Value"])
+                disp[k].add(row.get("Dispatch_Id", ""))
+    simds, xcc = 1024, 8  # MI355X: 256 CUs x 4 SIMDs; GRBM_GUI_ACTIVE is reported per XCD
+    rows = sorted(agg.items(), key=lambda kv: -kv[1]["GRBM_GUI_ACTIVE"])
+    total = sum(v["GRBM_GUI_ACTIVE"] for _, v in rows)
+    lines = ["| kernel | dispatches | share of active cycles | MFMA busy | MFMA flops (MOPS x 512) | "
+             "FP64 VALU flops issued | VALU issue busy | LDS bank-conflict cycles per LDS instruction |",
+             "|---|---|---|---|---|---|---|---|"]
+    for k, v in rows[:top]:
+        cyc = v["GRBM_GUI_ACTIVE"] / xcc
+        mf = 512.0 * (v.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) + v.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0))
+        lds = v.get("SQ_INSTS_LDS", 0.0)
+        lines.append(f"| {k} | {len(disp[k])} | {100 * v['GRBM_GUI_ACTIVE'] / total:.1f}% | "
+                     f"{v.get('SQ_VALU_MFMA_BUSY_CYCLES', 0.0) / (simds * cyc):.2f} | {mf:.3e} | "
+                     f"{64 * v.get('SQ_INSTS_VALU_FLOPS_FP64', 0.0):.3e} | "
+                     f"{4 * v.get('SQ_INSTS_VALU', 0.0) / (simds * cyc):.2f} | "
+                     f"{(v.get('SQ_LDS_BANK_CONFLICT', 0.0) / lds) if lds else 0.0:.2f} |")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,7 +199,12 @@ def main():
     ap.add_argument("--converge-maxit", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (a known-traffic kernel for counter scaling)")
+    ap.add_argument("--counter-summary", metavar="DIR",
+                    help="print the per-kernel table of a rocprofv3 --pmc CSV output directory and exit")
     args = ap.parse_args()
+    if args.counter_summary:
+        print(counter_summary(args.counter_summary))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         sys.exit("bench.py: the THC-CCSD hot path runs on one GPU; multi-GPU runs are not "
