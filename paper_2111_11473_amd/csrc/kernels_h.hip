@@ -230,11 +230,16 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
   constexpr unsigned GBLK_B = 16u * C::BZ * 8u;                       // bytes of one G block
   const unsigned nbz = (unsigned)Pp / C::BZ;                          // G blocks per block row
   unsigned voff_g, so_g;
+  // Both G blocks land in LDS swizzled (see gsw / gmsw below) so that the sixteen values a wave
+  // broadcasts from either fall in distinct banks: lane l fills LDS granule l (16 bytes) with the
+  // granule of the source block that the swizzle puts there.
   if (g_yz) {
-    voff_g = (unsigned)gs * 1024u + (unsigned)lane * 16u;
+    const int y = lane / 4, zp = (lane % 4) ^ (((y >> 1) & 1) << 1);  // storage row, source column pair
+    voff_g = (unsigned)gs * 1024u + (unsigned)(y * 4 + zp) * 16u;
     so_g = ((unsigned)Yb * nbz + (unsigned)(z0 / C::BZ)) * GBLK_B;
   } else {
-    const int r = gs * 8 + lane / 8, col = 2 * (lane % 8);  // destination row (Z) and column (Y)
+    const int r = gs * 8 + lane / 8;                     // destination row (Z)
+    const int col = (2 * (lane % 8)) ^ (4 * (r & 3));    // source column (Y) of the storage pair
     voff_g = (unsigned)(col / C::BZ) * GBLK_B + ((unsigned)(zs * C::BZ + r) * C::BZ + (unsigned)(col % C::BZ)) * 8u;
     so_g = ((unsigned)Zb * nbz + (unsigned)(y0 / C::BZ)) * GBLK_B;
   }
@@ -267,10 +272,13 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
     g_at += dPP;
   };
 
-  // broadcast-register sources: lane l holds G^YZ[ly0 + 4 r + m / 4][lz0 + m % 4], m = l % 16
+  // broadcast-register sources: lane l holds G^YZ[ly0 + 4 r + m / 4][lz0 + m % 4], m = l % 16.
+  // LDS holds G^YZ (y, z) at y BZ + (z ^ 4 ((y >> 1) & 1)) and G^ZY (z, y) at z BY + (y ^ 4 (z & 3)):
+  // the 4 x 4 values a read takes (32 banks of 4 bytes) then cover every bank once instead of
+  // two (G^YZ: rows y and y + 2) or four (G^ZY: every row) times.
   const int m = lane & 15;
-  const int goff0 = (ly0 + (m >> 2)) * C::BZ + lz0 + (m & 3);
-  const int gmoff0 = (lz0 + (m & 3)) * BY + ly0 + (m >> 2);
+  const int goff0 = (ly0 + (m >> 2)) * C::BZ + ((lz0 + (m & 3)) ^ (((m >> 3) & 1) << 2));
+  const int gmoff0 = (lz0 + (m & 3)) * BY + ((ly0 + (m >> 2)) ^ (4 * (m & 3)));
 
   constexpr int D = NS - 1;  // stages in flight ahead of the one being consumed
   static_assert(D <= 3, "wait_pipe allows at most two stages in flight behind the next one");
@@ -303,7 +311,7 @@ __global__ __launch_bounds__((Geo<NWZ, NS, TE>::NTHREADS)) void h_kernel(int Pp,
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       g[r] = sg[goff0 + 4 * r * C::BZ];
-      gm[r] = sgm[gmoff0 + 4 * r];
+      gm[r] = sgm[gmoff0 ^ (4 * r)];
     }
 #pragma unroll
     for (int p = 0; p < WY / 2; ++p) {
