@@ -73,6 +73,8 @@ typedef struct thc_options {
   int32_t flags;            /* THC_FLAG_* bits; 0 = defaults */
   int64_t x7_chunk;         /* amplitude ranks X per chunk of the Alg. 7 intermediates (R^X, S^X
                              * half-transformed, exchange outputs); 0 = automatic */
+  int64_t q_pairs;          /* Alg. 4 and 5: pairs per batched product; 0 = automatic */
+  int64_t q_jchunk;         /* Alg. 4 and 5: occupied j per chunk of the dense residual; 0 = automatic */
 } thc_options;
 
 /* Alg. 7 exchange contraction: by default fused on chip (no Q x Q intermediate) when o <= 200;
@@ -85,6 +87,12 @@ typedef struct thc_options {
 /* Print a line to stderr after each block of the residual's outer loops (fused pass over
  * Cholesky vectors, Alg. 6 H blocks, Alg. 7 row chunks), waiting for the stream each time. */
 #define THC_FLAG_PROGRESS (1 << 2)
+/* The quadratic ladder and exchange terms (Eq. 32 + 33): by default the context takes whichever of
+ * the paper's two algorithms its cost model estimates faster -- Alg. 4 and 5 (O(N^5), every step
+ * a matrix product; small systems) or Alg. 6 (O(N^4) with the three-way H accumulation).  These
+ * flags force one (not both). */
+#define THC_FLAG_QUINTIC (1 << 3)
+#define THC_FLAG_QUARTIC (1 << 4)
 
 /* Creates a context bound to the current HIP device and to `stream` (hipStream_t; NULL = the
  * default stream).  Allocates nothing on the device yet.  *out receives the context.
@@ -219,6 +227,10 @@ typedef struct thc_plan_info {
   int64_t x7_chunks;      /* such chunks per residual */
   int32_t exchange_fused; /* 1: the fused Alg. 7 exchange kernel, 0: its two-GEMM form */
   int32_t lvv_resident;   /* 1: the vv Cholesky block is held in device memory */
+  int32_t quintic;        /* 1: Eq. 32 + 33 by Alg. 4 and 5 (O(N^5)), 0: by Alg. 6 */
+  int32_t reserved;
+  int64_t q_pairs;        /* Alg. 4 and 5: pairs per batched product */
+  int64_t q_jchunk;       /* Alg. 4 and 5: occupied j per chunk of the dense residual */
   uint64_t device_bytes;  /* device working memory */
 } thc_plan_info;
 int thc_plan(const thc_ctx* ctx, thc_plan_info* out);

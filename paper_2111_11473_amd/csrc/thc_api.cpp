@@ -95,6 +95,11 @@ struct thc_ctx {
   double *tmpoP = nullptr, *tmpvP = nullptr, *Fxoo = nullptr, *Fxvv = nullptr, *Tf = nullptr, *fd = nullptr;
   // Alg. 6
   double *C6 = nullptr, *D6 = nullptr, *Ec = nullptr, *Fc = nullptr, *Gc = nullptr, *GYc = nullptr, *Hb = nullptr;
+  // Alg. 4 and 5 (the O(N^5) form of Eq. 32 and 33), when chosen instead of Alg. 6
+  bool quintic = false;
+  int64_t nq = 0, jq = 0;  // pairs per batched product; occupied j per chunk of the dense residual
+  double *Wq = nullptr, *qC = nullptr, *qD1 = nullptr, *qE = nullptr, *qF1 = nullptr, *qF = nullptr, *qG1 = nullptr,
+         *qG = nullptr, *qI1 = nullptr, *qR = nullptr, *qT1 = nullptr;
   double* delta = nullptr;     // Jacobi denominator shift of the learned guess (nP)
   void* pin = nullptr;         // pinned host staging buffer for every host <-> device transfer
   size_t pin_bytes = 0;
@@ -490,6 +495,37 @@ size_t tile_table_doubles(int64_t Pp, int64_t Xb, int64_t slots) {
   return aligned((size_t)((e + 1) / 2));
 }
 
+// Flops of the quadratic ladder and exchange terms (Eq. 32 + 33) by the O(N^5) Algorithms 4 and 5
+// (every step a matrix product: per (i, j) pair of Alg. 4 and (j, a) pair of Alg. 5, the
+// amplitudes, their Q x Q ERI transform, back, and the projection of the dense residual), and an
+// estimate of their time against Alg. 6 at the measured rates (FP64 MFMA products ~45 TFLOP/s,
+// the H-kernel ~26 TFLOP/s issued).
+double quintic_flops(int64_t o, int64_t v, int64_t P, int64_t Q) {
+  const double O = (double)o, V = (double)v, PP = (double)P, QQ = (double)Q, ov = O * V;
+  const double a4 = O * O * (2 * V * V * PP + 2 * V * V * QQ + 2 * QQ * QQ * V + 2 * O * QQ * QQ + 2 * O * O * QQ +
+                             2 * O * O * PP + 2 * O * PP * PP + 2 * V * PP * PP + 2 * V * V * PP);
+  const double a5 = ov * (2 * ov * PP + 2 * ov * QQ + 2 * QQ * QQ * O + 2 * QQ * QQ * V + 2 * O * QQ * V + 2 * ov * PP +
+                          2 * V * PP * PP + 2 * O * PP * PP + 2 * ov * PP);
+  return a4 + a5 + 2 * O * PP * PP * V + 2 * ov * ov * PP + 2 * ov * PP * PP;
+}
+
+bool prefer_quintic(int64_t o, int64_t v, int64_t P, int64_t Q) {
+  const double Pd = (double)P, Qd = (double)Q, od = (double)o, vd = (double)v;
+  const double t6 = 3.5 * Qd * Pd * Pd * Pd / 26.0e12 +
+                    (2 * (od + vd) * Pd * Pd * Qd + 2 * Qd * (od * vd * Pd + od * Pd * Pd) + 2 * vd * Pd * Pd * Pd) / 45.0e12;
+  return quintic_flops(o, v, P, Q) / 45.0e12 < t6;
+}
+
+std::vector<BufSpec> quintic_list(thc_ctx* ctx) {
+  const int64_t o = ctx->o, v = ctx->v, P = ctx->P, Q = ctx->Q, ov = ctx->ov, w = std::max(o, v), n = ctx->nq;
+  return {{&ctx->Wq, (size_t)(o * P * v)},          {&ctx->qT1, (size_t)(ov * P)},
+          {&ctx->qR, (size_t)(ov * ctx->jq * v)},    {&ctx->qC, (size_t)(n * std::max(v * v, ov))},
+          {&ctx->qD1, (size_t)(n * w * Q)},          {&ctx->qE, (size_t)(n * Q * Q)},
+          {&ctx->qF1, (size_t)(n * w * Q)},          {&ctx->qF, (size_t)(n * std::max(o * o, ov))},
+          {&ctx->qG1, (size_t)(n * w * P)},          {&ctx->qG, (size_t)(n * P * P)},
+          {&ctx->qI1, (size_t)(n * w * P)}};
+}
+
 // Picks the blocking (nb, KS, Xb, Ic, X7, the residency of the vv block) for a budget of device
 // bytes and fills ctx->plan_bytes; THC_ENOMEM if even the smallest blocking does not fit.
 int choose_plan(thc_ctx* ctx, double budget, int64_t slots) {
@@ -527,6 +563,31 @@ int choose_plan(thc_ctx* ctx, double budget, int64_t slots) {
   const double pers = list_bytes(persistent_list(ctx));
   const double a7 = list_bytes(alg7_list(ctx));
   const double setup = 8.0 * (double)setup_doubles(ctx);
+  // Eq. 32 + 33 by Alg. 4 and 5 (asked for, or estimated faster) instead of Alg. 6
+  ctx->quintic = (op.flags & THC_FLAG_QUINTIC) ||
+                 (!(op.flags & THC_FLAG_QUARTIC) && prefer_quintic(o, v, P, Q));
+  if (ctx->quintic) {
+    ctx->Xb = std::min<int64_t>(64, P64);  // no H block; the tile table stays minimal
+    ctx->Ic = 1;
+    const double fixedq = 8.0 * ((double)o * P * v + (double)ov * P);
+    const double left = budget - pers - a7 - fixedq;
+    const int64_t w = std::max(o, v);
+    const double per_pair = 8.0 * (double)(aligned((size_t)std::max(v * v, ov)) + 2 * aligned((size_t)(w * Q)) +
+                                           aligned((size_t)(Q * Q)) + aligned((size_t)std::max(o * o, ov)) +
+                                           2 * aligned((size_t)(w * P)) + aligned((size_t)(P * P)));
+    // the dense residual for all j when it takes at most half of what is left, else by chunks of j
+    int64_t jq = o;
+    if (8.0 * (double)ov * ov > 0.5 * left) jq = std::max<int64_t>(1, (int64_t)(0.5 * left / (8.0 * (double)ov * v)));
+    ctx->jq = std::min(op.q_jchunk > 0 ? op.q_jchunk : jq, o);
+    const double rbytes = 8.0 * (double)ov * ctx->jq * v;
+    ctx->nq = std::min<int64_t>(w, (int64_t)((left - rbytes) / per_pair));
+    if (op.q_pairs > 0) ctx->nq = std::min(ctx->nq, op.q_pairs);
+    if (ctx->nq < 1 || budget - pers - a7 < setup) {
+      ctx->err = "the working memory of Alg. 4 and 5 does not fit the budget";
+      return THC_ENOMEM;
+    }
+    return THC_OK;
+  }
   // H block and grid-point chunk
   auto fixed6 = [&](int64_t Xb) { return 8.0 * (double)Xb * ((double)Pp * (o + v + Pp + o) + (double)ov); };
   auto per_i = [&](int64_t Xb) {
@@ -581,7 +642,7 @@ int plan_and_alloc(thc_ctx* ctx) {
   double *e32 = nullptr, *f32 = nullptr, *tb = nullptr;
   std::vector<BufSpec> pers = persistent_list(ctx);
   pers.push_back({&tb, (tiles.size() + 1) / 2});
-  const std::vector<BufSpec> r6 = region6_list(ctx, &e32, &f32), a7 = alg7_list(ctx);
+  const std::vector<BufSpec> r6 = ctx->quintic ? quintic_list(ctx) : region6_list(ctx, &e32, &f32), a7 = alg7_list(ctx);
   size_t np = 0, n6 = 0, n7 = 0;
   for (const auto& a : pers) np += aligned(a.n);
   for (const auto& a : r6) n6 += aligned(a.n);
@@ -625,6 +686,7 @@ int plan_and_alloc(thc_ctx* ctx) {
 // The Alg. 6 operands whose padding must stay zero, cleared once the set-up no longer uses the
 // region as scratch.
 int clear_region6(thc_ctx* ctx) {
+  if (ctx->quintic) return THC_OK;  // Alg. 4 and 5 need no zero padding
   const int64_t o = ctx->o, v = ctx->v, Pp = ctx->Pp, Xb = ctx->Xb, Ic = ctx->Ic;
   RCHK(zero(ctx, ctx->C6, o * Xb * Pp));
   RCHK(zero(ctx, ctx->D6, v * Xb * Pp));
@@ -652,6 +714,82 @@ int progress(thc_ctx* ctx, const char* what, int64_t done, int64_t total) {
 // Copies one scalar region of ctx->scal to the host.
 int read_scalars(thc_ctx* ctx, double* h, int count) {
   RCHK(d2h(ctx, h, ctx->scal, count * sizeof(double)));
+  return THC_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Eq. 32 and 33 by Alg. 4 and 5: sigma += B^T R B with R_(ia)(jb) the dense quadratic ladder
+// (Alg. 4: sum_kl X_ij^kl t_kl^ab, X_ij^kl = sum_cd t_ij^cd (kc|ld)) and exchange (Alg. 5:
+// sum_kcld t_ik^cb t_lj^ad (lc|kd)) terms, formed pair by pair as matrix products in batches of
+// pairs, with the THC form of (ia|jb); R is held for a chunk of occupied j at a time.
+int quintic_terms(thc_ctx* ctx, const double* T) {
+  const int64_t o = ctx->o, v = ctx->v, P = ctx->P, Q = ctx->Q, ov = ctx->ov;
+  const double *Yo = ctx->Yo, *Yv = ctx->Yv, *xo = ctx->xo, *xv = ctx->xv, *z = ctx->z;
+  // W_j[Z][d] = sum_Z' T[Z][Z'] y_j^Z' y_d^Z'  (the right half of t_.j^.d for every j)
+  {
+    Gemm g = batched(mk(P, v, P, T, P, false, Yv, P, true, ctx->Wq, v), o, 0, 0, P * v);
+    g.kscaleB = Yo; g.ksB = 1; g.sksB = P;
+    RCHK(gemm(ctx, g));
+  }
+  const int64_t nq = ctx->nq, jq = ctx->jq, ldR = jq * v;
+  for (int64_t j0 = 0; j0 < o; j0 += jq) {
+    const int64_t jc = std::min(jq, o - j0);
+    // Alg. 4: pairs (i, j), a batch of j for each i
+    for (int64_t i = 0; i < o; ++i) {
+      for (int64_t b0 = 0; b0 < jc; b0 += nq) {
+        const int64_t nb = std::min(nq, jc - b0), j = j0 + b0;
+        // C[c][d] = t_ij^cd = sum_Z y_c^Z y_i^Z W_j[Z][d]
+        Gemm g = batched(mk(v, v, P, Yv, P, false, ctx->Wq + j * P * v, v, false, ctx->qC, v), nb, 0, P * v, v * v);
+        g.kscaleA = Yo + i * P; g.ksA = 1;
+        RCHK(gemm(ctx, g));
+        // E = z o (xv^T C xv);  F = xo E xo^T = X_ij^kl
+        RCHK(gemm(ctx, batched(mk(v, Q, v, ctx->qC, v, false, xv, Q, false, ctx->qD1, Q), nb, v * v, 0, v * Q)));
+        Gemm ge = batched(mk(Q, Q, v, xv, Q, true, ctx->qD1, Q, false, ctx->qE, Q), nb, 0, v * Q, Q * Q);
+        ge.hmul = z; ge.ldh = Q;
+        RCHK(gemm(ctx, ge));
+        RCHK(gemm(ctx, batched(mk(o, Q, Q, xo, Q, false, ctx->qE, Q, false, ctx->qF1, Q), nb, 0, Q * Q, o * Q)));
+        RCHK(gemm(ctx, batched(mk(o, o, Q, ctx->qF1, Q, false, xo, Q, true, ctx->qF, o), nb, o * Q, 0, o * o)));
+        // H = T o (Yo^T F Yo);  R_ij^ab = (Yv H Yv^T)_ab = sum_kl X_ij^kl t_kl^ab
+        RCHK(gemm(ctx, batched(mk(o, P, o, ctx->qF, o, false, Yo, P, false, ctx->qG1, P), nb, o * o, 0, o * P)));
+        Gemm gh = batched(mk(P, P, o, Yo, P, true, ctx->qG1, P, false, ctx->qG, P), nb, 0, o * P, P * P);
+        gh.hmul = T; gh.ldh = P;
+        RCHK(gemm(ctx, gh));
+        RCHK(gemm(ctx, batched(mk(v, P, P, Yv, P, false, ctx->qG, P, false, ctx->qI1, P), nb, 0, P * P, v * P)));
+        RCHK(gemm(ctx, batched(mk(v, v, P, ctx->qI1, P, false, Yv, P, true, ctx->qR + i * v * ldR + b0 * v, ldR),
+                               nb, v * P, 0, v)));
+      }
+    }
+    // Alg. 5: pairs (j, a), a batch of a for each j; adds sum_kcld t_ik^cb t_lj^ad (lc|kd) to R
+    for (int64_t jj = 0; jj < jc; ++jj) {
+      const int64_t j = j0 + jj;
+      for (int64_t a0 = 0; a0 < v; a0 += nq) {
+        const int64_t na = std::min(nq, v - a0);
+        // C[l][d] = t_lj^ad = sum_Z y_l^Z y_a^Z W_j[Z][d]
+        Gemm g = batched(mk(o, v, P, Yo, P, false, ctx->Wq + j * P * v, v, false, ctx->qC, v), na, 0, 0, ov);
+        g.kscaleA = Yv + a0 * P; g.ksA = 1; g.sksA = P;
+        RCHK(gemm(ctx, g));
+        // E = z o (xo^T C xv);  F[k][c] = sum_J xo[k][J] sum_I E[I][J] xv[c][I]
+        RCHK(gemm(ctx, batched(mk(o, Q, v, ctx->qC, v, false, xv, Q, false, ctx->qD1, Q), na, ov, 0, o * Q)));
+        Gemm ge = batched(mk(Q, Q, o, xo, Q, true, ctx->qD1, Q, false, ctx->qE, Q), na, 0, o * Q, Q * Q);
+        ge.hmul = z; ge.ldh = Q;
+        RCHK(gemm(ctx, ge));
+        RCHK(gemm(ctx, batched(mk(Q, v, Q, ctx->qE, Q, true, xv, Q, true, ctx->qF1, v), na, Q * Q, 0, Q * v)));
+        RCHK(gemm(ctx, batched(mk(o, v, Q, xo, Q, false, ctx->qF1, v, false, ctx->qF, v), na, 0, Q * v, ov)));
+        // H = T o (Yv^T F^T Yo);  R_ij^ab += (Yo H Yv^T)_ib
+        RCHK(gemm(ctx, batched(mk(v, P, o, ctx->qF, v, true, Yo, P, false, ctx->qG1, P), na, ov, 0, v * P)));
+        Gemm gh = batched(mk(P, P, v, Yv, P, true, ctx->qG1, P, false, ctx->qG, P), na, 0, v * P, P * P);
+        gh.hmul = T; gh.ldh = P;
+        RCHK(gemm(ctx, gh));
+        RCHK(gemm(ctx, batched(mk(o, P, P, Yo, P, false, ctx->qG, P, false, ctx->qI1, P), na, 0, P * P, o * P)));
+        RCHK(gemm(ctx, batched(mk(o, v, P, ctx->qI1, P, false, Yv, P, true, ctx->qR + a0 * ldR + jj * v, v * ldR,
+                                  1.0, 1.0), na, o * P, 0, ldR)));
+      }
+    }
+    // sigma += B^T R B over the chunk's columns (jb)
+    RCHK(gemm(ctx, mk(ov, P, jc * v, ctx->qR, ldR, false, ctx->Bkr + j0 * v * P, P, false, ctx->qT1, P)));
+    RCHK(gemm(ctx, mk(P, P, ov, ctx->Bkr, P, true, ctx->qT1, P, false, ctx->sig, P, 1.0, 1.0)));
+    RCHK(progress(ctx, "Alg. 4 and 5 occupied chunks", j0 / jq + 1, (o + jq - 1) / jq));
+  }
   return THC_OK;
 }
 
@@ -853,9 +991,14 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     MISC(k_sym_add(P, ctx->Qm, 1.0, ctx->sig, s));
   }
 
+  // ---------------- Alg. 4 + 5: the same terms in O(N^5), all matrix products ---------------
+  if ((mask & THC_TERM_EQ32) && ctx->quintic) {
+    ctx->section = "gemm@alg45";
+    RCHK(quintic_terms(ctx, T));
+  }
   // ---------------- Alg. 6: quartic T2^2 ladder + exchange (Eq. 32 + 33) ----------------------
   ctx->section = "gemm@alg6";
-  if (mask & THC_TERM_EQ32) {
+  if ((mask & THC_TERM_EQ32) && !ctx->quintic) {
     const int64_t Xb = ctx->Xb, nX = Xb / 64;
     for (int64_t X0 = 0; X0 < P; X0 += Xb) {
       const int64_t xb = std::min(Xb, P - X0);
@@ -1183,8 +1326,10 @@ namespace {
 bool options_valid(const thc_options* opt) {
   if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
       opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) ||
-      (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV | THC_FLAG_PROGRESS)) != 0 || opt->a_block < 0 ||
-      opt->i_chunk < 0 || opt->x_block < 0 || opt->x_chunk < 0 || opt->x7_chunk < 0)
+      (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV | THC_FLAG_PROGRESS | THC_FLAG_QUINTIC |
+                      THC_FLAG_QUARTIC)) != 0 || ((opt->flags & THC_FLAG_QUINTIC) && (opt->flags & THC_FLAG_QUARTIC)) || opt->a_block < 0 ||
+      opt->i_chunk < 0 || opt->x_block < 0 || opt->x_chunk < 0 || opt->x7_chunk < 0 || opt->q_pairs < 0 ||
+      opt->q_jchunk < 0)
     return false;
   // the metric S = B^T B (nP x nP) and the ERI-grid Gram (nQ x nQ) have rank at most o v
   return opt->nP <= opt->o * opt->v && opt->nQ <= opt->o * opt->v;
@@ -1206,6 +1351,9 @@ void fill_plan_info(const thc_ctx* ctx, int64_t tiles, int64_t entries, int64_t 
   p.x7_chunks = (ctx->P + ctx->X7 - 1) / ctx->X7;
   p.exchange_fused = exch_supported(ctx->o) && !(ctx->opt.flags & THC_FLAG_UNFUSED_EXCHANGE);
   p.lvv_resident = ctx->lvv_resident ? 1 : 0;
+  p.quintic = ctx->quintic ? 1 : 0;
+  p.q_pairs = ctx->quintic ? ctx->nq : 0;
+  p.q_jchunk = ctx->quintic ? ctx->jq : 0;
   p.device_bytes = (uint64_t)bytes;
   *out = p;
 }
@@ -1236,7 +1384,8 @@ int thc_plan_query(const thc_options* opt, int synthetic, uint64_t budget_bytes,
   const int rc = choose_plan(&c, (double)budget_bytes, slots);
   if (rc != THC_OK) return rc;
   double *e32 = nullptr, *f32 = nullptr;
-  const double pers = list_bytes(persistent_list(&c)), r6 = list_bytes(region6_list(&c, &e32, &f32));
+  const double pers = list_bytes(persistent_list(&c)),
+               r6 = list_bytes(c.quintic ? quintic_list(&c) : region6_list(&c, &e32, &f32));
   const double a7 = list_bytes(alg7_list(&c)), setup = 8.0 * (double)setup_doubles(&c);
   int64_t tiles = 0, entries = 0;
   tile_counts(c.Pp, c.Xb, slots, &tiles, &entries);

@@ -44,7 +44,8 @@ class Options(C.Structure):
     _fields_ = [("o", C.c_int64), ("v", C.c_int64), ("nL", C.c_int64), ("nP", C.c_int64), ("nQ", C.c_int64),
                 ("singles", C.c_int32), ("diis_max", C.c_int32), ("tol_energy", C.c_double),
                 ("a_block", C.c_int64), ("i_chunk", C.c_int64), ("x_block", C.c_int64), ("x_chunk", C.c_int64),
-                ("precision", C.c_int32), ("flags", C.c_int32), ("x7_chunk", C.c_int64)]
+                ("precision", C.c_int32), ("flags", C.c_int32), ("x7_chunk", C.c_int64), ("q_pairs", C.c_int64),
+                ("q_jchunk", C.c_int64)]
 
 
 class PlanInfo(C.Structure):
@@ -52,7 +53,8 @@ class PlanInfo(C.Structure):
                 ("x_block", C.c_int64), ("x_blocks", C.c_int64), ("i_chunk", C.c_int64), ("i_chunks", C.c_int64),
                 ("h_generations", C.c_int64), ("h_tiles", C.c_int64), ("x_chunk", C.c_int64),
                 ("x7_chunk", C.c_int64), ("x7_chunks", C.c_int64),
-                ("exchange_fused", C.c_int32), ("lvv_resident", C.c_int32), ("device_bytes", C.c_uint64)]
+                ("exchange_fused", C.c_int32), ("lvv_resident", C.c_int32), ("quintic", C.c_int32),
+                ("reserved", C.c_int32), ("q_pairs", C.c_int64), ("q_jchunk", C.c_int64), ("device_bytes", C.c_uint64)]
 
 
 class SynthSpec(C.Structure):
@@ -61,6 +63,8 @@ class SynthSpec(C.Structure):
 
 FLAG_STREAM_LVV = 1 << 1
 FLAG_PROGRESS = 1 << 2
+FLAG_QUINTIC = 1 << 3
+FLAG_QUARTIC = 1 << 4
 
 
 class ThcError(RuntimeError):
@@ -184,9 +188,9 @@ def dgemm(A, B, C_out, transA=False, transB=False, alpha=1.0, beta=0.0):
 
 
 def make_options(o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0, x_block=0,
-                 x_chunk=0, flags=0, precision=0, x7_chunk=0):
+                 x_chunk=0, flags=0, precision=0, x7_chunk=0, q_pairs=0, q_jchunk=0):
     return Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
-                   precision, flags, x7_chunk)
+                   precision, flags, x7_chunk, q_pairs, q_jchunk)
 
 
 def plan_query(o, v, nL, nP, nQ, budget_bytes, synthetic=False, **kw):
@@ -236,14 +240,14 @@ class THC:
     """One THC-CCSD problem on the current GPU (all tensors float64, CUDA, contiguous)."""
 
     def __init__(self, o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0,
-                 x_block=0, x_chunk=0, flags=0, precision=0, x7_chunk=0, workspace=None):
+                 x_block=0, x_chunk=0, flags=0, precision=0, x7_chunk=0, q_pairs=0, q_jchunk=0, workspace=None):
         """workspace: None (the library allocates its working memory), or a CUDA tensor whose
         memory the library uses instead (thc_create_with_workspace; kept referenced here)."""
         self.lib = load()
         self.o, self.v, self.nL, self.nP, self.nQ = o, v, nL, nP, nQ
         self.singles = bool(singles)
         opt = make_options(o, v, nL, nP, nQ, singles, diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
-                           flags, precision, x7_chunk)
+                           flags, precision, x7_chunk, q_pairs, q_jchunk)
         h = C.c_void_p()
         self.workspace = workspace
         if workspace is None:

@@ -152,8 +152,9 @@ def test_wide_rank_paths_match_oracle(thc, i_chunk):
     on 128 x 128 tiles with its K split."""
     cfg = synth.CONFIGS["wide"]
     _say("terms wide i_chunk", i_chunk)
-    s, ctx, Z0 = _make(thc, cfg, i_chunk=i_chunk)
+    s, ctx, Z0 = _make(thc, cfg, i_chunk=i_chunk, flags=thc.FLAG_QUARTIC)
     plan = ctx.plan()
+    assert plan["quintic"] == 0
     _say("  plan", plan)
     assert plan["h_generations"] >= 2 and plan["alg1_tile"] == 128 and plan["alg1_splits"] >= 2
     assert plan["i_chunks"] == (1 if i_chunk == 0 else 4)

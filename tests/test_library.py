@@ -59,7 +59,7 @@ def test_create_rejects_invalid_options(lib, field, value):
     larger than the o v pairs (singular metric / Gram matrix), out-of-range options."""
     from paper_2111_11473_amd import thc
     base = dict(o=10, v=40, nL=150, nP=120, nQ=300, singles=1, diis_max=8, tol_energy=1e-8, a_block=0,
-                i_chunk=0, x_block=0, x_chunk=0, precision=0, flags=0, x7_chunk=0)
+                i_chunk=0, x_block=0, x_chunk=0, precision=0, flags=0, x7_chunk=0, q_pairs=0, q_jchunk=0)
     base[field] = value
     opt = thc.Options(**base)
     lib.thc_create.argtypes = [ctypes.POINTER(thc.Options), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
