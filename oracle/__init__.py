@@ -16,3 +16,4 @@ from .ccsd import (dress_cholesky, one_electron, dressed_fock, doubles_terms, si
 from .thc import (khatri_rao, amplitudes, project, eri_fit, eri_thc_dense, metric, fock_operator,
                   pseudo_canonical, mp2_amplitudes, mp2_guess, thc_residual, solve, SolveResult,
                   driver_projection, energy_from_factors)
+from .density import mp2_density

@@ -257,3 +257,54 @@ def test_diis_drops_oldest_vectors_of_an_ill_conditioned_subspace():
     vecs, errs = [1, 2, 3], [a, b, c]
     _diis_condition(vecs, errs)
     assert vecs == [1, 2, 3]
+
+
+def _density_loops(t2):
+    """Eq. 47 and 48 as explicit loops over every index (brute force for tiny sizes)."""
+    o, _, v, _ = t2.shape
+    Doo = np.zeros((o, o))
+    Dvv = np.zeros((v, v))
+    for i in range(o):
+        for j in range(o):
+            acc = 0.0
+            for k in range(o):
+                for a in range(v):
+                    for b in range(v):
+                        acc += t2[i, k, a, b] * (2.0 * t2[j, k, a, b] - t2[j, k, b, a])
+            Doo[i, j] = -2.0 * acc
+    for a in range(v):
+        for b in range(v):
+            acc = 0.0
+            for i in range(o):
+                for j in range(o):
+                    for c in range(v):
+                        acc += t2[i, j, a, c] * (2.0 * t2[i, j, b, c] - t2[j, i, b, c])
+            Dvv[a, b] = 2.0 * acc
+    return Doo, Dvv
+
+
+def test_mp2_density_matches_loops_and_conserves_particles():
+    """The MP2 one-particle density of THC amplitudes (App. II, Eq. 47-48): equal to the
+    definition written as loops; symmetric; and tr D_oo + tr D_vv = 0 (the correction moves
+    electrons from occupied to virtual orbitals, the count is unchanged) -- a dropped factor 2 or a
+    transposed exchange term breaks the trace balance."""
+    rng = np.random.default_rng(12)
+    o, v, P = 3, 4, 7
+    Xo, Xv = rng.standard_normal((o, P)), rng.standard_normal((v, P))
+    Z = rng.standard_normal((P, P))
+    Z = Z + Z.T
+    Doo, Dvv = oracle.mp2_density(Xo, Xv, Z)
+    Loo, Lvv = _density_loops(oracle.amplitudes(Xo, Xv, Z))
+    assert np.abs(Doo - Loo).max() < 1e-12 * np.abs(Loo).max()
+    assert np.abs(Dvv - Lvv).max() < 1e-12 * np.abs(Lvv).max()
+    assert np.abs(Doo - Doo.T).max() < 1e-12 * np.abs(Doo).max()
+    assert np.abs(Dvv - Dvv.T).max() < 1e-12 * np.abs(Dvv).max()
+    assert abs(np.trace(Doo) + np.trace(Dvv)) < 1e-12 * abs(np.trace(Dvv))
+    assert np.trace(Dvv) > 0  # positive virtual occupation of a real amplitude
+
+
+def test_mp2_density_of_a_single_pair_amplitude():
+    """One amplitude t_00^00 = t (o = v = 1): D_oo = -2 t^2, D_vv = 2 t^2 (closed form)."""
+    Xo, Xv, Z = np.array([[1.0]]), np.array([[1.0]]), np.array([[0.3]])
+    Doo, Dvv = oracle.mp2_density(Xo, Xv, Z)
+    assert abs(Doo[0, 0] + 2 * 0.09) < 1e-15 and abs(Dvv[0, 0] - 2 * 0.09) < 1e-15
