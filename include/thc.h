@@ -165,6 +165,13 @@ int thc_residual(thc_ctx* ctx, const double* Z, const double* t1, double* sigma,
 int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t mask, double* sigma,
                        double* sigma1);
 
+/* MP2 one-particle density matrix (unrelaxed, closed shell; paper App. II, Eq. 47-48) of the
+ * amplitudes t = sum y y Z y y of a core, evaluated in O(N^4) through the Gram matrices o, v
+ * (Eq. 51-56): D_ij = -2 sum_kab t_ik^ab (2 t_jk^ab - t_jk^ba), D_ab = 2 sum_ijc t_ij^ac
+ * (2 t_ij^bc - t_ji^bc).  Z [nP][nP] raw basis (NULL: the current state, after thc_build_factors
+ * the MP2 guess); Doo [o][o], Dvv [v][v] device outputs.  FP64. */
+int thc_mp2_density(thc_ctx* ctx, const double* Z, double* Doo, double* Dvv);
+
 /* Jacobi + DIIS iterations from the current state (the paper gives no update rule: this is the
  * standard denominator-weighted update in the working basis where the Fock part of the projected
  * residual is exactly diagonal, Sec. II's equations; Pulay DIIS): each iteration evaluates the

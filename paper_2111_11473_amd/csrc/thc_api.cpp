@@ -1654,6 +1654,49 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
   return THC_OK;
 }
 
+int thc_mp2_density(thc_ctx* ctx, const double* Z, double* Doo, double* Dvv) {
+  if (!ctx) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  if (!Doo || !Dvv) { ctx->err = "null output"; return THC_EINVAL; }
+  hipStream_t s = ctx->stream;
+  const int64_t o = ctx->o, v = ctx->v, P = ctx->P, PP = P * P;
+  const double *Yo = ctx->Yo, *Yv = ctx->Yv, *Go = ctx->Go, *Gv = ctx->Gv;
+  const double* T = Z ? Z : ctx->Zs;
+  // T S T with S = o o v (the metric, Eq. 51-52)
+  RCHK(gemm(ctx, mk(P, P, P, ctx->S, P, false, T, P, false, ctx->Qm, P)));
+  RCHK(gemm(ctx, mk(P, P, P, T, P, false, ctx->Qm, P, false, ctx->E9, P)));
+  // Coulomb-like parts (Eq. 53, 54): D_oo = -4 Yo (v o TST) Yo^T, D_vv = 4 Yv (o o TST) Yv^T
+  MISC(k_hadamard(PP, Gv, ctx->E9, 1.0, 0.0, ctx->ot, s));
+  MISC(k_hadamard(PP, Go, ctx->E9, 1.0, 0.0, ctx->vt, s));
+  RCHK(gemm(ctx, mk(o, P, P, Yo, P, false, ctx->ot, P, false, ctx->tmpoP, P)));
+  RCHK(gemm(ctx, mk(o, o, P, ctx->tmpoP, P, false, Yo, P, true, Doo, o, -4.0, 0.0)));
+  RCHK(gemm(ctx, mk(v, P, P, Yv, P, false, ctx->vt, P, false, ctx->tmpvP, P)));
+  RCHK(gemm(ctx, mk(v, v, P, ctx->tmpvP, P, false, Yv, P, true, Dvv, v, 4.0, 0.0)));
+  // Exchange-like parts (Eq. 55, 56), for blocks of the outer index r (i, or a):
+  //   M_r = (T^T diag(y_r) G1) o G2,  K_r = M_r T,  u_r^Y = sum_X G1^XY K_r^XY,
+  //   D[r][s] += f sum_Y y_s^Y u_r^Y
+  // with (G1, G2, y, f) = (v, o, y_o, 2) for D_oo and (o, v, y_v, -2) for D_vv.
+  const int64_t ch = std::min(ctx->nb, ctx->nL);  // blocks fit the fused pass's nb x P^2 buffers
+  for (int pass = 0; pass < 2; ++pass) {
+    const int64_t n = pass == 0 ? o : v;
+    const double* Yr = pass == 0 ? Yo : Yv;
+    const double *G1 = pass == 0 ? Gv : Go, *G2 = pass == 0 ? Go : Gv;
+    double* D = pass == 0 ? Doo : Dvv;
+    const double f = pass == 0 ? 2.0 : -2.0;
+    for (int64_t r0 = 0; r0 < n; r0 += ch) {
+      const int64_t nr = std::min(ch, n - r0);
+      Gemm g = batched(mk(P, P, P, T, P, true, G1, P, false, ctx->Ccat, P), nr, 0, 0, PP);
+      g.kscaleA = Yr + r0 * P; g.ksA = 1; g.sksA = P;
+      g.hmul = G2; g.ldh = P;
+      RCHK(gemm(ctx, g));
+      RCHK(gemm(ctx, batched(mk(P, P, P, ctx->Ccat, P, false, T, P, false, ctx->Dcat, P), nr, PP, 0, PP)));
+      MISC(k_colsum_rowscaled(nr, P, P, G1, ctx->Dcat, PP, ctx->Dt, nr, s));
+      RCHK(gemm(ctx, mk(nr, n, P, ctx->Dt, nr, true, Yr, P, true, D + r0 * n, n, f, 1.0)));
+    }
+  }
+  return THC_OK;
+}
+
 int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t mask, double* sigma, double* sigma1) {
   if (!ctx) return THC_EINVAL;
   RCHK(need_built(ctx));

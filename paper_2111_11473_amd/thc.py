@@ -31,7 +31,7 @@ SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_term
            "thc_history_precision", "thc_history_flags",
            "thc_energy",
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan",
-           "thc_set_synthetic", "thc_synth_gamma", "thc_create_with_workspace", "thc_plan_query", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
+           "thc_set_synthetic", "thc_synth_gamma", "thc_mp2_density", "thc_create_with_workspace", "thc_plan_query", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
            "thc_last_error", "thc_destroy",
            "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
            "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
     lib.thc_plan.argtypes = [VP, C.POINTER(PlanInfo)]
     lib.thc_set_synthetic.argtypes = [VP, C.POINTER(SynthSpec)]
+    lib.thc_mp2_density.argtypes = [VP, P, P, P]
     lib.thc_create_with_workspace.argtypes = [C.POINTER(Options), VP, C.c_size_t, VP, C.POINTER(VP)]
     lib.thc_plan_query.argtypes = [C.POINTER(Options), C.c_int, C.c_uint64, C.POINTER(PlanInfo)]
     lib.thc_synth_gamma.argtypes = [VP, C.POINTER(D)]
@@ -299,6 +300,15 @@ class THC:
         Z = torch.empty((self.nP, self.nP), dtype=torch.float64, device="cuda")
         self._check(self.lib.thc_build_factors(self.ctx, None, None, None, _ptr(Z)), "thc_build_factors")
         return Z
+
+    def mp2_density(self, Z=None):
+        """(D_oo, D_vv): the MP2 one-particle density of the amplitudes of core Z (default: the
+        current state), App. II."""
+        Doo = torch.empty((self.o, self.o), dtype=torch.float64, device="cuda")
+        Dvv = torch.empty((self.v, self.v), dtype=torch.float64, device="cuda")
+        zp = _ptr(Z, self.nP ** 2, "Z") if Z is not None else None
+        self._check(self.lib.thc_mp2_density(self.ctx, zp, _ptr(Doo), _ptr(Dvv)), "thc_mp2_density")
+        return Doo, Dvv
 
     def synth_gamma(self):
         g = C.c_double(0.0)
