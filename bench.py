@@ -196,6 +196,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--no-next", action="store_true", help="skip the Alg. 4/5 and MP2-density timings")
     ap.add_argument("--converge-maxit", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (a known-traffic kernel for counter scaling)")
@@ -340,6 +341,38 @@ def main():
     results = {}
     for name in legs:
         results[name] = leg(LEG_PRECISION[name])
+
+    def next_rows():
+        """The two further paths on the same workload (FP64): Eq. 32 + 33 by Alg. 4 and 5 (O(N^5),
+        matrix products only) against Alg. 6 (the H-kernel path), and the MP2 one-particle density
+        of the guess amplitudes (App. II, O(N^4))."""
+        res = {}
+        for key, flag in (("alg6_eq32_33_ms", thc.FLAG_QUARTIC), ("alg45_eq32_33_ms", thc.FLAG_QUINTIC)):
+            ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, flags=flag | flags)
+            ctx.set_synthetic(cfg.seed, cfg.decay, cfg.coupling)
+            Z0 = ctx.build_synthetic()
+            ctx.residual(Z0, None, mask=thc.TERM_EQ32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                ctx.residual(Z0, None, mask=thc.TERM_EQ32)
+            torch.cuda.synchronize()
+            res[key] = 1e3 * (time.perf_counter() - t0) / 2
+            if flag == thc.FLAG_QUARTIC:
+                ctx.mp2_density()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    ctx.mp2_density()
+                torch.cuda.synchronize()
+                res["mp2_density_ms"] = 1e3 * (time.perf_counter() - t0) / 5
+            ctx.close()
+            torch.cuda.synchronize()
+        res["cost_model_choice"] = "alg45" if thc.plan_query(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, 270e9, synthetic=True)["quintic"] else "alg6"
+        print(f"bench: next rows {res}", file=sys.stderr, flush=True)
+        return res
+
+    extra = next_rows() if (not large and "fp64" in legs and not args.no_next) else None
     head = legs[0]
     dt, prof, gf64, gfm, conv_head, plan_head = results[head]
     h_ms, h_n = prof["h_kernel"]
@@ -437,6 +470,7 @@ def main():
         "plan": plan_head,
         "converge": conv64 if head == "fp64" else results[head][4],
         "cpu_baseline": cpu,
+        "next_rows": extra,
     }
     for name in legs:
         if name != "fp64":

@@ -1,7 +1,11 @@
 """End-to-end learned guess on small systems of the learned set (o in [6, 9]): training rows from
 converged solves, training on the GPU, BF16 inference, and held-out solves from the predicted
 start.  The converged energy must not depend on the start, the fallback must keep every solve
-converged, and the iteration counts of both starts are reported."""
+converged, and the learned start must not cost iterations on average.  What it gains is small:
+about 3% of the iterations on such systems and none at o >= 30, because Jacobi + DIIS from the MP2
+guess already converges in 4-6 iterations there and the specified guess family (a diagonal
+rescaling of the MP2 guess and a diagonal denominator shift) cannot shorten that -- even the exact
+least-squares targets of each held-out system save no iteration."""
 import numpy as np
 import pytest
 
@@ -35,4 +39,25 @@ def test_learned_guess_end_to_end(ready):
         plain.append(r["plain_iterations"])
         learn.append(r["learned_iterations"])
     say("mean iterations plain", np.mean(plain), "learned", np.mean(learn))
-    assert np.mean(learn) <= np.mean(plain) + 1.0
+    assert np.mean(learn) <= np.mean(plain)
+    assert all(lv <= pv + 1 for lv, pv in zip(learn, plain))
+
+
+class _FarPrediction:
+    """A network stand-in whose prediction is far off: start 100 times the MP2 guess, denominators
+    shifted by 99 per index (steps a hundred times too short)."""
+
+    def infer(self, phi):
+        import torch
+        return torch.full((phi.shape[0], 2), 99.0, dtype=torch.float32, device=phi.device)
+
+
+def test_learned_fallback_when_the_prediction_fails(ready):
+    """A failing prediction ends at the plain solution: the learned attempt either does not
+    converge within its iteration limit (then the solve falls back to the plain guess) or the
+    solver detects the divergence and restarts from the MP2 guess with plain denominators."""
+    from paper_2111_11473_amd import learned
+    r = learned.solve_pair(_FarPrediction(), learned.system_config(201, 6, 9), maxit=25)
+    print("[gpu-learned] far prediction", r, flush=True)
+    assert r["plain_converged"] and r["learned_converged"]
+    assert r["energy_difference"] < 1e-8
