@@ -17,3 +17,4 @@ from .thc import (khatri_rao, amplitudes, project, eri_fit, eri_thc_dense, metri
                   pseudo_canonical, mp2_amplitudes, mp2_guess, thc_residual, solve, SolveResult,
                   driver_projection, energy_from_factors)
 from .density import mp2_density
+from . import cpals

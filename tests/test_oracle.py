@@ -308,3 +308,57 @@ def test_mp2_density_of_a_single_pair_amplitude():
     Xo, Xv, Z = np.array([[1.0]]), np.array([[1.0]]), np.array([[0.3]])
     Doo, Dvv = oracle.mp2_density(Xo, Xv, Z)
     assert abs(Doo[0, 0] + 2 * 0.09) < 1e-15 and abs(Dvv[0, 0] - 2 * 0.09) < 1e-15
+
+
+def _cp_problem(seed, I=5, J=6, K=7, n=3, noise=0.0):
+    rng = np.random.default_rng(seed)
+    X, Y, Z = rng.standard_normal((I, n)), rng.standard_normal((J, n)), rng.standard_normal((K, n))
+    A = np.einsum("in,jn,kn->ijk", X, Y, Z) + noise * rng.standard_normal((I, J, K))
+    return A, X, Y, Z, rng
+
+
+def test_cp_als_update_solves_its_normal_equations():
+    """Each weighted ALS update is the exact minimizer for its factor: the gradient of the weighted
+    objective with respect to that factor (by central differences of the objective itself, not the
+    normal equations) vanishes, and the objective never increases along a sweep."""
+    from oracle import cpals
+    A, _, _, _, rng = _cp_problem(1, noise=0.3)
+    X, Y, Z = (rng.standard_normal(s) for s in ((5, 3), (6, 3), (7, 3)))
+    w1, w2, w3 = 0.5 + rng.random(5), 0.5 + rng.random(6), rng.standard_normal(7)  # eps may be negative
+    prev = cpals.objective(A, X, Y, Z, w1, w2, w3)
+    for mode in range(3):
+        F = cpals.update(A, X, Y, Z, w1, w2, w3, mode)
+        X, Y, Z = (F, Y, Z) if mode == 0 else (X, F, Z) if mode == 1 else (X, Y, F)
+        cur = cpals.objective(A, X, Y, Z, w1, w2, w3)
+        assert cur <= prev * (1 + 1e-12)
+        prev = cur
+        h = 1e-5
+        for (r, c) in ((0, 0), (2, 1), (F.shape[0] - 1, 2)):
+            Fp, Fm = F.copy(), F.copy()
+            Fp[r, c] += h
+            Fm[r, c] -= h
+            args = lambda G: (G, Y, Z) if mode == 0 else (X, G, Z) if mode == 1 else (X, Y, G)
+            g = (cpals.objective(A, *args(Fp), w1, w2, w3) - cpals.objective(A, *args(Fm), w1, w2, w3)) / (2 * h)
+            assert abs(g) < 1e-6 * max(1.0, cur)
+
+
+def test_cp_als_recovers_a_planted_low_rank_array():
+    """A rank-3 array is reproduced to rounding from a perturbed start, with and without weights
+    (a planted exact factorization has zero weighted residual for any weights)."""
+    from oracle import cpals
+    A, X0, Y0, Z0, rng = _cp_problem(2)
+    for w3 in (None, np.linspace(-2.0, 3.0, 7)):
+        X, Y, Z = (F + 0.05 * rng.standard_normal(F.shape) for F in (X0, Y0, Z0))
+        _, _, _, obj = cpals.cp_als(A, X, Y, Z, 200, w3=w3)
+        assert obj[-1] < 1e-24 * np.sum(A ** 2)
+        assert all(b <= a * (1 + 1e-10) for a, b in zip(obj, obj[1:]))
+
+
+def test_cp_als_unit_weights_equal_no_weights():
+    from oracle import cpals
+    A, _, _, _, rng = _cp_problem(3, noise=0.2)
+    X, Y, Z = (rng.standard_normal(s) for s in ((5, 3), (6, 3), (7, 3)))
+    a = cpals.cp_als(A, X, Y, Z, 3)
+    b = cpals.cp_als(A, X, Y, Z, 3, np.ones(5), np.ones(6), np.ones(7))
+    for u, v in zip(a[:3], b[:3]):
+        assert np.abs(u - v).max() < 1e-12 * np.abs(u).max()
