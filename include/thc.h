@@ -172,6 +172,27 @@ int thc_residual_terms(thc_ctx* ctx, const double* Z, const double* t1, uint32_t
  * the MP2 guess); Doo [o][o], Dvv [v][v] device outputs.  FP64. */
 int thc_mp2_density(thc_ctx* ctx, const double* Z, double* Doo, double* Dvv);
 
+/* Weighted CANDECOMP/PARAFAC of a 3-index array by alternating least squares (paper Sec. II.c
+ * Eq. 15-16 and Sec. II.d Eq. 21: the factorization that turns the projectors and the Cholesky
+ * vectors into THC form; Appendix I Eq. 43-46: its row-wise normal equations, solved by conjugate
+ * gradients preconditioned with diag(S)).  Minimizes
+ *     O = sum_ijk (w1_i w2_j w3_k)^2 (A_ijk - sum_n X_in Y_jn Z_kn)^2
+ * by `sweeps` sweeps, each the update of X, then Y, then Z with the other two fixed.
+ *   A          device [I][J][K]
+ *   w1, w2, w3 device [I], [J], [K] weights (NULL: all ones)
+ *   X, Y, Z    device [I][n], [J][n], [K][n]; in: the start, out: the factors after the sweeps
+ *   cg_tol     each column's residual norm relative to its right-hand side ends the CG solve
+ *   cg_maxit   iteration limit of one CG solve
+ *   objective  HOST [sweeps + 1] out: O before the first sweep and after each (NULL: not computed)
+ *   cg_iters   HOST out: the most CG iterations one solve took (may be NULL)
+ * Work on `stream`; synchronizes it before returning.  Allocates and frees its own workspace
+ * (about (IJ + 3 max(I, J, K) + 7 n) n doubles): it is a set-up step, not part of an iteration.
+ * Returns THC_ENOTCONV if some solve reached cg_maxit (the factors are then still updated with the
+ * last iterate), THC_EINVAL for bad sizes, THC_ENOMEM, THC_EDEVICE. */
+int thc_cp_als(const double* A, int64_t I, int64_t J, int64_t K, int64_t n, const double* w1, const double* w2,
+               const double* w3, double* X, double* Y, double* Z, int sweeps, double cg_tol, int cg_maxit,
+               double* objective, int* cg_iters, void* stream);
+
 /* Jacobi + DIIS iterations from the current state (the paper gives no update rule: this is the
  * standard denominator-weighted update in the working basis where the Fock part of the projected
  * residual is exactly diagonal, Sec. II's equations; Pulay DIIS): each iteration evaluates the

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libthc.so")
-SOURCES = ["gemm_f64.hip", "kernels_misc.hip", "kernels_h.hip", "kernels_exch.hip", "mlp.hip", "synth_gen.hip", "thc_api.cpp", "hostla.cpp"]
+SOURCES = ["gemm_f64.hip", "kernels_misc.hip", "kernels_h.hip", "kernels_exch.hip", "mlp.hip", "synth_gen.hip", "cpals.hip", "thc_api.cpp", "hostla.cpp"]
 ARCH = os.environ.get("THC_OFFLOAD_ARCH", "gfx950")
 
 

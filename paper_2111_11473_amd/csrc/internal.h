@@ -105,6 +105,21 @@ hipError_t synth_normalize(int64_t n, const double* y, const double* dot, double
 // Orbital energies (host): o occupied then v virtual, each sorted ascending.
 void synth_energies(uint64_t seed, int64_t o, int64_t v, double* eps);
 
+// Weighted CP-ALS pieces (cpals.hip).
+hipError_t cp_weighted_rows(int64_t m, int64_t n, const double* w, const double* X, double* out, hipStream_t s);
+hipError_t cp_mttkrp_reduce(int64_t I, int64_t J, int64_t n, const double* T, const double* V, bool over_j,
+                            double* out, hipStream_t s);
+int64_t cp_wnorm2_parts(int64_t I, int64_t J, int64_t K);
+hipError_t cp_wnorm2(int64_t I, int64_t J, int64_t K, const double* A, const double* w1, const double* w2,
+                     const double* w3, double* part, hipStream_t s);
+hipError_t cp_col_dot(int64_t n, int64_t m, const double* A, const double* B, double* out, hipStream_t s);
+hipError_t cp_cg_step(int64_t n, int64_t m, const double* rz, const double* pq, const double* P, const double* Q,
+                      double* U, double* R, hipStream_t s);
+hipError_t cp_cg_precond(int64_t n, int64_t m, const double* d, const double* R, double* Zr, hipStream_t s);
+hipError_t cp_cg_dir(int64_t n, int64_t m, const double* rz_new, const double* rz_old, const double* Zr, double* P,
+                     hipStream_t s);
+hipError_t cp_diag(int64_t n, const double* S, double* d, hipStream_t s);
+
 // Fused exchange contraction Gt^X = xo (z o (xo^T Rx^X))^T for X = 0..nx-1 (kernels_exch.hip);
 // xo [o][Q], z [Q][Q], Rx and Gt [nx][o][Q].  Supported for 1 <= o <= 200.  f32: operands rounded
 // to FP32, FP32 MFMA and accumulation (the mixed-precision path); else FP64 throughout.

@@ -2005,6 +2005,152 @@ int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops
   return THC_OK;
 }
 
+// ------------------------------------------------------------------------------------------
+// Weighted CP-ALS (Sec. II.c-d, Eq. 15-16, 21; Appendix I, Eq. 43-46).
+namespace {
+struct CpWork {
+  std::vector<void*> mem;
+  ~CpWork() { for (void* q : mem) (void)hipFree(q); }
+  double* get(size_t n) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(double)) != hipSuccess) return nullptr;
+    mem.push_back(q);
+    return (double*)q;
+  }
+};
+
+#define CPCHK(expr)                        \
+  do {                                     \
+    if ((expr) != hipSuccess) return THC_EDEVICE; \
+  } while (0)
+
+// Solves S U = B ([n][m], column c one right-hand side) by conjugate gradients preconditioned with
+// diag(S), from the U given; stops when every column's residual is below tol times its right-hand
+// side.  *iters: iterations taken; returns THC_ENOTCONV if maxit is reached first.
+int cp_pcg(int64_t n, int64_t m, const double* S, const double* B, double* U, double tol, int maxit, double* d,
+           double* R, double* Zr, double* P, double* Q, double* rz, double* rz2, double* pq, double* rr, double* bb,
+           int* iters, hipStream_t s) {
+  CPCHK(cp_diag(n, S, d, s));
+  CPCHK(hipMemcpyAsync(R, B, n * m * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CPCHK(gemm_f64(mk(n, m, n, S, n, false, U, m, false, R, m, -1.0, 1.0), s));
+  CPCHK(cp_cg_precond(n, m, d, R, Zr, s));
+  CPCHK(hipMemcpyAsync(P, Zr, n * m * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CPCHK(cp_col_dot(n, m, R, Zr, rz, s));
+  CPCHK(cp_col_dot(n, m, B, B, bb, s));
+  std::vector<double> hr(m), hb(m);
+  CPCHK(hipMemcpyAsync(hb.data(), bb, m * sizeof(double), hipMemcpyDeviceToHost, s));
+  CPCHK(hipStreamSynchronize(s));
+  for (int it = 1; it <= maxit; ++it) {
+    CPCHK(gemm_f64(mk(n, m, n, S, n, false, P, m, false, Q, m), s));
+    CPCHK(cp_col_dot(n, m, P, Q, pq, s));
+    CPCHK(cp_cg_step(n, m, rz, pq, P, Q, U, R, s));
+    CPCHK(cp_col_dot(n, m, R, R, rr, s));
+    CPCHK(hipMemcpyAsync(hr.data(), rr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    CPCHK(hipStreamSynchronize(s));
+    bool done = true;
+    for (int64_t c = 0; c < m && done; ++c) done = std::sqrt(hr[c]) <= tol * std::sqrt(hb[c]);
+    *iters = it;
+    if (done) return THC_OK;
+    CPCHK(cp_cg_precond(n, m, d, R, Zr, s));
+    CPCHK(cp_col_dot(n, m, R, Zr, rz2, s));
+    CPCHK(cp_cg_dir(n, m, rz2, rz, Zr, P, s));
+    std::swap(rz, rz2);
+  }
+  return THC_ENOTCONV;
+}
+}  // namespace
+
+int thc_cp_als(const double* A, int64_t I, int64_t J, int64_t K, int64_t n, const double* w1, const double* w2,
+               const double* w3, double* X, double* Y, double* Z, int sweeps, double cg_tol, int cg_maxit,
+               double* objective, int* cg_iters, void* stream) {
+  if (!A || !X || !Y || !Z || I < 1 || J < 1 || K < 1 || n < 1 || sweeps < 0 || !(cg_tol > 0.0) || cg_maxit < 1)
+    return THC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t m = std::max(std::max(I, J), K), IJ = I * J;
+  CpWork w;
+  double *TB = w.get(IJ * n), *Xw = w.get(I * n), *Yw = w.get(J * n), *Zw = w.get(K * n), *Zwt = w.get(K * n);
+  double *G1 = w.get(n * n), *G2 = w.get(n * n), *G3 = w.get(n * n), *S = w.get(n * n), *H = w.get(n * n);
+  double *Bt = w.get(n * m), *U = w.get(n * m), *R = w.get(n * m), *Zr = w.get(n * m), *P = w.get(n * m),
+         *Qb = w.get(n * m);
+  double *d = w.get(n), *rz = w.get(m), *rz2 = w.get(m), *pq = w.get(m), *rr = w.get(m), *bb = w.get(m);
+  const int64_t nparts = cp_wnorm2_parts(I, J, K);
+  double *parts = w.get(nparts), *sc = w.get(4);
+  if (!TB || !Xw || !Yw || !Zw || !Zwt || !G1 || !G2 || !G3 || !S || !H || !Bt || !U || !R || !Zr || !P || !Qb || !d ||
+      !rz || !rz2 || !pq || !rr || !bb || !parts || !sc)
+    return THC_ENOMEM;
+  int worst = 0, rc_all = THC_OK;
+  // one factor update: S U = B with U = F^T warm-started from F, then F = U^T
+  auto solve = [&](double* F, int64_t rows) -> int {
+    CPCHK(k_copy2d(1, n, rows, F, n, 0, U, rows, 0, true, s));
+    int its = 0;
+    const int rc = cp_pcg(n, rows, S, Bt, U, cg_tol, cg_maxit, d, R, Zr, P, Qb, rz, rz2, pq, rr, bb, &its, s);
+    worst = std::max(worst, its);
+    if (rc == THC_ENOTCONV) rc_all = THC_ENOTCONV;
+    else if (rc != THC_OK) return rc;
+    CPCHK(k_copy2d(1, rows, n, U, rows, 0, F, n, 0, true, s));
+    return THC_OK;
+  };
+  // objective = |A_w|^2 - 2 sum_kn w3_k^2 Z_kn R_Z[k][n] + sum (G1 o G2 o G3), all with the current factors
+  double anorm = 0.0;
+  {
+    CPCHK(cp_wnorm2(I, J, K, A, w1, w2, w3, parts, s));
+    CPCHK(k_sum(nparts, parts, sc, s));
+    CPCHK(hipMemcpyAsync(&anorm, sc, sizeof(double), hipMemcpyDeviceToHost, s));
+    CPCHK(hipStreamSynchronize(s));
+  }
+  auto grams = [&]() -> int {  // Xw, Yw, Zw and G1 = X^T Xw, G2 = Y^T Yw, G3 = Z^T Zw
+    CPCHK(cp_weighted_rows(I, n, w1, X, Xw, s));
+    CPCHK(cp_weighted_rows(J, n, w2, Y, Yw, s));
+    CPCHK(cp_weighted_rows(K, n, w3, Z, Zw, s));
+    CPCHK(gemm_f64(mk(n, n, I, X, n, true, Xw, n, false, G1, n), s));
+    CPCHK(gemm_f64(mk(n, n, J, Y, n, true, Yw, n, false, G2, n), s));
+    CPCHK(gemm_f64(mk(n, n, K, Z, n, true, Zw, n, false, G3, n), s));
+    return THC_OK;
+  };
+  auto record = [&](int idx) -> int {  // objective of the current factors into objective[idx]
+    if (!objective) return THC_OK;
+    RCHK(grams());
+    // R_Z^T = KR(Xw, Yw)^T A  ([n][K])
+    CPCHK(k_kr(I, J, n, Xw, Yw, TB, s));
+    CPCHK(gemm_f64(mk(n, K, IJ, TB, n, true, A, K, false, Bt, K), s));
+    CPCHK(k_copy2d(1, n, K, Zw, n, 0, Zwt, K, 0, true, s));
+    CPCHK(k_dot(n * K, Zwt, Bt, sc, s));
+    CPCHK(k_hadamard(n * n, G1, G2, 1.0, 0.0, H, s));
+    CPCHK(k_dot(n * n, H, G3, sc + 1, s));
+    double h[2];
+    CPCHK(hipMemcpyAsync(h, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CPCHK(hipStreamSynchronize(s));
+    objective[idx] = anorm - 2.0 * h[0] + h[1];
+    return THC_OK;
+  };
+  RCHK(record(0));
+  for (int sw = 0; sw < sweeps; ++sw) {
+    RCHK(grams());
+    // X: T = A (W3^2 Z) (IJ x n); B_X^T[n][i] = sum_j w2_j^2 Y_jn T[i][j][n]; S = G2 o G3
+    CPCHK(gemm_f64(mk(IJ, n, K, A, K, false, Zw, n, false, TB, n), s));
+    CPCHK(cp_mttkrp_reduce(I, J, n, TB, Yw, true, Bt, s));
+    CPCHK(k_hadamard(n * n, G2, G3, 1.0, 0.0, S, s));
+    RCHK(solve(X, I));
+    // Y: B_Y^T[n][j] = sum_i w1_i^2 X_in T[i][j][n] (T unchanged: it depends on Z only); S = G1 o G3
+    CPCHK(cp_weighted_rows(I, n, w1, X, Xw, s));
+    CPCHK(gemm_f64(mk(n, n, I, X, n, true, Xw, n, false, G1, n), s));
+    CPCHK(cp_mttkrp_reduce(I, J, n, TB, Xw, false, Bt, s));
+    CPCHK(k_hadamard(n * n, G1, G3, 1.0, 0.0, S, s));
+    RCHK(solve(Y, J));
+    // Z: B_Z^T = KR(W1^2 X, W2^2 Y)^T A ([n][K]); S = G1 o G2
+    CPCHK(cp_weighted_rows(J, n, w2, Y, Yw, s));
+    CPCHK(gemm_f64(mk(n, n, J, Y, n, true, Yw, n, false, G2, n), s));
+    CPCHK(k_kr(I, J, n, Xw, Yw, TB, s));
+    CPCHK(gemm_f64(mk(n, K, IJ, TB, n, true, A, K, false, Bt, K), s));
+    CPCHK(k_hadamard(n * n, G1, G2, 1.0, 0.0, S, s));
+    RCHK(solve(Z, K));
+    RCHK(record(sw + 1));
+  }
+  CPCHK(hipStreamSynchronize(s));
+  if (cg_iters) *cg_iters = worst;
+  return rc_all;
+}
+
 int thc_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
               int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC,
               int64_t batch, void* stream) {

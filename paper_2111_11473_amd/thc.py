@@ -31,7 +31,7 @@ SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_term
            "thc_history_precision", "thc_history_flags",
            "thc_energy",
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan",
-           "thc_set_synthetic", "thc_synth_gamma", "thc_mp2_density", "thc_create_with_workspace", "thc_plan_query", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
+           "thc_set_synthetic", "thc_synth_gamma", "thc_mp2_density", "thc_create_with_workspace", "thc_plan_query", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_cp_als", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
            "thc_last_error", "thc_destroy",
            "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
            "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
@@ -106,6 +106,8 @@ def load(path: str = LIB_PATH):
     lib.thc_synth_normals.argtypes = [C.c_uint64, C.c_int32, C.c_uint64, I64, D, P, VP]
     lib.thc_synth_cholesky.argtypes = [C.c_uint64, I64, I64, I64, D, D, P, VP]
     lib.thc_synth_energies.argtypes = [C.c_uint64, I64, I64, C.POINTER(D)]
+    lib.thc_cp_als.argtypes = [P, I64, I64, I64, I64, P, P, P, P, P, P, C.c_int, D, C.c_int, C.POINTER(D),
+                               C.POINTER(C.c_int), VP]
     lib.thc_profile.argtypes = [VP, C.c_int]
     lib.thc_profile_get.argtypes = [VP, C.c_char_p, C.POINTER(D), C.POINTER(I64)]
     lib.thc_profile_flops.argtypes = [VP, C.POINTER(D), C.POINTER(D), C.POINTER(D)]
@@ -235,6 +237,25 @@ def synth_energies(seed, o, v):
     if rc != 0:
         raise ThcError(rc, "thc_synth_energies failed")
     return list(e)
+
+
+def cp_als(A, X, Y, Z, sweeps, w1=None, w2=None, w3=None, cg_tol=1e-12, cg_maxit=500, objective=True):
+    """Weighted CP-ALS on the GPU: `sweeps` sweeps (X, Y, Z in turn) updating the float64 CUDA
+    tensors X [I, n], Y [J, n], Z [K, n] in place for the array A [I, J, K] and optional weights.
+    Returns (objective list of sweeps + 1 values or None, most CG iterations of one solve)."""
+    lib = load()
+    I, J, K = A.shape
+    n = X.shape[1]
+    if X.shape != (I, n) or Y.shape != (J, n) or Z.shape != (K, n):
+        raise ValueError("factor shapes do not match A")
+    obj = (C.c_double * (sweeps + 1))() if objective else None
+    its = C.c_int(0)
+    rc = lib.thc_cp_als(_ptr(A, name="A"), I, J, K, n, _ptr(w1, I, "w1"), _ptr(w2, J, "w2"), _ptr(w3, K, "w3"),
+                        _ptr(X, name="X"), _ptr(Y, name="Y"), _ptr(Z, name="Z"), int(sweeps), float(cg_tol),
+                        int(cg_maxit), obj, C.byref(its), _stream())
+    if rc != 0:
+        raise ThcError(rc, "thc_cp_als failed")
+    return (list(obj) if objective else None), its.value
 
 
 class THC:
