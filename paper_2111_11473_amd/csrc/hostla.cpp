@@ -4,7 +4,9 @@
 //  * the symmetric eigenproblem of the (N_P x N_P) Fock operator in the orthonormalized
 //    amplitude basis: Householder reduction to tridiagonal form followed by the implicit
 //    QL iteration with Wilkinson-type shifts, with the orthogonal transformations
-//    accumulated (Golub & Van Loan, Matrix Computations, Sec. 8.3).
+//    accumulated (Golub & Van Loan, Matrix Computations, Sec. 8.3).  The QL step sequence (shift
+//    from the leading 2 x 2 block, rotations chased up the tridiagonal) is the published tql2
+//    procedure of Bowdler, Martin, Reinsch & Wilkinson (Numer. Math. 11, 293-306, 1968).
 // All matrices are row-major.
 #include <algorithm>
 #include <cmath>
