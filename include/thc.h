@@ -75,7 +75,25 @@ typedef struct thc_options {
                              * half-transformed, exchange outputs); 0 = automatic */
   int64_t q_pairs;          /* Alg. 4 and 5: pairs per batched product; 0 = automatic */
   int64_t q_jchunk;         /* Alg. 4 and 5: occupied j per chunk of the dense residual; 0 = automatic */
+  uint64_t split_mask;      /* precision 1 only: THC_CHAIN_* bits of the contraction chains whose GEMMs
+                               run as compensated split-BF16 products instead of FP32 MFMA
+                               (precision 2 is every chain); 0 = none */
+  int32_t guess;            /* starting point of the first thc_iterate after thc_build_factors:
+                               0 = the MP2 guess; 1 = the learned guess of the network given to
+                               thc_set_guess_network (falls back to the MP2 guess with the plain
+                               denominators if the iteration diverges from it, or has not cut the
+                               residual norm tenfold after three iterations) */
+  int32_t reserved;         /* 0 */
 } thc_options;
+
+/* Contraction chains of the residual (bits of thc_options.split_mask). */
+#define THC_CHAIN_FUSED (1u << 0)    /* fused pass over Cholesky vectors: Alg. 1 panels and core, Alg. 2, 3, 8 */
+#define THC_CHAIN_ASSEMBLY (1u << 1) /* assembly of the symmetric terms: Alg. 2, 3, 9 */
+#define THC_CHAIN_ALG45 (1u << 2)    /* Alg. 4 and 5 (when the cost model takes them) */
+#define THC_CHAIN_ALG6 (1u << 3)     /* the matrix products of Alg. 6 around the H accumulation */
+#define THC_CHAIN_ALG7 (1u << 4)     /* Alg. 7 (its fused exchange kernel stays FP32 MFMA) */
+#define THC_CHAIN_SINGLES (1u << 5)  /* singles residual: Alg. 8 and 10 */
+#define THC_CHAIN_ALL 0x3Fu
 
 /* Alg. 7 exchange contraction: by default fused on chip (no Q x Q intermediate) when o <= 200;
  * this flag forces the two-GEMM form with its x_chunk-blocked Q x Q intermediate instead. */
@@ -202,7 +220,8 @@ int thc_cp_als(const double* A, int64_t I, int64_t J, int64_t K, int64_t n, cons
  * error overlap matrix has a condition number above 1e12).  Divergence -- a residual norm or
  * energy that is not finite, a norm above 10 times the smallest of the call, or three rises in a
  * row -- restarts once from the MP2 guess with the plain denominators and an empty DIIS subspace
- * (within the same maxit).  *iters (host, may be NULL): residual evaluations; *rnorm (host, may be
+ * (within the same maxit); so does a learned start (thc_options.guess = 1) whose residual norm has
+ * not fallen tenfold after three iterations.  *iters (host, may be NULL): residual evaluations; *rnorm (host, may be
  * NULL): last residual norm.  Returns THC_ENOTCONV when maxit is reached, THC_EDIVERGED when the
  * restarted iteration diverges too. */
 int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm);
@@ -213,6 +232,7 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm);
 #define THC_ITER_MIXED 1
 #define THC_ITER_RESTARTED 2
 #define THC_ITER_DIIS_DROPPED 4
+#define THC_ITER_LEARNED 8  /* the iteration descends from the learned start (thc_options.guess = 1) */
 int thc_history_flags(const thc_ctx* ctx, int max, int* flags, int* count);
 
 /* Per-iteration record of the last thc_iterate call (host arrays of length >= max, any may be
@@ -328,6 +348,15 @@ int thc_guess_targets(thc_ctx* ctx, const double* Th0, const double* Tstar, cons
  * vector [W1 (n_in x width, row-major), b1, W2 (width x width), b2, W3 (width x n_out), b3],
  * Glorot-uniform initial weights from `seed`, zero biases.  Bound to `stream` (hipStream_t). */
 typedef struct thc_mlp thc_mlp;
+
+/* The network whose prediction starts the first thc_iterate after thc_build_factors when
+ * thc_options.guess = 1 (features of the MP2 guess as thc_guess_features, BF16 inference as
+ * thc_mlp_infer, applied as thc_guess_apply, all on the context's stream; a divergence or stall
+ * from that start restarts from the MP2 guess with the plain denominators, see thc_iterate).  The network must have 10
+ * inputs, width 256 and 1 or 2 outputs; it is not owned and must outlive its use.  NULL detaches
+ * it.  thc_iterate returns THC_ESTATE if guess = 1 and no network is attached, THC_EINVAL if
+ * nP^2 + o v < 6 nP (too small to stage the features). */
+int thc_set_guess_network(thc_ctx* ctx, thc_mlp* net);
 int thc_mlp_create(int64_t n_in, int64_t width, int64_t n_out, uint64_t seed, void* stream, thc_mlp** out);
 /* Host arrays: mu_in, sd_in [n_in]; mu_out, sd_out [n_out]; scales must be positive. */
 int thc_mlp_set_norm(thc_mlp* net, const float* mu_in, const float* sd_in, const float* mu_out, const float* sd_out);

@@ -125,6 +125,9 @@ struct thc_ctx {
   bool prof = false;
   std::vector<ProfRec> recs;
   const char* section = nullptr;  // residual section, for per-section GEMM records ("gemm@<section>")
+  int chain = -1;                 // THC_CHAIN_* bit index of the section (split_mask), -1 outside
+  thc_mlp* guess_net = nullptr;   // network of the learned start (thc_options.guess = 1), not owned
+  bool guess_pending = false;     // the state is the MP2 guess thc_build_factors left
   double gemm_flops = 0.0, gemm_flops32 = 0.0, gemm_flops16 = 0.0;  // MFMA GEMM flops (2 K per distinct output,
                                                                      // FP64 / FP32 / split-BF16) while profiling
   std::vector<hipEvent_t> pool;
@@ -232,7 +235,8 @@ int gemm(thc_ctx* ctx, const Gemm& g0) {
   g.ws = ctx->gws;
   g.ws_len = ctx->gws ? GEMM_WS : 0;
   if (ctx->mixed && !g.keep64) {
-    if (ctx->opt.precision == 2) g.bf16x3 = true; else g.f32 = true;
+    const bool split = ctx->opt.precision == 2 || (ctx->chain >= 0 && ((ctx->opt.split_mask >> ctx->chain) & 1u));
+    if (split) g.bf16x3 = true; else g.f32 = true;
   }
   if (ctx->prof && g.K > 0) {
     // a symmetric product (upper) needs only the N (N + 1) / 2 distinct outputs
@@ -258,7 +262,10 @@ Gemm k64(Gemm g) {
 struct MixedScope {
   thc_ctx* ctx;
   MixedScope(thc_ctx* c) : ctx(c) { ctx->mixed = ctx->want_mixed; }
-  ~MixedScope() { ctx->mixed = false; }
+  ~MixedScope() {
+    ctx->mixed = false;
+    ctx->chain = -1;
+  }
 };
 
 // Plain (batched) GEMM helper.
@@ -820,6 +827,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
 
   // ---------------- fused pass over blocks of Cholesky vectors (Alg. 1, 2, 3, 8) -------------
   ctx->section = "gemm@fused";
+  ctx->chain = 0;
   for (int64_t A0 = 0; A0 < nL; A0 += ctx->nb) {
     const int64_t nb = std::min(ctx->nb, nL - A0);
     const double* Loo = ctx->Loo + A0 * o * o;
@@ -924,6 +932,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
 
   // ---------------- Fock matrix, T1-transformed (Eq. 24-27) -----------------------------------
   ctx->section = "gemm@fock";
+  ctx->chain = -1;
   ctx->mixed = false;  // the T1-transformed Fock matrix stays FP64
   double* Foo = ctx->Fh;
   double* Fov = ctx->Fh + o * o;
@@ -959,6 +968,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
 
   // ---------------- assembly of the symmetric terms (Alg. 2, 3, 9) ----------------------------
   ctx->section = "gemm@assembly";
+  ctx->chain = 1;
   ctx->mixed = ctx->want_mixed;
   RCHK(gemm(ctx, mk(P, P, P, ctx->S, P, false, T, P, false, ctx->ST, P)));
   if (mask & THC_TERM_EQ28) MISC(k_batch_sum_sym(ctx->KS, P, ctx->sig28, 1.0, ctx->sig, s));
@@ -994,10 +1004,12 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   // ---------------- Alg. 4 + 5: the same terms in O(N^5), all matrix products ---------------
   if ((mask & THC_TERM_EQ32) && ctx->quintic) {
     ctx->section = "gemm@alg45";
+    ctx->chain = 2;
     RCHK(quintic_terms(ctx, T));
   }
   // ---------------- Alg. 6: quartic T2^2 ladder + exchange (Eq. 32 + 33) ----------------------
   ctx->section = "gemm@alg6";
+  ctx->chain = 3;
   if ((mask & THC_TERM_EQ32) && !ctx->quintic) {
     const int64_t Xb = ctx->Xb, nX = Xb / 64;
     for (int64_t X0 = 0; X0 < P; X0 += Xb) {
@@ -1058,6 +1070,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
   // Rows X of the P x o x Q intermediates are taken in chunks of X7 (the paper's split of Alg. 7
   // over X); S^X and R^X are held for every X (the products with them need every row).
   ctx->section = "gemm@alg7";
+  ctx->chain = 4;
   if (mask & THC_TERM_EQ35) {
     const int64_t X7 = ctx->X7;
     // S^X_ia = - sum_YZ y_i^Y y_a^Z Gv[X][Y] Go[X][Z] T[Y][Z]  (Alg. 7)
@@ -1115,6 +1128,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
 
   // ---------------- singles residual (Alg. 8, Alg. 10) ---------------------------------------
   ctx->section = "gemm@singles";
+  ctx->chain = 5;
   if (sres && (mask & THC_TERM_EQ38)) {
     // s38 was accumulated with undressed Lvv/Loo; the dressing adds -xi_oo^T t1 + t1 xi_vv^T
     MISC(k_axpby(ov, 1.0, ctx->s38, 1.0, ctx->sig1, s));
@@ -1141,6 +1155,7 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
     }
   }
   ctx->section = nullptr;
+  ctx->chain = -1;
   return THC_OK;
 }
 
@@ -1329,7 +1344,7 @@ bool options_valid(const thc_options* opt) {
       (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV | THC_FLAG_PROGRESS | THC_FLAG_QUINTIC |
                       THC_FLAG_QUARTIC)) != 0 || ((opt->flags & THC_FLAG_QUINTIC) && (opt->flags & THC_FLAG_QUARTIC)) || opt->a_block < 0 ||
       opt->i_chunk < 0 || opt->x_block < 0 || opt->x_chunk < 0 || opt->x7_chunk < 0 || opt->q_pairs < 0 ||
-      opt->q_jchunk < 0)
+      opt->q_jchunk < 0 || (opt->split_mask & ~(uint64_t)THC_CHAIN_ALL) != 0 || opt->guess < 0 || opt->guess > 1)
     return false;
   // the metric S = B^T B (nP x nP) and the ERI-grid Gram (nQ x nQ) have rank at most o v
   return opt->nP <= opt->o * opt->v && opt->nQ <= opt->o * opt->v;
@@ -1649,6 +1664,7 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
   RCHK(clear_region6(ctx));
   HIPCHK(hipStreamSynchronize(s));
   ctx->built = true;
+  ctx->guess_pending = true;
   ctx->diis_n = 0;
   ctx->diis_head = 0;
   return THC_OK;
@@ -1753,6 +1769,7 @@ int thc_set_state(thc_ctx* ctx, const double* Z, const double* t1) {
   RCHK(basis_from_raw(ctx, ctx->Zs, ctx->Th));
   ctx->diis_n = 0;
   ctx->diis_head = 0;
+  ctx->guess_pending = false;
   return THC_OK;
 }
 
@@ -1783,6 +1800,40 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   double rn_min = -1.0, rn_last = -1.0;
   int rises = 0;
   bool fell_back = false, restarted = false;
+  // learned start (thc_options.guess = 1): the network's prediction from the features of the MP2
+  // guess scales the start and shifts the denominators; the divergence restart above is its fallback
+  bool learned = false;
+  int learned_its = 0;
+  double rn_learned = 0.0;
+  if (ctx->opt.guess == 1 && ctx->guess_pending) {
+    thc_mlp* net = ctx->guess_net;
+    if (!net) {
+      ctx->err = "thc_options.guess = 1 needs a network (thc_set_guess_network)";
+      return THC_ESTATE;
+    }
+    if (12 * P * (int64_t)sizeof(float) > len * (int64_t)sizeof(double)) {
+      ctx->err = "the learned start needs nP^2 + o v >= 6 nP";
+      return THC_EINVAL;
+    }
+    float* phi = (float*)ctx->dT;  // the Jacobi step's buffer is free before the first residual
+    float* pred = phi + P * 10;
+    MISC(k_dot(PP, ctx->Th, ctx->Th, ctx->scal + 40, s));
+    MISC(k_guess_features(P, ctx->o, ctx->v, ctx->Th, ctx->e, ctx->eps, ctx->scal + 40, phi, s));
+    if (hipStreamSynchronize(net->stream) != hipSuccess) return THC_EDEVICE;  // its parameters are final
+    if (!net->packed) {
+      HIPCHK(mlp_pack_bf16(net->n_in, net->n_out, net->p, net->wb, net->bb, s));
+      net->packed = true;
+    }
+    HIPCHK(mlp_infer_bf16(P, net->n_in, net->n_out, phi, net->mu_in, net->sd_in, net->wb, net->bb, net->mu_out,
+                          net->sd_out, pred, s));
+    MISC(k_guess_apply(P, pred, net->n_out, ctx->Th, ctx->delta, s));
+    ctx->has_shift = net->n_out > 1;
+    RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
+    ctx->diis_n = 0;
+    ctx->diis_head = 0;
+    learned = true;
+  }
+  ctx->guess_pending = false;
   for (int it = 1; it <= maxit; ++it) {
     ctx->want_mixed = mixed_phase;
     RCHK(residual_impl(ctx, ctx->Zs, singles ? ctx->t1 : nullptr, THC_TERM_ALL));
@@ -1798,10 +1849,15 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
     ctx->hist_r.push_back(rn);
     ctx->hist_t.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
     ctx->hist_mixed.push_back(mixed_phase ? 1 : 0);
-    ctx->hist_flags.push_back((mixed_phase ? THC_ITER_MIXED : 0) | (restarted ? THC_ITER_RESTARTED : 0));
+    ctx->hist_flags.push_back((mixed_phase ? THC_ITER_MIXED : 0) | (restarted ? THC_ITER_RESTARTED : 0) |
+                              (learned ? THC_ITER_LEARNED : 0));
     restarted = false;
     if (finite && rn_last >= 0.0) rises = rn > rn_last ? rises + 1 : 0;
-    const bool diverged = !finite || (rn_min > 0.0 && rn > 10.0 * rn_min) || rises >= 3;
+    // a learned start that has not cut the residual norm tenfold in three iterations is abandoned
+    // like a divergent one (from the MP2 guess the norm falls by orders of magnitude in that time)
+    if (learned && ++learned_its == 1) rn_learned = rn;
+    const bool stalled = learned && learned_its == 3 && !(rn < 0.1 * rn_learned);
+    const bool diverged = !finite || (rn_min > 0.0 && rn > 10.0 * rn_min) || rises >= 3 || stalled;
     if (finite) {
       rn_last = rn;
       rn_min = rn_min < 0.0 ? rn : std::min(rn_min, rn);
@@ -1813,6 +1869,7 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
         return THC_EDIVERGED;
       }
       fell_back = restarted = true;
+      learned = false;
       HIPCHK(hipMemcpyAsync(ctx->Th, ctx->Th0, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
       RCHK(zero(ctx, ctx->t1, ov));
       RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
@@ -2175,6 +2232,7 @@ int thc_guess_features(thc_ctx* ctx, float* phi) {
 int thc_guess_apply(thc_ctx* ctx, const float* pred, int64_t ld) {
   if (!ctx || !pred || ld < 1) return THC_EINVAL;
   RCHK(need_built(ctx));
+  ctx->guess_pending = false;
   MISC(k_guess_apply(ctx->P, pred, ld, ctx->Th, ctx->delta, ctx->stream));
   ctx->has_shift = ld > 1;
   RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
@@ -2186,6 +2244,7 @@ int thc_guess_apply(thc_ctx* ctx, const float* pred, int64_t ld) {
 int thc_set_shift(thc_ctx* ctx, const double* delta) {
   if (!ctx) return THC_EINVAL;
   RCHK(need_built(ctx));
+  ctx->guess_pending = false;
   if (delta) HIPCHK(hipMemcpyAsync(ctx->delta, delta, ctx->P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   ctx->has_shift = delta != nullptr;
   ctx->diis_n = 0;
@@ -2207,6 +2266,16 @@ int thc_working(thc_ctx* ctx, double* Th, double* sigma_hat) {
   return THC_OK;
 }
 
+
+int thc_set_guess_network(thc_ctx* ctx, thc_mlp* net) {
+  if (!ctx) return THC_EINVAL;
+  if (net && (net->n_in != 10 || net->w != 256 || net->n_out < 1 || net->n_out > 2 || !net->wb)) {
+    ctx->err = "the guess network needs 10 inputs, width 256 and 1 or 2 outputs";
+    return THC_EINVAL;
+  }
+  ctx->guess_net = net;
+  return THC_OK;
+}
 
 int thc_guess_targets(thc_ctx* ctx, const double* Th0, const double* Tstar, const double* sig0, double* c,
                       double* delta) {

@@ -37,13 +37,23 @@ def system_config(s: int, o_min: int, o_max: int, coupling: float | None = None)
     return synth.Config(f"learn{s}", o, 9 * o, 30 * o, 20 * o, 50 * o, 30.0, 2000 + s, coupling=c)
 
 
-def _context(thc, cfg, singles, tol_energy):
-    import torch
-    s = synth.make_system(cfg)
-    ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, singles=singles, diis_max=8, tol_energy=tol_energy)
-    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-    Z0 = ctx.build_factors(d(s["L"]), d(s["eps"]), d(s["Xo"]), d(s["Xv"]), d(s["xo"]), d(s["xv"]))
-    return ctx, Z0
+def _context(thc, cfg, singles, tol_energy, precision=0):
+    """A context for system cfg with its inputs generated on the GPU by the library (the same
+    values as synth.make_system) and the factors built; returns (context, MP2-guess core Z0)."""
+    ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, singles=singles, diis_max=8, tol_energy=tol_energy,
+                  precision=precision)
+    ctx.set_synthetic(cfg.seed, cfg.decay, cfg.coupling, 0.0 if cfg.gamma is None else cfg.gamma)
+    return ctx, ctx.build_synthetic()
+
+
+def _to_target(energies, seconds, e_ref, thresh=1e-6):
+    """(iterations, seconds) until the energy is within thresh of e_ref and stays there."""
+    k = len(energies)
+    while k > 0 and abs(energies[k - 1] - e_ref) < thresh:
+        k -= 1
+    if k == len(energies):
+        return None, None
+    return k + 1, seconds[k]
 
 
 def generate(systems, o_min, o_max, tol=1e-7, tol_energy=1e-8, maxit=100, singles=True, log=print):
@@ -97,37 +107,104 @@ def train(X, T, epochs=60, batch=4096, lr=2e-3, seed=1, log=print):
     return net, first, losses
 
 
-def solve_pair(net, cfg, tol=1e-7, tol_energy=1e-8, maxit=100, singles=True):
-    """Iterations of the plain solve and of the learned-guess solve (with fallback)."""
+def _learned_solve(ctx, Z0, net, tol, maxit):
+    """Solve from the network's prediction with fallback to the plain guess; returns
+    (iterations, converged, fallback, energies, seconds) with the fallback's record appended."""
+    from . import thc
+    ctx.set_state(Z0)
+    ctx.set_shift(None)
+    ctx.guess_apply(net.infer(ctx.guess_features()))
+    fallback = False
+    try:
+        it, _, ok = ctx.iterate(tol=tol, maxit=maxit, raise_on_notconv=False)
+        e, _, t = ctx.history()
+    except thc.ThcError:  # the prediction diverged past the solver's own restart
+        it, ok, e, t = maxit, False, [], []
+    if not ok:
+        fallback = True
+        t_used = t[-1] if t else 0.0
+        ctx.set_state(Z0)
+        ctx.set_shift(None)
+        it2, _, ok = ctx.iterate(tol=tol, maxit=maxit, raise_on_notconv=False)
+        e2, _, t2 = ctx.history()
+        it, e, t = it + it2, e + e2, t + [t_used + x for x in t2]
+    return it, ok, fallback, e, t
+
+
+def solve_pair(net, cfg, tol=1e-7, tol_energy=1e-8, maxit=100, singles=True, mixed=False):
+    """Iterations of the plain FP64 solve and of the learned-guess FP64 solve (with fallback);
+    with mixed=True also the learned-guess solve in mixed precision.  Each solve also reports the
+    iterations and seconds (iteration time only, set-up excluded) until its energy is within
+    1e-6 Eh of the plain solve's converged energy and stays there."""
     from . import thc
     ctx, Z0 = _context(thc, cfg, singles, tol_energy)
     it_p, _, ok_p = ctx.iterate(tol=tol, maxit=maxit, raise_on_notconv=False)
     e_p = ctx.energy()
-    ctx.set_state(Z0)
-    ctx.set_shift(None)
-    phi = ctx.guess_features()
-    pred = net.infer(phi)
-    ctx.guess_apply(pred)
-    fallback = False
-    try:
-        it_l, _, ok_l = ctx.iterate(tol=tol, maxit=maxit, raise_on_notconv=False)
-    except thc.ThcError:  # non-finite residual: the prediction diverged
-        it_l, ok_l = maxit, False
-    if not ok_l:
-        fallback = True
-        ctx.set_state(Z0)
-        ctx.set_shift(None)
-        it2, _, ok_l = ctx.iterate(tol=tol, maxit=maxit, raise_on_notconv=False)
-        it_l += it2
+    hp, _, tp = ctx.history()
+    it_l, ok_l, fallback, hl, tl = _learned_solve(ctx, Z0, net, tol, maxit)
     e_l = ctx.energy()
     ctx.close()
-    return {"o": cfg.o, "nP": cfg.nP, "plain_iterations": it_p, "learned_iterations": it_l, "plain_converged": ok_p,
-            "learned_converged": ok_l, "fallback": fallback, "energy_plain": e_p, "energy_learned": e_l,
-            "energy_difference": abs(e_l - e_p)}
+    r = {"o": cfg.o, "nP": cfg.nP, "plain_iterations": it_p, "learned_iterations": it_l, "plain_converged": ok_p,
+         "learned_converged": ok_l, "fallback": fallback, "energy_plain": e_p, "energy_learned": e_l,
+         "energy_difference": abs(e_l - e_p), "plain_seconds": tp[-1] if tp else None,
+         "learned_seconds": tl[-1] if tl else None}
+    r["plain_to_1e-6"] = _to_target(hp, tp, e_p)
+    r["learned_to_1e-6"] = _to_target(hl, tl, e_p)
+    if mixed:
+        ctx, Z0 = _context(thc, cfg, singles, tol_energy, precision=1)
+        it_m, ok_m, fb_m, hm, tm = _learned_solve(ctx, Z0, net, tol, maxit)
+        e_m = ctx.energy()
+        ctx.close()
+        r.update({"mixed_learned_iterations": it_m, "mixed_learned_converged": ok_m, "mixed_fallback": fb_m,
+                  "energy_mixed_learned": e_m, "mixed_energy_difference": abs(e_m - e_p),
+                  "mixed_learned_seconds": tm[-1] if tm else None, "mixed_learned_to_1e-6": _to_target(hm, tm, e_p)})
+    return r
+
+
+def save_net(net, path):
+    mu_in, sd_in, mu_out, sd_out = net.get_norm()
+    np.savez(path, params=net.get_params().cpu().numpy(), mu_in=mu_in, sd_in=sd_in, mu_out=mu_out, sd_out=sd_out,
+             shape=np.array([net.n_in, net.width, net.n_out]))
+
+
+def load_net(path):
+    import torch
+    from . import thc
+    d = np.load(path)
+    n_in, width, n_out = (int(x) for x in d["shape"])
+    net = thc.MLP(n_in, width, n_out)
+    net.set_norm(d["mu_in"], d["sd_in"], d["mu_out"], d["sd_out"])
+    net.set_params(torch.from_numpy(np.ascontiguousarray(d["params"], dtype=np.float32)).to("cuda"))
+    return net
+
+
+def _summary(res, args, extra):
+    ip = np.array([r["plain_iterations"] for r in res], dtype=float)
+    il = np.array([r["learned_iterations"] for r in res], dtype=float)
+    out = {"systems_heldout": len(res), "o_range": [args.o_min, args.o_max], "coupling": args.coupling,
+           "tol": args.tol, **extra,
+           "mean_iterations_plain": float(ip.mean()), "mean_iterations_learned": float(il.mean()),
+           "median_iterations_plain": float(np.median(ip)), "median_iterations_learned": float(np.median(il)),
+           "mean_reduction": float(1.0 - il.mean() / ip.mean()), "fallbacks": int(sum(r["fallback"] for r in res)),
+           "max_energy_difference": float(max(r["energy_difference"] for r in res))}
+    for key in ("plain_to_1e-6", "learned_to_1e-6", "mixed_learned_to_1e-6"):
+        v = [r[key] for r in res if key in r]
+        if v and all(x[0] is not None for x in v):
+            out[key + "_mean_iterations"] = float(np.mean([x[0] for x in v]))
+            out[key + "_total_seconds"] = float(np.sum([x[1] for x in v]))
+    if any("mixed_learned_iterations" in r for r in res):
+        im = np.array([r["mixed_learned_iterations"] for r in res], dtype=float)
+        out["mean_iterations_mixed_learned"] = float(im.mean())
+        out["mixed_fallbacks"] = int(sum(r["mixed_fallback"] for r in res))
+        out["max_mixed_energy_difference"] = float(max(r["mixed_energy_difference"] for r in res))
+    return out
 
 
 def main():
-    ap = argparse.ArgumentParser()
+    ap = argparse.ArgumentParser(description="Learned-guess experiment. Without --gen/--eval: generate, train "
+                                 "and evaluate in one run. --gen A B --save rows.npz: training rows of systems "
+                                 "A..B-1 only. --rows f1.npz,... --save-net net.npz: train on saved rows. "
+                                 "--net net.npz --eval A B: evaluate held-out systems A..B-1.")
     ap.add_argument("--train", type=int, default=200)
     ap.add_argument("--heldout", type=int, default=56)
     ap.add_argument("--o-min", type=int, default=30)
@@ -135,34 +212,60 @@ def main():
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--coupling", type=float, default=0.2)
     ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--mixed", action="store_true", help="also solve each held-out system in mixed precision "
+                    "from the learned start")
+    ap.add_argument("--gen", type=int, nargs=2, default=None)
+    ap.add_argument("--rows", default=None)
+    ap.add_argument("--net", default=None)
+    ap.add_argument("--save-net", default=None)
+    ap.add_argument("--eval", type=int, nargs=2, default=None)
+    ap.add_argument("--save", default=None)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     global COUPLING
     COUPLING = args.coupling
     log = lambda *a: print(*a, flush=True)
     t0 = time.perf_counter()
-    log(f"generating training data from {args.train} systems (o in [{args.o_min}, {args.o_max}])")
-    X, T, info = generate(range(args.train), args.o_min, args.o_max, tol=args.tol, log=log)
-    log(f"{X.shape[0]} rows; training")
-    net, first, losses = train(X, T, epochs=args.epochs, log=log)
-    log(f"evaluating on {args.heldout} held-out systems")
+    if args.gen:  # saved after every system, so a run cut short keeps what it made
+        Xs, Ts, infos = [], [], []
+        for sidx in range(*args.gen):
+            X, T, info = generate([sidx], args.o_min, args.o_max, tol=args.tol, log=log)
+            Xs.append(X), Ts.append(T), infos.extend(info)
+            np.savez(args.save, X=np.concatenate(Xs), T=np.concatenate(Ts), info=json.dumps(infos))
+        log(f"{sum(x.shape[0] for x in Xs)} rows from systems {args.gen[0]}..{args.gen[1] - 1} "
+            f"in {time.perf_counter() - t0:.0f} s")
+        return
+    extra = {}
+    if args.net:
+        net = load_net(args.net)
+    else:
+        if args.rows:
+            parts = [np.load(f) for f in args.rows.split(",")]
+            X = np.concatenate([d["X"] for d in parts])
+            T = np.concatenate([d["T"] for d in parts])
+            info = sum((json.loads(str(d["info"])) for d in parts), [])
+        else:
+            log(f"generating training data from {args.train} systems (o in [{args.o_min}, {args.o_max}])")
+            X, T, info = generate(range(args.train), args.o_min, args.o_max, tol=args.tol, log=log)
+        log(f"{X.shape[0]} rows from {len(info)} systems; training")
+        net, first, losses = train(X, T, epochs=args.epochs, log=log)
+        extra = {"systems_train": len(info), "rows": int(X.shape[0]), "loss_initial": first,
+                 "loss_final": losses[-1]}
+        if args.save_net:
+            save_net(net, args.save_net)
+    heldout = range(*args.eval) if args.eval else range(200, 200 + args.heldout)
+    log(f"evaluating on held-out systems {heldout.start}..{heldout.stop - 1}")
     res = []
-    for s in range(200, 200 + args.heldout):
-        r = solve_pair(net, system_config(s, args.o_min, args.o_max), tol=args.tol)
+    for s in heldout:
+        r = solve_pair(net, system_config(s, args.o_min, args.o_max), tol=args.tol, mixed=args.mixed)
         r["system"] = s
         res.append(r)
         log(f"  system {s}: o={r['o']} plain {r['plain_iterations']} learned {r['learned_iterations']}"
-            f"{' (fallback)' if r['fallback'] else ''} |dE| {r['energy_difference']:.1e}")
-    ip = np.array([r["plain_iterations"] for r in res], dtype=float)
-    il = np.array([r["learned_iterations"] for r in res], dtype=float)
-    report = {"systems_train": args.train, "systems_heldout": args.heldout, "o_range": [args.o_min, args.o_max],
-              "coupling": args.coupling, "tol": args.tol,
-              "rows": int(X.shape[0]), "loss_initial": first, "loss_final": losses[-1],
-              "mean_iterations_plain": float(ip.mean()), "mean_iterations_learned": float(il.mean()),
-              "median_iterations_plain": float(np.median(ip)), "median_iterations_learned": float(np.median(il)),
-              "mean_reduction": float(1.0 - il.mean() / ip.mean()), "fallbacks": int(sum(r["fallback"] for r in res)),
-              "max_energy_difference": float(max(r["energy_difference"] for r in res)),
-              "seconds": time.perf_counter() - t0, "heldout": res}
+            f"{' (fallback)' if r['fallback'] else ''} |dE| {r['energy_difference']:.1e}; to 1e-6 Eh: plain "
+            f"{r['plain_to_1e-6']} learned {r['learned_to_1e-6']}"
+            + (f" mixed+learned {r['mixed_learned_to_1e-6']} ({r['mixed_learned_iterations']} it)" if args.mixed
+               else ""))
+    report = {**_summary(res, args, extra), "seconds": time.perf_counter() - t0, "heldout": res}
     log(json.dumps({k: v for k, v in report.items() if k != "heldout"}))
     if args.out:
         with open(args.out, "w") as fh:

@@ -18,7 +18,10 @@ THC_OK, THC_EINVAL, THC_ENOMEM, THC_EDEVICE, THC_ESINGULAR, THC_ENUMERIC, THC_EN
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 ERRNAMES = {0: "THC_OK", -1: "THC_EINVAL", -2: "THC_ENOMEM", -3: "THC_EDEVICE", -4: "THC_ESINGULAR",
             -5: "THC_ENUMERIC", -6: "THC_ENOTCONV", -7: "THC_ESTATE", -8: "THC_EDIVERGED"}
-ITER_MIXED, ITER_RESTARTED, ITER_DIIS_DROPPED = 1, 2, 4
+ITER_MIXED, ITER_RESTARTED, ITER_DIIS_DROPPED, ITER_LEARNED = 1, 2, 4, 8
+# contraction chains (bits of Options.split_mask)
+CHAIN_FUSED, CHAIN_ASSEMBLY, CHAIN_ALG45, CHAIN_ALG6, CHAIN_ALG7, CHAIN_SINGLES = (1 << k for k in range(6))
+CHAIN_ALL = 0x3F
 
 TERM_EQ28, TERM_EQ29, TERM_EQ31, TERM_EQ32, TERM_EQ35, TERM_EQ41, TERM_EQ38, TERM_EQ42 = (1 << k for k in range(8))
 TERM_ALL = 0xFF
@@ -33,7 +36,7 @@ SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_term
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan",
            "thc_set_synthetic", "thc_synth_gamma", "thc_mp2_density", "thc_create_with_workspace", "thc_plan_query", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_cp_als", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
            "thc_last_error", "thc_destroy",
-           "thc_guess_features", "thc_guess_apply", "thc_set_shift", "thc_working", "thc_guess_targets",
+           "thc_guess_features", "thc_guess_apply", "thc_set_guess_network", "thc_set_shift", "thc_working", "thc_guess_targets",
            "thc_mlp_create", "thc_mlp_set_norm", "thc_mlp_fit_norm", "thc_mlp_get_norm", "thc_mlp_num_params", "thc_mlp_get_params", "thc_mlp_set_params",
            "thc_mlp_forward", "thc_mlp_forward_noalloc", "thc_mlp_loss_grad", "thc_mlp_train_step", "thc_mlp_infer", "thc_mlp_last_error",
            "thc_mlp_destroy"]
@@ -45,7 +48,7 @@ class Options(C.Structure):
                 ("singles", C.c_int32), ("diis_max", C.c_int32), ("tol_energy", C.c_double),
                 ("a_block", C.c_int64), ("i_chunk", C.c_int64), ("x_block", C.c_int64), ("x_chunk", C.c_int64),
                 ("precision", C.c_int32), ("flags", C.c_int32), ("x7_chunk", C.c_int64), ("q_pairs", C.c_int64),
-                ("q_jchunk", C.c_int64)]
+                ("q_jchunk", C.c_int64), ("split_mask", C.c_uint64), ("guess", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -118,6 +121,7 @@ def load(path: str = LIB_PATH):
     lib.thc_destroy.restype = None
     lib.thc_guess_features.argtypes = [VP, P]
     lib.thc_guess_apply.argtypes = [VP, P, I64]
+    lib.thc_set_guess_network.argtypes = [VP, VP]
     lib.thc_set_shift.argtypes = [VP, P]
     lib.thc_working.argtypes = [VP, P, P]
     lib.thc_guess_targets.argtypes = [VP, P, P, P, P, P]
@@ -191,9 +195,9 @@ def dgemm(A, B, C_out, transA=False, transB=False, alpha=1.0, beta=0.0):
 
 
 def make_options(o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0, x_block=0,
-                 x_chunk=0, flags=0, precision=0, x7_chunk=0, q_pairs=0, q_jchunk=0):
+                 x_chunk=0, flags=0, precision=0, x7_chunk=0, q_pairs=0, q_jchunk=0, split_mask=0, guess=0):
     return Options(o, v, nL, nP, nQ, int(singles), diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
-                   precision, flags, x7_chunk, q_pairs, q_jchunk)
+                   precision, flags, x7_chunk, q_pairs, q_jchunk, split_mask, guess, 0)
 
 
 def plan_query(o, v, nL, nP, nQ, budget_bytes, synthetic=False, **kw):
@@ -262,14 +266,15 @@ class THC:
     """One THC-CCSD problem on the current GPU (all tensors float64, CUDA, contiguous)."""
 
     def __init__(self, o, v, nL, nP, nQ, singles=True, diis_max=8, tol_energy=1e-8, a_block=0, i_chunk=0,
-                 x_block=0, x_chunk=0, flags=0, precision=0, x7_chunk=0, q_pairs=0, q_jchunk=0, workspace=None):
+                 x_block=0, x_chunk=0, flags=0, precision=0, x7_chunk=0, q_pairs=0, q_jchunk=0, split_mask=0,
+                 guess=0, workspace=None):
         """workspace: None (the library allocates its working memory), or a CUDA tensor whose
         memory the library uses instead (thc_create_with_workspace; kept referenced here)."""
         self.lib = load()
         self.o, self.v, self.nL, self.nP, self.nQ = o, v, nL, nP, nQ
         self.singles = bool(singles)
         opt = make_options(o, v, nL, nP, nQ, singles, diis_max, tol_energy, a_block, i_chunk, x_block, x_chunk,
-                           flags, precision, x7_chunk, q_pairs, q_jchunk)
+                           flags, precision, x7_chunk, q_pairs, q_jchunk, split_mask, guess)
         h = C.c_void_p()
         self.workspace = workspace
         if workspace is None:
@@ -423,6 +428,13 @@ class THC:
         if pred.dim() != 2 or pred.shape[0] != self.nP:
             raise ValueError("pred must be nP x k")
         self._check(self.lib.thc_guess_apply(self.ctx, _fptr(pred, name="pred"), pred.shape[1]), "thc_guess_apply")
+
+    def set_guess_network(self, net=None):
+        """The network (MLP) whose prediction starts the first iterate() after build_factors when the
+        context was made with guess=1; None detaches it.  The network must outlive its use."""
+        self._guess_net = net
+        self._check(self.lib.thc_set_guess_network(self.ctx, net.net if net is not None else None),
+                    "thc_set_guess_network")
 
     def set_shift(self, delta=None):
         self._check(self.lib.thc_set_shift(self.ctx, _ptr(delta, self.nP, "delta")), "thc_set_shift")
