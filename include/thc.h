@@ -68,8 +68,9 @@ typedef struct thc_options {
                                exchange included) and FP32 H-kernel operands with FP64 accumulation,
                                FP64 energy, denominators, fit and DIIS, and thc_iterate finishing with
                                FP64 residuals; 2 = as 1 with the GEMM contractions as compensated
-                               split-BF16 products (hi hi + hi lo + lo hi on BF16 MFMA, FP32
-                               accumulation); the fused exchange stays FP32 MFMA */
+                               split-BF16 products (each FP32-rounded operand split exactly into
+                               three bf16 pieces, the six largest cross products on BF16 MFMA,
+                               FP32 accumulation); the fused exchange stays FP32 MFMA */
   int32_t flags;            /* THC_FLAG_* bits; 0 = defaults */
   int64_t x7_chunk;         /* amplitude ranks X per chunk of the Alg. 7 intermediates (R^X, S^X
                              * half-transformed, exchange outputs); 0 = automatic */

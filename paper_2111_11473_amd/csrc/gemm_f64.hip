@@ -286,23 +286,30 @@ __global__ __launch_bounds__(256, OCC) void dgemm_kernel(const Gemm g, const int
 }
 
 // Split-BF16 products (the compensated mode of the mixed-precision path): every operand is
-// rounded to FP32 and split into a bf16 head (its top 16 bits) and a bf16 tail (the top 16 bits
-// of the remainder), x = hi + lo + O(2^-16 |x|), and each product is hi hi + hi lo + lo hi on
-// v_mfma_f32_16x16x16bf16_1k with FP32 accumulation (the lo lo term, O(2^-16) relative, is
-// dropped).  A thread loads packets of 4 consecutive k of one row, scales them, splits them and
-// stores the hi and lo packets (8 bytes each) to LDS, where a lane's MFMA fragment (row lr,
-// k = 4 lk .. 4 lk + 3) is one packet.  One 16-k slab is one MFMA k-step; tiles, double
+// rounded to FP32 and split into three bf16 pieces by truncation -- hi (its top 16 bits), mid (the
+// top 16 bits of the remainder) and lo (what is left, at most 8 significant bits, so exact):
+// x = hi + mid + lo exactly.  Each product is the six terms down to second order in the pieces,
+// mid mid + hi lo + lo hi + hi mid + mid hi + hi hi (smallest first), on
+// v_mfma_f32_16x16x16bf16_1k with FP32 accumulation; the dropped terms (mid lo, lo mid, lo lo)
+// are O(2^-24) relative, the FP32 product's own rounding.  A thread loads packets of 4
+// consecutive k of one row, scales them, splits them and stores the three packets (8 bytes each)
+// to LDS, where a lane's MFMA fragment (row lr, k = 4 lk .. 4 lk + 3) is one packet.  One 16-k slab is one MFMA k-step; tiles, double
 // buffering, the XCD-aware order and the epilogue are those of the FP64/FP32 kernel.
 typedef short bf4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 
-// hi / lo bf16 pairs of two FP32 values, packed two to a dword (element 0 in the low half)
-__device__ inline void split_pair(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+// hi / mid / lo bf16 pieces of two FP32 values, each piece packed two to a dword (element 0 in
+// the low half).  Both subtractions are exact: each removes the leading bits of its operand.
+__device__ inline void split_pair(float x0, float x1, uint32_t& hi, uint32_t& mi, uint32_t& lo) {
   const uint32_t h0 = __builtin_bit_cast(uint32_t, x0) & 0xFFFF0000u;
   const uint32_t h1 = __builtin_bit_cast(uint32_t, x1) & 0xFFFF0000u;
   const float r0 = x0 - __builtin_bit_cast(float, h0), r1 = x1 - __builtin_bit_cast(float, h1);
+  const uint32_t m0 = __builtin_bit_cast(uint32_t, r0) & 0xFFFF0000u;
+  const uint32_t m1 = __builtin_bit_cast(uint32_t, r1) & 0xFFFF0000u;
+  const float q0 = r0 - __builtin_bit_cast(float, m0), q1 = r1 - __builtin_bit_cast(float, m1);
   hi = (h0 >> 16) | h1;
-  lo = (__builtin_bit_cast(uint32_t, r0) >> 16) | (__builtin_bit_cast(uint32_t, r1) & 0xFFFF0000u);
+  mi = (m0 >> 16) | m1;
+  lo = (__builtin_bit_cast(uint32_t, q0) >> 16) | (__builtin_bit_cast(uint32_t, q1) & 0xFFFF0000u);
 }
 
 template <int BM, int BN, bool TA, bool TB>
@@ -310,10 +317,10 @@ __global__ __launch_bounds__(256, 2) void bgemm_kernel(const Gemm g, const int64
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TI = WM / 16, TJ = WN / 16;
   constexpr int QA = BM / 64, QB = BN / 64;  // packets (4 k of one row) per thread and slab
-  // LDS: [buffer][hi, lo][k / 4][row] packets; rows padded so that the four k / 4 planes a wave
-  // reads at once sit 32 banks apart
-  __shared__ u2 As[2][2][4][BM + 16];
-  __shared__ u2 Bs[2][2][4][BN + 16];
+  // LDS: [buffer][hi, mid, lo][k / 4][row] packets; rows padded so that the four k / 4 planes a
+  // wave reads at once sit 32 banks apart
+  __shared__ u2 As[2][3][4][BM + 16];
+  __shared__ u2 Bs[2][3][4][BN + 16];
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -377,21 +384,21 @@ __global__ __launch_bounds__(256, 2) void bgemm_kernel(const Gemm g, const int64
   auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
-      uint32_t h0, l0, h1, l1;
-      split_pair((float)(ra[q][0] * rsa[q][0]), (float)(ra[q][1] * rsa[q][1]), h0, l0);
-      split_pair((float)(ra[q][2] * rsa[q][2]), (float)(ra[q][3] * rsa[q][3]), h1, l1);
-      const u2 hi = u2{h0, h1}, lo = u2{l0, l1};
-      As[buf][0][aq[q]][am[q]] = hi;
-      As[buf][1][aq[q]][am[q]] = lo;
+      uint32_t h0, m0, l0, h1, m1, l1;
+      split_pair((float)(ra[q][0] * rsa[q][0]), (float)(ra[q][1] * rsa[q][1]), h0, m0, l0);
+      split_pair((float)(ra[q][2] * rsa[q][2]), (float)(ra[q][3] * rsa[q][3]), h1, m1, l1);
+      As[buf][0][aq[q]][am[q]] = u2{h0, h1};
+      As[buf][1][aq[q]][am[q]] = u2{m0, m1};
+      As[buf][2][aq[q]][am[q]] = u2{l0, l1};
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-      uint32_t h0, l0, h1, l1;
-      split_pair((float)(rb[q][0] * rsb[q][0]), (float)(rb[q][1] * rsb[q][1]), h0, l0);
-      split_pair((float)(rb[q][2] * rsb[q][2]), (float)(rb[q][3] * rsb[q][3]), h1, l1);
-      const u2 hi = u2{h0, h1}, lo = u2{l0, l1};
-      Bs[buf][0][bq[q]][bn[q]] = hi;
-      Bs[buf][1][bq[q]][bn[q]] = lo;
+      uint32_t h0, m0, l0, h1, m1, l1;
+      split_pair((float)(rb[q][0] * rsb[q][0]), (float)(rb[q][1] * rsb[q][1]), h0, m0, l0);
+      split_pair((float)(rb[q][2] * rsb[q][2]), (float)(rb[q][3] * rsb[q][3]), h1, m1, l1);
+      Bs[buf][0][bq[q]][bn[q]] = u2{h0, h1};
+      Bs[buf][1][bq[q]][bn[q]] = u2{m0, m1};
+      Bs[buf][2][bq[q]][bn[q]] = u2{l0, l1};
     }
   };
 
@@ -403,23 +410,28 @@ __global__ __launch_bounds__(256, 2) void bgemm_kernel(const Gemm g, const int64
 
   const int lr = lane & 15, lk = lane >> 4;
   auto compute = [&](int buf) {
-    bf4 ah[TI], al[TI], bh[TJ], bl[TJ];
+    bf4 ah[TI], am_[TI], al[TI], bh[TJ], bm[TJ], bl[TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
       ah[i] = __builtin_bit_cast(bf4, As[buf][0][lk][wm * WM + i * 16 + lr]);
-      al[i] = __builtin_bit_cast(bf4, As[buf][1][lk][wm * WM + i * 16 + lr]);
+      am_[i] = __builtin_bit_cast(bf4, As[buf][1][lk][wm * WM + i * 16 + lr]);
+      al[i] = __builtin_bit_cast(bf4, As[buf][2][lk][wm * WM + i * 16 + lr]);
     }
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
       bh[j] = __builtin_bit_cast(bf4, Bs[buf][0][lk][wn * WN + j * 16 + lr]);
-      bl[j] = __builtin_bit_cast(bf4, Bs[buf][1][lk][wn * WN + j * 16 + lr]);
+      bm[j] = __builtin_bit_cast(bf4, Bs[buf][1][lk][wn * WN + j * 16 + lr]);
+      bl[j] = __builtin_bit_cast(bf4, Bs[buf][2][lk][wn * WN + j * 16 + lr]);
     }
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
       for (int j = 0; j < TJ; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am_[i], bm[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bm[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am_[i], bh[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
   };

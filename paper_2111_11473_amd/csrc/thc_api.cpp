@@ -447,18 +447,15 @@ std::vector<BufSpec> persistent_list(thc_ctx* ctx) {
   };
 }
 
-// Alg. 6 region for an H block of Xb ranks and grid-point chunks of Ic points (FP32 copies of
-// E, F in the mixed-precision path).
-std::vector<BufSpec> region6_list(thc_ctx* ctx, double** e32, double** f32) {
+// Alg. 6 region for an H block of Xb ranks and grid-point chunks of Ic points.  The mixed path's
+// FP32 E, F live in the first half of the FP64 E, F buffers: a residual uses one precision or the
+// other, and each writes every element (padding included) that its H-kernel reads.
+std::vector<BufSpec> region6_list(thc_ctx* ctx) {
   const int64_t o = ctx->o, v = ctx->v, P = ctx->P, Pp = ctx->Pp, ov = ctx->ov, Xb = ctx->Xb, Ic = ctx->Ic;
   std::vector<BufSpec> l = {
       {&ctx->C6, (size_t)(o * Xb * Pp)}, {&ctx->D6, (size_t)(v * Xb * Pp)}, {&ctx->Ec, (size_t)(Ic * Xb * Pp)},
       {&ctx->Fc, (size_t)(Ic * Xb * Pp)}, {&ctx->Gc, (size_t)(Ic * Pp * Pp)}, {&ctx->GYc, (size_t)(Ic * o * P)},
       {&ctx->Hb, (size_t)(Xb * Pp * Pp)}, {&ctx->R1, (size_t)(Xb * Pp * o)}, {&ctx->I6, (size_t)(Xb * ov)}};
-  if (ctx->opt.precision >= 1) {
-    l.push_back({e32, (size_t)((Ic * Xb * Pp + 1) / 2)});
-    l.push_back({f32, (size_t)((Ic * Xb * Pp + 1) / 2)});
-  }
   return l;
 }
 
@@ -598,7 +595,7 @@ int choose_plan(thc_ctx* ctx, double budget, int64_t slots) {
   // H block and grid-point chunk
   auto fixed6 = [&](int64_t Xb) { return 8.0 * (double)Xb * ((double)Pp * (o + v + Pp + o) + (double)ov); };
   auto per_i = [&](int64_t Xb) {
-    return 8.0 * (2.0 * (double)Xb * Pp + (double)Pp * Pp + (double)o * P) + (op.precision >= 1 ? 8.0 * (double)Xb * Pp : 0.0);
+    return 8.0 * (2.0 * (double)Xb * Pp + (double)Pp * Pp + (double)o * P);
   };
   if (op.x_block > 0 && (op.x_block % 64 != 0 || op.x_block > P64)) {
     ctx->err = "x_block must be a multiple of 64 and at most the rank rounded up to 64";
@@ -646,10 +643,10 @@ int plan_and_alloc(thc_ctx* ctx) {
   }
   RCHK(choose_plan(ctx, budget, ctx->hslots));
   const std::vector<uint32_t> tiles = h_tiles(ctx->Pp, ctx->Xb, ctx->hslots);
-  double *e32 = nullptr, *f32 = nullptr, *tb = nullptr;
+  double* tb = nullptr;
   std::vector<BufSpec> pers = persistent_list(ctx);
   pers.push_back({&tb, (tiles.size() + 1) / 2});
-  const std::vector<BufSpec> r6 = ctx->quintic ? quintic_list(ctx) : region6_list(ctx, &e32, &f32), a7 = alg7_list(ctx);
+  const std::vector<BufSpec> r6 = ctx->quintic ? quintic_list(ctx) : region6_list(ctx), a7 = alg7_list(ctx);
   size_t np = 0, n6 = 0, n7 = 0;
   for (const auto& a : pers) np += aligned(a.n);
   for (const auto& a : r6) n6 += aligned(a.n);
@@ -679,8 +676,8 @@ int plan_and_alloc(thc_ctx* ctx) {
   for (const auto& a : r6) { *a.p = at; at += aligned(a.n); }
   at = ctx->setup_scratch + std::max(n6, nsetup);
   for (const auto& a : a7) { *a.p = at; at += aligned(a.n); }
-  ctx->Ec32 = reinterpret_cast<float*>(e32);
-  ctx->Fc32 = reinterpret_cast<float*>(f32);
+  ctx->Ec32 = ctx->opt.precision >= 1 && !ctx->quintic ? reinterpret_cast<float*>(ctx->Ec) : nullptr;
+  ctx->Fc32 = ctx->opt.precision >= 1 && !ctx->quintic ? reinterpret_cast<float*>(ctx->Fc) : nullptr;
   ctx->htiles = reinterpret_cast<uint32_t*>(tb);
   ctx->nhtiles = (int64_t)tiles.size();
   ctx->hfilled = 0;
@@ -700,11 +697,7 @@ int clear_region6(thc_ctx* ctx) {
   RCHK(zero(ctx, ctx->Gc, Ic * Pp * Pp));
   RCHK(zero(ctx, ctx->Hb, Xb * Pp * Pp));
   RCHK(zero(ctx, ctx->Ec, Ic * Xb * Pp));
-  RCHK(zero(ctx, ctx->Fc, Ic * Xb * Pp));
-  if (ctx->Ec32) {
-    RCHK(zero(ctx, reinterpret_cast<double*>(ctx->Ec32), (Ic * Xb * Pp + 1) / 2));
-    RCHK(zero(ctx, reinterpret_cast<double*>(ctx->Fc32), (Ic * Xb * Pp + 1) / 2));
-  }
+  RCHK(zero(ctx, ctx->Fc, Ic * Xb * Pp));  // also the FP32 copies, which share this memory
   return THC_OK;
 }
 
@@ -1398,9 +1391,8 @@ int thc_plan_query(const thc_options* opt, int synthetic, uint64_t budget_bytes,
   }
   const int rc = choose_plan(&c, (double)budget_bytes, slots);
   if (rc != THC_OK) return rc;
-  double *e32 = nullptr, *f32 = nullptr;
   const double pers = list_bytes(persistent_list(&c)),
-               r6 = list_bytes(c.quintic ? quintic_list(&c) : region6_list(&c, &e32, &f32));
+               r6 = list_bytes(c.quintic ? quintic_list(&c) : region6_list(&c));
   const double a7 = list_bytes(alg7_list(&c)), setup = 8.0 * (double)setup_doubles(&c);
   int64_t tiles = 0, entries = 0;
   tile_counts(c.Pp, c.Xb, slots, &tiles, &entries);

@@ -265,6 +265,10 @@ def main():
             f"{r['plain_to_1e-6']} learned {r['learned_to_1e-6']}"
             + (f" mixed+learned {r['mixed_learned_to_1e-6']} ({r['mixed_learned_iterations']} it)" if args.mixed
                else ""))
+        if args.out:  # after every system, so a run cut short keeps what it measured
+            with open(args.out, "w") as fh:
+                json.dump({**_summary(res, args, extra), "seconds": time.perf_counter() - t0, "heldout": res}, fh,
+                          indent=1)
     report = {**_summary(res, args, extra), "seconds": time.perf_counter() - t0, "heldout": res}
     log(json.dumps({k: v for k, v in report.items() if k != "heldout"}))
     if args.out:

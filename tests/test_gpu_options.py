@@ -3,7 +3,7 @@
 * split_mask -- which contraction chains of a mixed-precision residual run as compensated
   split-BF16 products instead of FP32 MFMA.  Every chain set is bit-for-bit precision 2, none is
   bit-for-bit precision 1, a chain that does not run in this configuration (Alg. 4-5 under Alg. 6)
-  changes nothing, and one that does (Alg. 6) changes the result but stays within the split-BF16
+  changes nothing, and one that does (Alg. 6) changes the result but stays within the mixed
   bound of the FP64 residual.
 * guess = 1 -- the library starts the first iterate() from the attached network's prediction.
   With a network whose output is a constant (zero weights, the output mean set by hand) the run is
@@ -74,7 +74,7 @@ def test_split_mask_routes_chains(thc):
         r = _residual(thc, cfg, Z, t1, precision=1, split_mask=getattr(thc, name))
         err = np.abs(r - ref64).max() / scale
         _say(name, "differs from FP32:", not np.array_equal(r, p1), "error vs FP64 %.2e" % err)
-        assert err < 5e-4, (name, err)
+        assert err < 5e-5, (name, err)
         if name == "CHAIN_ALG6":
             assert not np.array_equal(r, p1)
     with pytest.raises(thc.ThcError):
