@@ -67,7 +67,9 @@ typedef struct thc_options {
   int32_t precision;        /* 0 = FP64 throughout; 1 = mixed: FP32-MFMA contractions (the fused Alg. 7
                                exchange included) and FP32 H-kernel operands with FP64 accumulation,
                                FP64 energy, denominators, fit and DIIS, and thc_iterate finishing with
-                               FP64 residuals; 2 = as 1 with the GEMM contractions as compensated
+                               FP64 residuals (mixed ones until the norm has dropped 1e4-fold, is
+                               within 10 tol, stops falling, or the last two predict the next one
+                               below tol; only an FP64 residual declares convergence); 2 = as 1 with the GEMM contractions as compensated
                                split-BF16 products (each FP32-rounded operand split exactly into
                                three bf16 pieces, the six largest cross products on BF16 MFMA,
                                FP32 accumulation); the fused exchange stays FP32 MFMA */

@@ -1879,7 +1879,12 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
     if (mixed_phase) {
       ++mixed_its;
       if (rn_first < 0.0) rn_first = rn;
-      if (rn < 1e-4 * rn_first || rn < 10.0 * tol || (mixed_its >= 3 && rn > 0.7 * rn_prev)) mixed_phase = false;
+      // FP64 from the next iteration on once the norm has dropped 1e4-fold, is within 10 tol, has
+      // stopped decreasing, or falls fast enough that the next one is predicted below tol (then
+      // that iteration can already declare convergence)
+      const bool next_below_tol = mixed_its >= 2 && rn_prev > 0.0 && rn * (rn / rn_prev) < tol;
+      if (rn < 1e-4 * rn_first || rn < 10.0 * tol || next_below_tol || (mixed_its >= 3 && rn > 0.7 * rn_prev))
+        mixed_phase = false;
       rn_prev = rn;
     } else if (have_old && rn < tol && std::fabs(E - E_old) < ctx->opt.tol_energy) {
       return THC_OK;
