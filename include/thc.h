@@ -228,6 +228,21 @@ int thc_cp_als(const double* A, int64_t I, int64_t J, int64_t K, int64_t n, cons
  * NULL): last residual norm.  Returns THC_ENOTCONV when maxit is reached, THC_EDIVERGED when the
  * restarted iteration diverges too. */
 int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm);
+/* A call continues the previous call's iteration: its first |dE| test compares with the last
+ * energy of that call, unless the state was set since (thc_build_factors, thc_set_state,
+ * thc_guess_apply, thc_set_shift, thc_load_checkpoint with a fresh checkpoint). */
+
+/* Solver checkpoint, for resuming an interrupted solve in another context (or process) built on
+ * the same inputs and options: the state T^ (working basis) and t1, the denominator shift, the DIIS
+ * subspace (vectors, errors, overlap matrix, position) and the last energy.  thc_checkpoint_bytes
+ * gives the size, (P^2 + ov)(2 diis_max + 1) + P + diis_max^2 doubles plus a 72-byte header;
+ * thc_save_checkpoint writes it to host memory, thc_load_checkpoint restores it (THC_EINVAL for
+ * a buffer that is not a checkpoint of a context with the same nP, o v and diis_max).  A resumed
+ * FP64 solve repeats the uninterrupted one's iterations exactly; a mixed-precision one restarts
+ * its precision ladder.  Host buffers; both calls synchronize the stream. */
+int thc_checkpoint_bytes(thc_ctx* ctx, size_t* bytes);
+int thc_save_checkpoint(thc_ctx* ctx, void* host, size_t bytes);
+int thc_load_checkpoint(thc_ctx* ctx, const void* host, size_t bytes);
 
 /* Per iteration of the last thc_iterate call, THC_ITER_* bits: the residual was mixed precision;
  * the iteration started from the MP2 guess after a divergence; DIIS dropped vectors to keep its

@@ -76,6 +76,8 @@ struct thc_ctx {
   double *dvec = nullptr, *derr = nullptr, *dT = nullptr, *dt1 = nullptr;
   int diis_n = 0, diis_head = 0;
   std::vector<double> diisB;  // host copy of the error inner products (diis_max^2)
+  double E_last = 0.0;        // energy of the last iteration, for the next call's |dE| test
+  bool have_last = false;     // E_last belongs to the current state's iteration history
 
   // residual outputs
   double *sig = nullptr, *sig1 = nullptr, *sigh = nullptr, *scal = nullptr;
@@ -1657,6 +1659,7 @@ int thc_build_factors(thc_ctx* ctx, const double* L, const double* eps, const do
   HIPCHK(hipStreamSynchronize(s));
   ctx->built = true;
   ctx->guess_pending = true;
+  ctx->have_last = false;
   ctx->diis_n = 0;
   ctx->diis_head = 0;
   return THC_OK;
@@ -1762,6 +1765,86 @@ int thc_set_state(thc_ctx* ctx, const double* Z, const double* t1) {
   ctx->diis_n = 0;
   ctx->diis_head = 0;
   ctx->guess_pending = false;
+  ctx->have_last = false;
+  return THC_OK;
+}
+
+// Checkpoint: a fixed header, then T^ [P][P], t1 [ov], delta [P], the DIIS vectors and errors
+// [dm][P P + ov] each and the error overlap matrix [dm][dm], as raw FP64.
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int64_t P, ov, dm, diis_n, diis_head, has_shift, have_last;
+  double E_last;
+};
+constexpr char CKPT_MAGIC[8] = {'T', 'H', 'C', 'C', 'K', 'P', 'T', '1'};
+size_t ckpt_doubles(const thc_ctx* ctx) {
+  const int64_t P = ctx->P, ov = ctx->ov, dm = ctx->opt.diis_max, len = P * P + ov;
+  return (size_t)(P * P + ov + P + 2 * dm * len + dm * dm);
+}
+}  // namespace
+
+int thc_checkpoint_bytes(thc_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  *bytes = sizeof(CkptHeader) + 8 * ckpt_doubles(ctx);
+  return THC_OK;
+}
+
+int thc_save_checkpoint(thc_ctx* ctx, void* host, size_t bytes) {
+  if (!ctx || !host) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  const int64_t P = ctx->P, ov = ctx->ov, dm = ctx->opt.diis_max, len = P * P + ov;
+  if (bytes < sizeof(CkptHeader) + 8 * ckpt_doubles(ctx)) {
+    ctx->err = "checkpoint buffer too small (thc_checkpoint_bytes)";
+    return THC_EINVAL;
+  }
+  CkptHeader h{};
+  std::memcpy(h.magic, CKPT_MAGIC, 8);
+  h.P = P; h.ov = ov; h.dm = dm; h.diis_n = ctx->diis_n; h.diis_head = ctx->diis_head;
+  h.has_shift = ctx->has_shift ? 1 : 0; h.have_last = ctx->have_last ? 1 : 0; h.E_last = ctx->E_last;
+  std::memcpy(host, &h, sizeof h);
+  double* d = reinterpret_cast<double*>(static_cast<char*>(host) + sizeof h);
+  RCHK(d2h(ctx, d, ctx->Th, P * P * sizeof(double)));
+  RCHK(d2h(ctx, d + P * P, ctx->t1, ov * sizeof(double)));
+  RCHK(d2h(ctx, d + P * P + ov, ctx->delta, P * sizeof(double)));
+  if (dm > 0) {
+    RCHK(d2h(ctx, d + P * P + ov + P, ctx->dvec, dm * len * sizeof(double)));
+    RCHK(d2h(ctx, d + P * P + ov + P + dm * len, ctx->derr, dm * len * sizeof(double)));
+    std::memcpy(d + P * P + ov + P + 2 * dm * len, ctx->diisB.data(), (size_t)(dm * dm) * sizeof(double));
+  }
+  return THC_OK;
+}
+
+int thc_load_checkpoint(thc_ctx* ctx, const void* host, size_t bytes) {
+  if (!ctx || !host) return THC_EINVAL;
+  RCHK(need_built(ctx));
+  const int64_t P = ctx->P, ov = ctx->ov, dm = ctx->opt.diis_max, len = P * P + ov;
+  CkptHeader h;
+  if (bytes < sizeof h) return THC_EINVAL;
+  std::memcpy(&h, host, sizeof h);
+  if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.P != P || h.ov != ov || h.dm != dm ||
+      bytes < sizeof h + 8 * ckpt_doubles(ctx) || h.diis_n < 0 || h.diis_n > dm || h.diis_head < 0 ||
+      (dm > 0 && h.diis_head >= dm)) {
+    ctx->err = "not a checkpoint of a context with these sizes and DIIS subspace";
+    return THC_EINVAL;
+  }
+  const double* d = reinterpret_cast<const double*>(static_cast<const char*>(host) + sizeof h);
+  RCHK(h2d(ctx, ctx->Th, d, P * P * sizeof(double)));
+  RCHK(h2d(ctx, ctx->t1, d + P * P, ov * sizeof(double)));
+  RCHK(h2d(ctx, ctx->delta, d + P * P + ov, P * sizeof(double)));
+  if (dm > 0) {
+    RCHK(h2d(ctx, ctx->dvec, d + P * P + ov + P, dm * len * sizeof(double)));
+    RCHK(h2d(ctx, ctx->derr, d + P * P + ov + P + dm * len, dm * len * sizeof(double)));
+    std::memcpy(ctx->diisB.data(), d + P * P + ov + P + 2 * dm * len, (size_t)(dm * dm) * sizeof(double));
+  }
+  RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
+  ctx->has_shift = h.has_shift != 0;
+  ctx->diis_n = (int)h.diis_n;
+  ctx->diis_head = (int)h.diis_head;
+  ctx->E_last = h.E_last;
+  ctx->have_last = h.have_last != 0;
+  ctx->guess_pending = false;
   return THC_OK;
 }
 
@@ -1772,8 +1855,10 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   const int64_t P = ctx->P, PP = P * P, ov = ctx->ov, len = PP + ov;
   const bool singles = ctx->opt.singles != 0;
   const int dm = ctx->opt.diis_max;
-  double E_old = 0.0;
-  bool have_old = false;
+  // a call continues the previous one's iteration: its first energy is compared with the last
+  // one (unless the state was set from outside since)
+  double E_old = ctx->E_last;
+  bool have_old = ctx->have_last;
   ctx->hist_e.clear();
   ctx->hist_r.clear();
   ctx->hist_t.clear();
@@ -1824,6 +1909,7 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
     ctx->diis_n = 0;
     ctx->diis_head = 0;
     learned = true;
+    have_old = ctx->have_last = false;
   }
   ctx->guess_pending = false;
   for (int it = 1; it <= maxit; ++it) {
@@ -1862,6 +1948,7 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
       }
       fell_back = restarted = true;
       learned = false;
+      ctx->have_last = false;
       HIPCHK(hipMemcpyAsync(ctx->Th, ctx->Th0, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
       RCHK(zero(ctx, ctx->t1, ov));
       RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
@@ -1887,10 +1974,14 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
         mixed_phase = false;
       rn_prev = rn;
     } else if (have_old && rn < tol && std::fabs(E - E_old) < ctx->opt.tol_energy) {
+      ctx->E_last = E;
+      ctx->have_last = true;
       return THC_OK;
     }
     E_old = E;
     have_old = true;
+    ctx->E_last = E;
+    ctx->have_last = true;
     // Jacobi step in the working basis; (dT, dt1) is the DIIS error vector
     double* dTp = ctx->dT;
     double* dt1p = ctx->dT + PP;
@@ -2230,6 +2321,7 @@ int thc_guess_apply(thc_ctx* ctx, const float* pred, int64_t ld) {
   if (!ctx || !pred || ld < 1) return THC_EINVAL;
   RCHK(need_built(ctx));
   ctx->guess_pending = false;
+  ctx->have_last = false;
   MISC(k_guess_apply(ctx->P, pred, ld, ctx->Th, ctx->delta, ctx->stream));
   ctx->has_shift = ld > 1;
   RCHK(raw_from_basis(ctx, ctx->Th, ctx->Zs));
@@ -2242,6 +2334,7 @@ int thc_set_shift(thc_ctx* ctx, const double* delta) {
   if (!ctx) return THC_EINVAL;
   RCHK(need_built(ctx));
   ctx->guess_pending = false;
+  ctx->have_last = false;
   if (delta) HIPCHK(hipMemcpyAsync(ctx->delta, delta, ctx->P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   ctx->has_shift = delta != nullptr;
   ctx->diis_n = 0;

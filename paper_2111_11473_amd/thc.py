@@ -31,7 +31,8 @@ TERMS = {"eq28": TERM_EQ28, "eq29": TERM_EQ29, "eq31": TERM_EQ31, "eq32+33": TER
 
 # exported symbols (kept in sync with include/thc.h; checked by the tests)
 SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_terms", "thc_iterate", "thc_history",
-           "thc_history_precision", "thc_history_flags",
+           "thc_history_precision", "thc_history_flags", "thc_checkpoint_bytes", "thc_save_checkpoint",
+           "thc_load_checkpoint",
            "thc_energy",
            "thc_get_state", "thc_set_state", "thc_memory_bytes", "thc_plan",
            "thc_set_synthetic", "thc_synth_gamma", "thc_mp2_density", "thc_create_with_workspace", "thc_plan_query", "thc_synth_normals", "thc_synth_cholesky", "thc_synth_energies", "thc_cp_als", "thc_profile", "thc_profile_get", "thc_profile_flops", "thc_dgemm",
@@ -97,6 +98,9 @@ def load(path: str = LIB_PATH):
     lib.thc_energy.argtypes = [VP, C.POINTER(D)]
     lib.thc_history_precision.argtypes = [VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.thc_history_flags.argtypes = [VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.thc_checkpoint_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
+    lib.thc_save_checkpoint.argtypes = [VP, VP, C.c_size_t]
+    lib.thc_load_checkpoint.argtypes = [VP, VP, C.c_size_t]
     lib.thc_get_state.argtypes = [VP, P, P]
     lib.thc_set_state.argtypes = [VP, P, P]
     lib.thc_memory_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
@@ -389,6 +393,22 @@ class THC:
         n = C.c_int(0)
         self._check(self.lib.thc_history_flags(self.ctx, max_it, f, C.byref(n)), "thc_history_flags")
         return [f[k] for k in range(min(n.value, max_it))]
+
+    def save_checkpoint(self):
+        """The solver state (T^, t1, shift, DIIS subspace, last energy) as a uint8 numpy array."""
+        import numpy as np
+        n = C.c_size_t(0)
+        self._check(self.lib.thc_checkpoint_bytes(self.ctx, C.byref(n)), "thc_checkpoint_bytes")
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self.lib.thc_save_checkpoint(self.ctx, buf.ctypes.data_as(C.c_void_p), n.value),
+                    "thc_save_checkpoint")
+        return buf
+
+    def load_checkpoint(self, buf):
+        import numpy as np
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.thc_load_checkpoint(self.ctx, buf.ctypes.data_as(C.c_void_p), buf.size),
+                    "thc_load_checkpoint")
 
     def energy(self):
         e = C.c_double(0.0)

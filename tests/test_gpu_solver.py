@@ -1,6 +1,7 @@
 """Failure handling of the solver (thc_iterate), each condition forced from the host: a NaN
 state, a start a hundred times the MP2 guess, an iteration limit of one, and inputs on which the
-plain iteration itself diverges (the unscaled synthetic Cholesky vectors)."""
+plain iteration itself diverges (the unscaled synthetic Cholesky vectors); and checkpoint/resume
+of an interrupted solve in a fresh context."""
 import numpy as np
 import pytest
 
@@ -99,3 +100,37 @@ def test_divergence_after_restart_is_reported(thc):
     _say("unscaled", len(flags), flags)
     assert sum(1 for f in flags if f & thc.ITER_RESTARTED) == 1
     ctx.close()
+
+
+def test_checkpoint_resumes_the_iteration_exactly(thc, plain):
+    """Two iterations, a checkpoint saved to host memory, a fresh context built on the same inputs
+    loading it and iterating on: every energy and residual norm equals the uninterrupted solve's,
+    bit for bit, and so does the iteration count; a checkpoint from another size is refused."""
+    import numpy as np
+    cfg, it_plain, e_plain = plain
+    a, _ = _ctx(thc, cfg)
+    it_a, _, ok = a.iterate(tol=1e-9, maxit=60)
+    e_a, r_a, _ = a.history()
+    a.close()
+    b, _ = _ctx(thc, cfg)
+    it_b, _, ok_b = b.iterate(tol=1e-9, maxit=2, raise_on_notconv=False)
+    assert (it_b, ok_b) == (2, False)
+    e_b, r_b, _ = b.history()
+    ck = b.save_checkpoint()
+    b.close()
+    c, _ = _ctx(thc, cfg)
+    c.load_checkpoint(ck)
+    it_c, _, ok_c = c.iterate(tol=1e-9, maxit=60)
+    e_c, r_c, _ = c.history()
+    _say("checkpoint", len(ck), "bytes;", it_a, "=", it_b, "+", it_c)
+    assert ok and ok_c and it_a == it_b + it_c
+    assert e_b + e_c == e_a and r_b + r_c == r_a
+    assert abs(c.energy() - e_plain) < 1e-9
+    c.close()
+    other = synth.CONFIGS["small"]
+    d, _ = _ctx(thc, other)
+    with pytest.raises(thc.ThcError, match="THC_EINVAL"):
+        d.load_checkpoint(ck)
+    with pytest.raises(thc.ThcError, match="THC_EINVAL"):
+        d.load_checkpoint(np.zeros(16, dtype=np.uint8))
+    d.close()
