@@ -114,6 +114,9 @@ typedef struct thc_options {
  * flags force one (not both). */
 #define THC_FLAG_QUINTIC (1 << 3)
 #define THC_FLAG_QUARTIC (1 << 4)
+/* Debugging: wait for the stream after every device step of the context, so that a device error
+ * is returned (THC_EDEVICE, thc_last_error naming the step) by the step that caused it. */
+#define THC_FLAG_CHECK (1 << 5)
 
 /* Creates a context bound to the current HIP device and to `stream` (hipStream_t; NULL = the
  * default stream).  Allocates nothing on the device yet.  *out receives the context.

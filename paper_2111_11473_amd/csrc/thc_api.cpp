@@ -140,9 +140,17 @@ namespace {
 
 constexpr double C_D = 0.5;  // prefactor of the Eq. 35-37 ring contraction (closed-shell CCSD)
 
+// THC_FLAG_CHECK: every device step is waited for, so an error is reported by the step that
+// caused it (the network object has no such mode)
+inline hipError_t step_check(thc_ctx* c) {
+  return (c->opt.flags & THC_FLAG_CHECK) ? hipStreamSynchronize(c->stream) : hipSuccess;
+}
+inline hipError_t step_check(thc_mlp*) { return hipSuccess; }
+
 #define HIPCHK(expr)                                                                 \
   do {                                                                               \
     hipError_t _e = (expr);                                                          \
+    if (_e == hipSuccess) _e = step_check(ctx);                                      \
     if (_e != hipSuccess) {                                                          \
       ctx->err = std::string(#expr) + ": " + hipGetErrorString(_e);                  \
       return THC_EDEVICE;                                                            \
@@ -1337,7 +1345,7 @@ bool options_valid(const thc_options* opt) {
   if (opt->o < 1 || opt->v < 1 || opt->nL < 1 || opt->nP < 1 || opt->nQ < 1 || opt->diis_max < 0 ||
       opt->diis_max > 16 || (opt->precision < 0 || opt->precision > 2) ||
       (opt->flags & ~(THC_FLAG_UNFUSED_EXCHANGE | THC_FLAG_STREAM_LVV | THC_FLAG_PROGRESS | THC_FLAG_QUINTIC |
-                      THC_FLAG_QUARTIC)) != 0 || ((opt->flags & THC_FLAG_QUINTIC) && (opt->flags & THC_FLAG_QUARTIC)) || opt->a_block < 0 ||
+                      THC_FLAG_QUARTIC | THC_FLAG_CHECK)) != 0 || ((opt->flags & THC_FLAG_QUINTIC) && (opt->flags & THC_FLAG_QUARTIC)) || opt->a_block < 0 ||
       opt->i_chunk < 0 || opt->x_block < 0 || opt->x_chunk < 0 || opt->x7_chunk < 0 || opt->q_pairs < 0 ||
       opt->q_jchunk < 0 || (opt->split_mask & ~(uint64_t)THC_CHAIN_ALL) != 0 || opt->guess < 0 || opt->guess > 1)
     return false;

@@ -69,6 +69,7 @@ FLAG_STREAM_LVV = 1 << 1
 FLAG_PROGRESS = 1 << 2
 FLAG_QUINTIC = 1 << 3
 FLAG_QUARTIC = 1 << 4
+FLAG_CHECK = 1 << 5
 
 
 class ThcError(RuntimeError):
@@ -379,6 +380,19 @@ class THC:
         self._check(self.lib.thc_history(self.ctx, max_it, e, r, t, C.byref(n)), "thc_history")
         m = min(n.value, max_it)
         return list(e[:m]), list(r[:m]), list(t[:m])
+
+    def iteration_log(self, max_it=1000):
+        """One record per iteration of the last iterate() call (a JSON line each, if dumped):
+        iteration, energy, its change, residual norm, wall seconds since the call began, and the
+        iteration's flags."""
+        e, r, t = self.history(max_it)
+        f = self.history_flags(max_it)
+        out = []
+        for k in range(len(e)):
+            out.append({"iteration": k + 1, "energy": e[k], "dE": e[k] - e[k - 1] if k else None, "rnorm": r[k],
+                        "seconds": t[k], "mixed": bool(f[k] & ITER_MIXED), "restarted": bool(f[k] & ITER_RESTARTED),
+                        "diis_dropped": bool(f[k] & ITER_DIIS_DROPPED), "learned": bool(f[k] & ITER_LEARNED)})
+        return out
 
     def history_precision(self, max_it=1000):
         """1 for each iteration of the last iterate() whose residual was mixed precision, else 0."""

@@ -134,3 +134,26 @@ def test_checkpoint_resumes_the_iteration_exactly(thc, plain):
     with pytest.raises(thc.ThcError, match="THC_EINVAL"):
         d.load_checkpoint(np.zeros(16, dtype=np.uint8))
     d.close()
+
+
+def test_step_checking_mode_and_iteration_log(thc, plain):
+    """THC_FLAG_CHECK (a wait after every device step) changes no result: the solve's history is
+    bit for bit the plain one's; the per-iteration log carries the history."""
+    import json
+    cfg, it_plain, e_plain = plain
+    a, _ = _ctx(thc, cfg)
+    a.iterate(tol=1e-9, maxit=60)
+    ref = a.history()
+    a.close()
+    ctx = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, singles=True, tol_energy=1e-10, flags=thc.FLAG_CHECK)
+    ctx.set_synthetic(cfg.seed, cfg.decay, cfg.coupling, 0.0)
+    ctx.build_synthetic()
+    it, _, ok = ctx.iterate(tol=1e-9, maxit=60)
+    got = ctx.history()
+    assert ok and got[0] == ref[0] and got[1] == ref[1]
+    log = ctx.iteration_log()
+    assert [r["iteration"] for r in log] == list(range(1, it + 1))
+    assert [r["energy"] for r in log] == got[0] and log[0]["dE"] is None
+    assert not any(r["mixed"] or r["restarted"] or r["learned"] for r in log)
+    json.dumps(log)
+    ctx.close()

@@ -53,13 +53,15 @@ def test_binding_refuses_host_tensors():
 
 @pytest.mark.parametrize("field,value", [("o", 0), ("v", -1), ("nL", 0), ("nP", 0), ("nQ", 0),
                                          ("nP", 10 * 40 + 1), ("nQ", 10 * 40 + 1), ("precision", 3),
-                                         ("diis_max", 17), ("flags", 1 << 5), ("x_block", -64)])
+                                         ("diis_max", 17), ("flags", 1 << 6), ("x_block", -64),
+                                         ("split_mask", 1 << 6), ("guess", 2)])
 def test_create_rejects_invalid_options(lib, field, value):
     """Option validation happens before any device call: sizes below 1, a pair basis or ERI grid
     larger than the o v pairs (singular metric / Gram matrix), out-of-range options."""
     from paper_2111_11473_amd import thc
     base = dict(o=10, v=40, nL=150, nP=120, nQ=300, singles=1, diis_max=8, tol_energy=1e-8, a_block=0,
-                i_chunk=0, x_block=0, x_chunk=0, precision=0, flags=0, x7_chunk=0, q_pairs=0, q_jchunk=0)
+                i_chunk=0, x_block=0, x_chunk=0, precision=0, flags=0, x7_chunk=0, q_pairs=0, q_jchunk=0,
+                split_mask=0, guess=0, reserved=0)
     base[field] = value
     opt = thc.Options(**base)
     lib.thc_create.argtypes = [ctypes.POINTER(thc.Options), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
