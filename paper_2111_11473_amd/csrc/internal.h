@@ -169,6 +169,14 @@ hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const d
 hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
                           const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
                           bool fresh, hipStream_t s);
+// FP32 kernel of the mixed-precision path: E, F as above in FP32; G and its transpose GT (GT_I =
+// G_I^T) in FP32 16 x 16 blocks, [I][Pp/16][Pp/16][16][16]; FP32 arithmetic and accumulation over
+// the chunk, added into the FP64 H (or written, fresh); tiles from h32_tiles (16 x 16 block pairs).
+hipError_t h_accumulate_f32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
+                            const float* G, const float* GT, double* H, const uint32_t* tiles, int64_t ntiles,
+                            int64_t slots, bool fresh, hipStream_t s);
+std::vector<uint32_t> h32_tiles(int64_t Pp, int64_t Xb, int64_t slots);
+int64_t h32_slots_per_xcd();
 constexpr int H_GBLK = 8;  // column width of the G blocks
 std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots);
 int64_t h_slots_per_xcd();

@@ -384,9 +384,8 @@ int64_t hilbert_index(int64_t n, int64_t y, int64_t z) {
   return d;
 }
 
-template <int NWZ>
+template <int NZS>
 std::vector<uint32_t> tiles_for(int64_t Pp, int64_t Xb, int64_t slots) {
-  constexpr int NZS = BY / (WZ * NWZ);
   const int64_t nB = Pp / BY, nX = Xb / LANES;
   // Block pairs (Yb <= Zb) in Hilbert-curve order: any run of consecutive pairs covers a compact
   // patch of the (Y, Z) triangle, so the runs that share an XCD's L2 touch few distinct operand
@@ -433,6 +432,225 @@ hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const TE* E, 
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------------------------
+// FP32 instantiation for the mixed-precision path: E, F and G in FP32, FP32 arithmetic and FP32
+// accumulation over one grid-point chunk, added into the FP64 H at its end.  With 4-byte
+// accumulators a wave holds an 8 (Y) x 8 (Z) patch (64 + 64 mirror accumulators in 128 VGPRs),
+// so a workgroup of four waves owns a whole 16 x 16 (Y, Z) block pair: per output a third of the
+// LDS reads and half the copied bytes of the FP64 kernel.  G^YZ and G^ZY come from two arrays,
+// G and its transpose, both in 16 x 16 blocks ([I][Pp/16][Pp/16][16][16]), so both copies are
+// plain 1 KB blocks whose rows a wave reads without bank conflicts.  G is broadcast into the FMAs
+// by DPP row_newbcast as in the FP64 kernel (16 values to a VGPR).
+constexpr int W8 = 8;                           // patch edge (Y and Z) per wave
+constexpr int S32_PAIR = 64 * 2 * 4;            // one row pair of 64 X (FP32): 512 bytes
+constexpr int S32_EY = 0, S32_FY = 8 * S32_PAIR, S32_EZ = 16 * S32_PAIR, S32_FZ = 24 * S32_PAIR;
+constexpr int S32_G = 32 * S32_PAIR, S32_GT = S32_G + 1024, S32_STAGE = S32_GT + 1024;  // 18 KB
+constexpr int S32_NS = 4;
+static_assert(S32_NS * S32_STAGE * 2 <= 160 * 1024, "two workgroups per CU");
+
+// One row j of the wave patch (eight Z): t_k = ey fz_k + ez_k fy, then acc_k += G^YZ t_k and
+// accm_k += G^ZY t_k, G broadcast from lane B + k of each row of 16 lanes (B = 8 (j % 2)).  Every
+// DPP read comes at least two instructions after the VALU write of its t_k.
+template <int B>
+__device__ inline void h_row32(float (&acc)[W8], float (&accm)[W8], float ey, float fy, const float (&ez)[W8],
+                               const float (&fz)[W8], float g, float gm) {
+  float t0, t1, t2, t3, t4, t5, t6, t7;
+  asm("v_mul_f32 %[t0], %[ey], %[f0]\n\t"
+      "v_mul_f32 %[t1], %[ey], %[f1]\n\t"
+      "v_mul_f32 %[t2], %[ey], %[f2]\n\t"
+      "v_mul_f32 %[t3], %[ey], %[f3]\n\t"
+      "v_mul_f32 %[t4], %[ey], %[f4]\n\t"
+      "v_mul_f32 %[t5], %[ey], %[f5]\n\t"
+      "v_mul_f32 %[t6], %[ey], %[f6]\n\t"
+      "v_mul_f32 %[t7], %[ey], %[f7]\n\t"
+      "v_fmac_f32 %[t0], %[e0], %[fy]\n\t"
+      "v_fmac_f32 %[t1], %[e1], %[fy]\n\t"
+      "v_fmac_f32 %[t2], %[e2], %[fy]\n\t"
+      "v_fmac_f32 %[t3], %[e3], %[fy]\n\t"
+      "v_fmac_f32 %[t4], %[e4], %[fy]\n\t"
+      "v_fmac_f32 %[t5], %[e5], %[fy]\n\t"
+      "v_fmac_f32 %[t6], %[e6], %[fy]\n\t"
+      "v_fmac_f32 %[t7], %[e7], %[fy]\n\t"
+      "v_fmac_f32_dpp %[a0], %[g], %[t0] row_newbcast:%[b0]\n\t"
+      "v_fmac_f32_dpp %[m0], %[gm], %[t0] row_newbcast:%[b0]\n\t"
+      "v_fmac_f32_dpp %[a1], %[g], %[t1] row_newbcast:%[b1]\n\t"
+      "v_fmac_f32_dpp %[m1], %[gm], %[t1] row_newbcast:%[b1]\n\t"
+      "v_fmac_f32_dpp %[a2], %[g], %[t2] row_newbcast:%[b2]\n\t"
+      "v_fmac_f32_dpp %[m2], %[gm], %[t2] row_newbcast:%[b2]\n\t"
+      "v_fmac_f32_dpp %[a3], %[g], %[t3] row_newbcast:%[b3]\n\t"
+      "v_fmac_f32_dpp %[m3], %[gm], %[t3] row_newbcast:%[b3]\n\t"
+      "v_fmac_f32_dpp %[a4], %[g], %[t4] row_newbcast:%[b4]\n\t"
+      "v_fmac_f32_dpp %[m4], %[gm], %[t4] row_newbcast:%[b4]\n\t"
+      "v_fmac_f32_dpp %[a5], %[g], %[t5] row_newbcast:%[b5]\n\t"
+      "v_fmac_f32_dpp %[m5], %[gm], %[t5] row_newbcast:%[b5]\n\t"
+      "v_fmac_f32_dpp %[a6], %[g], %[t6] row_newbcast:%[b6]\n\t"
+      "v_fmac_f32_dpp %[m6], %[gm], %[t6] row_newbcast:%[b6]\n\t"
+      "v_fmac_f32_dpp %[a7], %[g], %[t7] row_newbcast:%[b7]\n\t"
+      "v_fmac_f32_dpp %[m7], %[gm], %[t7] row_newbcast:%[b7]"
+      : [a0] "+v"(acc[0]), [a1] "+v"(acc[1]), [a2] "+v"(acc[2]), [a3] "+v"(acc[3]), [a4] "+v"(acc[4]),
+        [a5] "+v"(acc[5]), [a6] "+v"(acc[6]), [a7] "+v"(acc[7]), [m0] "+v"(accm[0]), [m1] "+v"(accm[1]),
+        [m2] "+v"(accm[2]), [m3] "+v"(accm[3]), [m4] "+v"(accm[4]), [m5] "+v"(accm[5]), [m6] "+v"(accm[6]),
+        [m7] "+v"(accm[7]), [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [t4] "=&v"(t4),
+        [t5] "=&v"(t5), [t6] "=&v"(t6), [t7] "=&v"(t7)
+      : [ey] "v"(ey), [fy] "v"(fy), [e0] "v"(ez[0]), [e1] "v"(ez[1]), [e2] "v"(ez[2]), [e3] "v"(ez[3]),
+        [e4] "v"(ez[4]), [e5] "v"(ez[5]), [e6] "v"(ez[6]), [e7] "v"(ez[7]), [f0] "v"(fz[0]), [f1] "v"(fz[1]),
+        [f2] "v"(fz[2]), [f3] "v"(fz[3]), [f4] "v"(fz[4]), [f5] "v"(fz[5]), [f6] "v"(fz[6]), [f7] "v"(fz[7]),
+        [g] "v"(g), [gm] "v"(gm), [b0] "n"(B), [b1] "n"(B + 1), [b2] "n"(B + 2), [b3] "n"(B + 3),
+        [b4] "n"(B + 4), [b5] "n"(B + 5), [b6] "n"(B + 6), [b7] "n"(B + 7));
+}
+
+__device__ inline float fload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__global__ __launch_bounds__(256) void h32_kernel(int Pp, int Xb, int64_t ldi, int64_t nI, const float* __restrict__ E,
+                                                  const float* __restrict__ F, const float* __restrict__ G,
+                                                  const float* __restrict__ GT, double* __restrict__ H,
+                                                  const uint32_t* __restrict__ tiles, int flags) {
+  __shared__ __attribute__((aligned(16))) char lds[S32_NS * S32_STAGE];
+  const uint32_t tile = tiles[blockIdx.x];
+  if (tile & EMPTY) return;  // whole workgroup, before any barrier
+  const bool rev = flags & 1;
+  const bool fresh = flags & 2;
+  const int Yb = tile & 511, Zb = (tile >> 9) & 511, xt = (tile >> 20) & 1023;
+  const bool mirror = Yb != Zb;
+  const int y0 = Yb * BY, z0 = Zb * BY, X0 = xt * LANES;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __builtin_assume(w >= 0 && w < 4);
+  const int ly0 = (w & 1) * W8, lz0 = (w >> 1) * W8;
+
+  // a diagonal block has no mirror: its G^ZY slots stay zero (never copied)
+  if (!mirror)
+    for (int i = threadIdx.x; i < 256; i += 256)
+#pragma unroll
+      for (int b = 0; b < S32_NS; ++b) ((float*)(lds + b * S32_STAGE + S32_GT))[i] = 0.0f;
+
+  float acc[W8][W8], accm[W8][W8];
+#pragma unroll
+  for (int j = 0; j < W8; ++j)
+#pragma unroll
+    for (int k = 0; k < W8; ++k) acc[j][k] = accm[j][k] = 0.0f;
+
+  // copies of one stage: wave w takes row chunks w, w + 4, w + 8, w + 12 (1 KB = two row pairs
+  // each: E^Y, F^Y, E^Z, F^Z four chunks apiece); wave 0 also the G^YZ block, wave 1 (off the
+  // diagonal) the G^ZY block of the transpose
+  const unsigned voff_r = (unsigned)(lane >> 5) * S32_PAIR + (unsigned)(lane & 31) * 16u;
+  const bool g_yz = w == 0, g_zy = w == 1 && mirror;
+  const bool extra = g_yz || g_zy;
+  const unsigned nb16 = (unsigned)Pp / 16u;
+  const unsigned so_g = ((unsigned)Yb * nb16 + (unsigned)Zb) * 1024u;  // byte offset of the block in one I
+  const int64_t PX = (int64_t)Pp * LANES;
+  const int64_t PP = (int64_t)Pp * Pp;
+  const int64_t first = (rev && nI > 0) ? nI - 1 : 0;
+  const float* e_at = E + ((int64_t)xt * ldi + first) * PX;
+  const float* f_at = F + ((int64_t)xt * ldi + first) * PX;
+  const float* g_at = (g_zy ? GT : G) + first * PP;
+  const int64_t dPX = rev ? -PX : PX, dPP = rev ? -PP : PP;
+  auto stage_in = [&](int buf) {
+    const __amdgpu_buffer_rsrc_t re = rsrc(e_at, PX * 4);
+    const __amdgpu_buffer_rsrc_t rf = rsrc(f_at, PX * 4);
+    char* sb = lds + buf * S32_STAGE;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = w + 4 * q;      // chunk: region c / 4 (E^Y, F^Y, E^Z, F^Z), pairs 2 (c % 4), + 1
+      const int reg = c >> 2;
+      const int pair0 = (reg < 2 ? y0 : z0) / 2 + 2 * (c & 3);
+      bload_lds((reg & 1) ? rf : re, sb + c * 1024, voff_r, (unsigned)pair0 * S32_PAIR);
+    }
+    if (extra) bload_lds(rsrc(g_at, PP * 4), sb + (g_yz ? S32_G : S32_GT), (unsigned)lane * 16u, so_g);
+    e_at += dPX;
+    f_at += dPX;
+    g_at += dPP;
+  };
+
+  // broadcast sources: lane l holds G[ly0 + 2 r + m / 8][lz0 + m % 8] (r = 0..3, m = l % 16) of
+  // the block, G^YZ from G and G^ZY from the transpose (the same position in its block)
+  const int m = lane & 15;
+  const int goff = (ly0 + (m >> 3)) * 16 + lz0 + (m & 7);
+
+  constexpr int D = S32_NS - 1;
+  auto next = [](int b) { return b + 1 == S32_NS ? 0 : b + 1; };
+  int sbuf = 0;
+  int64_t issued = 0;
+  for (; issued < D && issued < nI; ++issued) {
+    stage_in(sbuf);
+    sbuf = next(sbuf);
+  }
+  wait_pipe<4>((int)(issued > 0 ? issued - 1 : 0), extra);
+  int buf = 0;
+  auto consume = [&]() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(1);
+    const char* __restrict__ st = lds + buf * S32_STAGE;
+    const float* __restrict__ sg = (const float*)(st + S32_G);
+    const float* __restrict__ sgt = (const float*)(st + S32_GT);
+    auto pair = [&](int off, int p) { return *(const f2*)(st + off + p * S32_PAIR + lane * 8); };
+    float ez[W8], fz[W8];
+#pragma unroll
+    for (int q = 0; q < W8 / 2; ++q) {
+      const f2 a = pair(S32_EZ, lz0 / 2 + q), b = pair(S32_FZ, lz0 / 2 + q);
+      ez[2 * q] = a.x; ez[2 * q + 1] = a.y;
+      fz[2 * q] = b.x; fz[2 * q + 1] = b.y;
+    }
+    float g[4], gm[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      g[r] = sg[goff + 32 * r];
+      gm[r] = sgt[goff + 32 * r];
+    }
+#pragma unroll
+    for (int p = 0; p < W8 / 2; ++p) {
+      const f2 ey = pair(S32_EY, ly0 / 2 + p), fy = pair(S32_FY, ly0 / 2 + p);
+      h_row32<0>(acc[2 * p], accm[2 * p], ey.x, fy.x, ez, fz, g[p], gm[p]);
+      h_row32<8>(acc[2 * p + 1], accm[2 * p + 1], ey.y, fy.y, ez, fz, g[p], gm[p]);
+    }
+    __builtin_amdgcn_s_setprio(0);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  const int64_t steady = nI - D;
+  for (int64_t I = 0; I < steady; ++I) {
+    stage_in(sbuf);
+    sbuf = next(sbuf);
+    consume();
+    wait_pipe<4>(D - 1, extra);
+    buf = next(buf);
+  }
+  for (int64_t I = steady > 0 ? steady : 0; I < nI; ++I) {
+    consume();
+    const int64_t later = nI - I - 2;
+    wait_pipe<4>((int)(later > 0 ? later : 0), extra);
+    buf = next(buf);
+  }
+
+  // H (FP64, [Pp][Pp][Xb]) = or += the chunk's sums
+  const unsigned xrow = (unsigned)Xb * 8u;
+  const unsigned lo = (unsigned)lane * 8u;
+  const double* Hw = H + ((int64_t)(y0 + ly0) * Pp + z0 + lz0) * Xb + X0;
+  const double* Hm = H + ((int64_t)(z0 + lz0) * Pp + y0 + ly0) * Xb + X0;
+  const int64_t h_bytes = ((int64_t)(W8 - 1) * Pp + W8) * Xb * 8;
+  const __amdgpu_buffer_rsrc_t rh = rsrc(Hw, h_bytes);
+  const __amdgpu_buffer_rsrc_t rm = rsrc(Hm, h_bytes);
+#pragma unroll
+  for (int j = 0; j < W8; ++j)
+#pragma unroll
+    for (int k = 0; k < W8; ++k) {
+      const unsigned o = (unsigned)(j * Pp + k) * xrow;
+      const double v = fresh ? (double)acc[j][k] : bload(rh, lo, o) + (double)acc[j][k];
+      bstore(v, rh, lo, o);
+    }
+  if (mirror) {
+#pragma unroll
+    for (int j = 0; j < W8; ++j)
+#pragma unroll
+      for (int k = 0; k < W8; ++k) {
+        const unsigned o = (unsigned)(k * Pp + j) * xrow;
+        const double v = fresh ? (double)accm[j][k] : bload(rm, lo, o) + (double)accm[j][k];
+        bstore(v, rm, lo, o);
+      }
+  }
+}
+
 constexpr int H_NWZ = 2, H_NS = 3;    // 4 waves, 26 KB stages, three stages (two workgroups per CU)
 constexpr int H_NS32 = 4;             // FP32 E, F: 14 KB stages, four stages
 
@@ -453,12 +671,40 @@ int64_t h_slots_per_xcd() {
 // tiles that share an X tile and a Hilbert-curve patch of block pairs; run c sits at workgroup ids
 // b = 8 slots (c / 8) + 8 k + (c % 8), k < slots, so that it runs on one XCD.  Unused entries are
 // EMPTY.
-std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots) { return tiles_for<H_NWZ>(Pp, Xb, slots); }
+std::vector<uint32_t> h_tiles(int64_t Pp, int64_t Xb, int64_t slots) {
+  return tiles_for<BY / (WZ * H_NWZ)>(Pp, Xb, slots);
+}
 
 hipError_t h_accumulate(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const double* E, const double* F,
                         const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
                         bool fresh, hipStream_t s) {
   return launch<H_NWZ, H_NS, double>(Pp, Xb, ldi, nI, E, F, G, H, tiles, ntiles, slots, fresh, s);
+}
+
+int64_t h32_slots_per_xcd() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, h32_kernel, 256, 0) != hipSuccess)
+    return 0;
+  return std::max<int64_t>(1, (int64_t)(cus / 8) * std::max(per_cu, 1));
+}
+
+std::vector<uint32_t> h32_tiles(int64_t Pp, int64_t Xb, int64_t slots) { return tiles_for<1>(Pp, Xb, slots); }
+
+hipError_t h_accumulate_f32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
+                            const float* G, const float* GT, double* H, const uint32_t* tiles, int64_t ntiles,
+                            int64_t slots, bool fresh, hipStream_t s) {
+  if (Pp % BY != 0 || Pp <= 0 || Pp > 8192 || Xb % LANES != 0 || Xb > (Pp + LANES - 1) / LANES * LANES || Xb <= 0 ||
+      ntiles <= 0 || ntiles > 2147483647LL || nI < 0 || ldi < nI || slots < 1 || ntiles % (8 * slots) != 0)
+    return hipErrorInvalidValue;
+  const int64_t gen = 8 * slots;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += gen) {
+    hipLaunchKernelGGL(h32_kernel, dim3((unsigned)gen), dim3(256), 0, s, (int)Pp, (int)Xb, ldi, nI, E, F, G, GT, H,
+                       tiles + t0, (int)((t0 / gen) & 1) | (fresh ? 2 : 0));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,

@@ -111,6 +111,9 @@ struct thc_ctx {
   bool has_shift = false;
   uint32_t* htiles = nullptr;  // H-kernel tile table
   int64_t nhtiles = 0, hslots = 0, hfilled = 0;  // table length (with empty slots), slots per XCD, tiles
+  uint32_t* htiles32 = nullptr;  // tile table of the FP32 H-kernel (mixed precision: 16 x 16 block pairs)
+  int64_t nhtiles32 = 0, hslots32 = 0;
+  float *G32 = nullptr, *GT32 = nullptr;  // FP32 G and its transpose (mixed precision), in the FP64 G buffer
   int alg1_tile = 64;          // tile edge of the symmetric Alg. 1 product
   double *R1 = nullptr, *I6 = nullptr;
   // Alg. 7
@@ -615,7 +618,8 @@ int choose_plan(thc_ctx* ctx, double budget, int64_t slots) {
   int64_t Xb = 0;
   double rem = 0.0;
   for (int64_t xb = op.x_block > 0 ? op.x_block : P64; xb >= 64; xb -= 64) {
-    const double tiles = 8.0 * (double)tile_table_doubles(Pp, xb, slots);
+    // the FP32 kernel's table (mixed precision) has half as many tiles: at most as many entries
+    const double tiles = 8.0 * (double)tile_table_doubles(Pp, xb, slots) * (op.precision >= 1 ? 2.0 : 1.0);
     rem = budget - pers - a7 - tiles - fixed6(xb);
     const double r6 = fixed6(xb) + per_i(xb) * (double)ic_min;
     if (rem >= per_i(xb) * (double)ic_min && rem + r6 - std::max(r6, setup) >= 0.0) {
@@ -653,9 +657,15 @@ int plan_and_alloc(thc_ctx* ctx) {
   }
   RCHK(choose_plan(ctx, budget, ctx->hslots));
   const std::vector<uint32_t> tiles = h_tiles(ctx->Pp, ctx->Xb, ctx->hslots);
+  std::vector<uint32_t> tiles32;
+  if (ctx->opt.precision >= 1 && !ctx->quintic) {
+    ctx->hslots32 = h32_slots_per_xcd();
+    if (ctx->hslots32 < 1) { ctx->err = "cannot query the device for the H-kernel launch"; return THC_EDEVICE; }
+    tiles32 = h32_tiles(ctx->Pp, ctx->Xb, ctx->hslots32);
+  }
   double* tb = nullptr;
   std::vector<BufSpec> pers = persistent_list(ctx);
-  pers.push_back({&tb, (tiles.size() + 1) / 2});
+  pers.push_back({&tb, (tiles.size() + tiles32.size() + 1) / 2});
   const std::vector<BufSpec> r6 = ctx->quintic ? quintic_list(ctx) : region6_list(ctx), a7 = alg7_list(ctx);
   size_t np = 0, n6 = 0, n7 = 0;
   for (const auto& a : pers) np += aligned(a.n);
@@ -693,6 +703,14 @@ int plan_and_alloc(thc_ctx* ctx) {
   ctx->hfilled = 0;
   for (uint32_t t : tiles) ctx->hfilled += (t & 0x80000000u) ? 0 : 1;
   RCHK(h2d(ctx, ctx->htiles, tiles.data(), tiles.size() * sizeof(uint32_t)));
+  if (!tiles32.empty()) {
+    ctx->htiles32 = ctx->htiles + tiles.size();
+    ctx->nhtiles32 = (int64_t)tiles32.size();
+    RCHK(h2d(ctx, ctx->htiles32, tiles32.data(), tiles32.size() * sizeof(uint32_t)));
+    // FP32 G and G^T in the two halves of the FP64 G buffer (a residual uses one or the other)
+    ctx->G32 = reinterpret_cast<float*>(ctx->Gc);
+    ctx->GT32 = ctx->G32 + ctx->Ic * ctx->Pp * ctx->Pp;
+  }
   ctx->diisB.assign((size_t)std::max<int64_t>(ctx->opt.diis_max, 1) * std::max<int64_t>(ctx->opt.diis_max, 1), 0.0);
   return THC_OK;
 }
@@ -1042,22 +1060,33 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
           RCHK(gemm(ctx, ge));
           RCHK(gemm(ctx, gf));
         }
-        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6), stored in 16 x H_GBLK blocks
+        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6), stored in 16 x H_GBLK blocks (FP64) or,
+        // with its transpose, in 16 x 16 blocks (FP32, mixed precision)
         RCHK(gemm(ctx, mk(ic * o, P, v, ctx->Bq + I0 * ov, v, false, Yv, P, false, ctx->GYc, P)));
-        {
+        if (ctx->mixed) {
+          Gemm gg = batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, nullptr, Pp), ic, 0, o * P, Pp * Pp);
+          gg.Cf = ctx->G32;
+          gg.cblk = 16;
+          RCHK(gemm(ctx, gg));
+          Gemm gt = batched(mk(P, P, o, ctx->GYc, P, true, Yo, P, false, nullptr, Pp), ic, o * P, 0, Pp * Pp);
+          gt.Cf = ctx->GT32;
+          gt.cblk = 16;
+          RCHK(gemm(ctx, gt));
+        } else {
           Gemm gg = batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, Pp), ic, 0, o * P, Pp * Pp);
           gg.cblk = H_GBLK;
           RCHK(gemm(ctx, gg));
         }
-        {
+        if (ctx->mixed) {
+          Scope sc(ctx, "h_kernel");
+          sc.launches = ctx->nhtiles32 / (8 * ctx->hslots32);
+          HIPCHK(h_accumulate_f32(Pp, Xb, ctx->Ic, ic, ctx->Ec32, ctx->Fc32, ctx->G32, ctx->GT32, ctx->Hb,
+                                  ctx->htiles32, ctx->nhtiles32, ctx->hslots32, I0 == 0, s));
+        } else {
           Scope sc(ctx, "h_kernel");
           sc.launches = ctx->nhtiles / (8 * ctx->hslots);  // one dispatch per generation of tiles
-          if (ctx->mixed)
-            HIPCHK(h_accumulate32(Pp, Xb, ctx->Ic, ic, ctx->Ec32, ctx->Fc32, ctx->Gc, ctx->Hb, ctx->htiles,
-                                  ctx->nhtiles, ctx->hslots, I0 == 0, s));
-          else
-            HIPCHK(h_accumulate(Pp, Xb, ctx->Ic, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles,
-                                ctx->nhtiles, ctx->hslots, I0 == 0, s));
+          HIPCHK(h_accumulate(Pp, Xb, ctx->Ic, ic, ctx->Ec, ctx->Fc, ctx->Gc, ctx->Hb, ctx->htiles, ctx->nhtiles,
+                              ctx->hslots, I0 == 0, s));
         }
       }
       // I^X_ia = sum_YZ y_i^Z y_a^Y H^XYZ ; sigma^XW += sum_ia y_i^W y_a^W I^X_ia  (Alg. 6)
@@ -1406,8 +1435,10 @@ int thc_plan_query(const thc_options* opt, int synthetic, uint64_t budget_bytes,
   const double a7 = list_bytes(alg7_list(&c)), setup = 8.0 * (double)setup_doubles(&c);
   int64_t tiles = 0, entries = 0;
   tile_counts(c.Pp, c.Xb, slots, &tiles, &entries);
-  fill_plan_info(&c, tiles, entries, slots, pers + 8.0 * (double)tile_table_doubles(c.Pp, c.Xb, slots) +
-                                               std::max(r6, setup) + a7, out);
+  fill_plan_info(&c, tiles, entries, slots,
+                 pers + 8.0 * (double)tile_table_doubles(c.Pp, c.Xb, slots) * (opt->precision >= 1 ? 2.0 : 1.0) +
+                     std::max(r6, setup) + a7,
+                 out);
   return THC_OK;
 }
 

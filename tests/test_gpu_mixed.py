@@ -76,6 +76,31 @@ def test_mixed_residual_terms_within_bound(thc, name, precision):
     _say("worst term error", worst)
 
 
+@pytest.mark.parametrize("i_chunk", [0, 200])
+def test_mixed_wide_rank_h_path(thc, i_chunk):
+    """Eq. 32 + 33 in mixed precision at a rank (nP = 700) where the FP32 H-kernel runs many
+    generations of resident tiles (odd ones walking the grid points backwards) and, with 200-point
+    chunks, adds each chunk's FP32 sums into the FP64 H of the previous ones."""
+    cfg = synth.CONFIGS["wide"]
+    _say("wide mixed i_chunk", i_chunk)
+    s, ctx, Z0 = _make(thc, cfg, precision=1, i_chunk=i_chunk, flags=thc.FLAG_QUARTIC)
+    plan = ctx.plan()
+    assert plan["quintic"] == 0 and plan["i_chunks"] == (1 if i_chunk == 0 else 4)
+    rng = np.random.default_rng(4)
+    P = Z0.shape[0]
+    R = rng.standard_normal((P, P))
+    Z = Z0 + 0.3 * np.abs(Z0).max() * (R + R.T)
+    t1 = 0.02 * rng.standard_normal((cfg.o, cfg.v))
+    z, _ = oracle.eri_fit(s["L"], cfg.o, s["xo"], s["xv"])
+    V = oracle.eri_thc_dense(s["xo"], s["xv"], z)
+    ref, _ = oracle.thc_residual(s["eps"], s["L"], s["Xo"], s["Xv"], Z, t1, V, terms=True)
+    want = ref["eq32"] + ref["eq33"]
+    sig, _ = ctx.residual(_dev(Z), _dev(t1), mask=thc.TERM_EQ32)
+    err = np.abs(_host(sig) - want).max() / np.abs(want).max()
+    _say("  eq32+33 relative error %.2e" % err)
+    assert err < RTOL_MIXED[1]
+
+
 @pytest.mark.parametrize("precision", [1, 2])
 def test_mixed_solve_reaches_fp64_energy(thc, precision):
     cfg = synth.CONFIGS["medium"]
