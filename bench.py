@@ -381,6 +381,7 @@ def main():
     m_ms, _ = prof["misc"]
     x_ms, _ = prof["exch"]
     launches_per_residual = max(1, h_n // max(1, r_n))
+    h_peak = PEAK_FP64_VALU_TFLOPS if LEG_PRECISION[head] == 0 else PEAK_FP32_VALU_TFLOPS
     flops_per_launch = h_flops_per_residual / launches_per_residual
     avg_launch_s = (h_ms / 1e3) / max(1, h_n)
     achieved = flops_per_launch / avg_launch_s / 1e12
@@ -423,7 +424,7 @@ def main():
                 "precision": ("FP32 MFMA contractions" if precision == 1 else
                               "compensated split-BF16 contractions (three bf16 pieces per operand, six products, "
                               "FP32 accumulation)") +
-                             " and FP32 H operands (FP64 accumulation), FP64 energy, denominators, fit, DIIS; "
+                             " and the H accumulation in FP32 per grid-point chunk, FP64 energy, denominators, fit, DIIS; "
                              "FP64 finishing iterations",
                 "plan": planm, "converge": convm}
 
@@ -448,16 +449,22 @@ def main():
                                f"nL={cfg.nL} nP={cfg.nP} nQ={cfg.nQ}, seeded synthetic inputs generated on the device",
                    "o": cfg.o, "v": cfg.v, "nL": cfg.nL, "nP": cfg.nP, "nQ": cfg.nQ, "precision": head,
                    "parallelism": "single GPU"},
-        "roofline": {"kernel": "h_kernel (three-way accumulation of Alg. 6, FP64 VALU arithmetic, Y<->Z symmetric"
-                               + ("" if head_prec == 0 else "; FP32 E, F operands") + ")", "bound": "alu",
-                     "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+        "roofline": {"kernel": "h_kernel (three-way accumulation of Alg. 6, Y<->Z symmetric, "
+                               + ("FP64 VALU arithmetic" if head_prec == 0 else
+                                  "FP32 VALU arithmetic and operands, FP64 H across grid-point chunks") + ")",
+                     "bound": "alu",
+                     "achieved": achieved, "peak": h_peak, "unit": "TFLOP/s",
+                     "frac": achieved / h_peak,
                      "traffic": _traffic(cfg.name, launches_per_residual) if head_prec == 0 else None,
                      "launches": h_n,
                      "avg_launch_ms": 1e3 * avg_launch_s, "algorithmic_flops_per_launch": flops_per_launch,
                      "flop_count": "5 N_Q N_P^3 per residual (the accumulation as written)",
-                     "issued": {"achieved": achieved_issued, "frac": achieved_issued / PEAK_FP64_VALU_TFLOPS,
-                                "flop_count": "3.5 N_Q N_P^3 (one bracket for both H^XYZ and H^XZY)"}},
+                     "issued": {"achieved": achieved_issued, "frac": achieved_issued / h_peak,
+                                "flop_count": "3.5 N_Q N_P^3 (one bracket for both H^XYZ and H^XZY)"},
+                     **({} if head_prec == 0 else {
+                         "without_packed_fp32": {"peak": PEAK_FP64_VALU_TFLOPS, "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+                                                 "note": "the FP32 issue rate with packed FP32 instructions "
+                                                         "disabled (one FMA per lane per instruction)"}})},
         "mfma": {("gemm_fp64" if head_prec == 0 else "gemm_reduced"):
                      {"achieved": (gf64 if head_prec == 0 else gfm) / max(g_per, 1e-12) / 1e12,
                       "peak": PEAK_FP64_VALU_TFLOPS if head_prec == 0 else PEAK_FP32_MFMA_TFLOPS,

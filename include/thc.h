@@ -65,7 +65,8 @@ typedef struct thc_options {
                              * 0 = automatic */
   int64_t x_chunk;          /* amplitude ranks per Alg. 7 exchange chunk (two-GEMM form); 0 = automatic */
   int32_t precision;        /* 0 = FP64 throughout; 1 = mixed: FP32-MFMA contractions (the fused Alg. 7
-                               exchange included) and FP32 H-kernel operands with FP64 accumulation,
+                               exchange included) and the H accumulation in FP32 per grid-point chunk
+                               (added into an FP64 H),
                                FP64 energy, denominators, fit and DIIS, and thc_iterate finishing with
                                FP64 residuals (mixed ones until the norm has dropped 1e4-fold, is
                                within 10 tol, stops falling, or the last two predict the next one

@@ -53,7 +53,7 @@ constexpr int WY = 8, WZ = 4;              // per-wave patch
 constexpr int RSRC_W3 = 0x00020000;        // raw 32-bit buffer access
 constexpr uint32_t EMPTY = 0x80000000u;
 
-// TE: storage type of E and F (double, or float in the mixed-precision path); G and H are FP64.
+// TE: storage type of E and F (the FP64 kernel instantiates double; G and H are FP64).
 template <int NWZ, int NS, typename TE>
 struct Geo {
   static constexpr int NW = (BY / WY) * NWZ;        // waves per workgroup
@@ -652,7 +652,6 @@ __global__ __launch_bounds__(256) void h32_kernel(int Pp, int Xb, int64_t ldi, i
 }
 
 constexpr int H_NWZ = 2, H_NS = 3;    // 4 waves, 26 KB stages, three stages (two workgroups per CU)
-constexpr int H_NS32 = 4;             // FP32 E, F: 14 KB stages, four stages
 
 }  // namespace
 
@@ -705,12 +704,6 @@ hipError_t h_accumulate_f32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, con
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
-}
-
-hipError_t h_accumulate32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
-                          const double* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
-                          bool fresh, hipStream_t s) {
-  return launch<H_NWZ, H_NS32, float>(Pp, Xb, ldi, nI, E, F, G, H, tiles, ntiles, slots, fresh, s);
 }
 
 }  // namespace thc
