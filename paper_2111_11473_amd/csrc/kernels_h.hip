@@ -437,10 +437,11 @@ hipError_t launch(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const TE* E, 
 // accumulation over one grid-point chunk, added into the FP64 H at its end.  With 4-byte
 // accumulators a wave holds an 8 (Y) x 8 (Z) patch (64 + 64 mirror accumulators in 128 VGPRs),
 // so a workgroup of four waves owns a whole 16 x 16 (Y, Z) block pair: per output a third of the
-// LDS reads and half the copied bytes of the FP64 kernel.  G^YZ and G^ZY come from two arrays,
-// G and its transpose, both in 16 x 16 blocks ([I][Pp/16][Pp/16][16][16]), so both copies are
-// plain 1 KB blocks whose rows a wave reads without bank conflicts.  G is broadcast into the FMAs
-// by DPP row_newbcast as in the FP64 kernel (16 values to a VGPR).
+// LDS reads and half the copied bytes of the FP64 kernel.  G is stored in 16 x 16 blocks
+// ([I][Pp/16][Pp/16][16][16]); the tile's G^YZ block (Yb, Zb) is copied as it is, its G^ZY block
+// (Zb, Yb) with its 16-byte granules swizzled (row zz, granule g at position 4 zz + (g ^ ((zz / 2)
+// % 4))), so that the column pieces a wave broadcasts from it fall on distinct LDS banks.  G is
+// broadcast into the FMAs by DPP row_newbcast as in the FP64 kernel (16 values to a VGPR).
 constexpr int W8 = 8;                           // patch edge (Y and Z) per wave
 constexpr int S32_PAIR = 64 * 2 * 4;            // one row pair of 64 X (FP32): 512 bytes
 constexpr int S32_EY = 0, S32_FY = 8 * S32_PAIR, S32_EZ = 16 * S32_PAIR, S32_FZ = 24 * S32_PAIR;
@@ -505,8 +506,8 @@ __device__ inline float fload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned 
 
 __global__ __launch_bounds__(256) void h32_kernel(int Pp, int Xb, int64_t ldi, int64_t nI, const float* __restrict__ E,
                                                   const float* __restrict__ F, const float* __restrict__ G,
-                                                  const float* __restrict__ GT, double* __restrict__ H,
-                                                  const uint32_t* __restrict__ tiles, int flags) {
+                                                  double* __restrict__ H, const uint32_t* __restrict__ tiles,
+                                                  int flags) {
   __shared__ __attribute__((aligned(16))) char lds[S32_NS * S32_STAGE];
   const uint32_t tile = tiles[blockIdx.x];
   if (tile & EMPTY) return;  // whole workgroup, before any barrier
@@ -534,18 +535,20 @@ __global__ __launch_bounds__(256) void h32_kernel(int Pp, int Xb, int64_t ldi, i
 
   // copies of one stage: wave w takes row chunks w, w + 4, w + 8, w + 12 (1 KB = two row pairs
   // each: E^Y, F^Y, E^Z, F^Z four chunks apiece); wave 0 also the G^YZ block, wave 1 (off the
-  // diagonal) the G^ZY block of the transpose
+  // diagonal) the G^ZY block, lane l fetching the source granule the swizzle puts at position l
   const unsigned voff_r = (unsigned)(lane >> 5) * S32_PAIR + (unsigned)(lane & 31) * 16u;
   const bool g_yz = w == 0, g_zy = w == 1 && mirror;
   const bool extra = g_yz || g_zy;
   const unsigned nb16 = (unsigned)Pp / 16u;
-  const unsigned so_g = ((unsigned)Yb * nb16 + (unsigned)Zb) * 1024u;  // byte offset of the block in one I
+  const int gz_row = lane >> 2, gz_gran = (lane & 3) ^ ((gz_row >> 1) & 3);
+  const unsigned voff_g = g_zy ? (unsigned)(gz_row * 16 + 4 * gz_gran) * 4u : (unsigned)lane * 16u;
+  const unsigned so_g = (g_zy ? (unsigned)Zb * nb16 + (unsigned)Yb : (unsigned)Yb * nb16 + (unsigned)Zb) * 1024u;
   const int64_t PX = (int64_t)Pp * LANES;
   const int64_t PP = (int64_t)Pp * Pp;
   const int64_t first = (rev && nI > 0) ? nI - 1 : 0;
   const float* e_at = E + ((int64_t)xt * ldi + first) * PX;
   const float* f_at = F + ((int64_t)xt * ldi + first) * PX;
-  const float* g_at = (g_zy ? GT : G) + first * PP;
+  const float* g_at = G + first * PP;
   const int64_t dPX = rev ? -PX : PX, dPP = rev ? -PP : PP;
   auto stage_in = [&](int buf) {
     const __amdgpu_buffer_rsrc_t re = rsrc(e_at, PX * 4);
@@ -558,16 +561,24 @@ __global__ __launch_bounds__(256) void h32_kernel(int Pp, int Xb, int64_t ldi, i
       const int pair0 = (reg < 2 ? y0 : z0) / 2 + 2 * (c & 3);
       bload_lds((reg & 1) ? rf : re, sb + c * 1024, voff_r, (unsigned)pair0 * S32_PAIR);
     }
-    if (extra) bload_lds(rsrc(g_at, PP * 4), sb + (g_yz ? S32_G : S32_GT), (unsigned)lane * 16u, so_g);
+    if (extra) bload_lds(rsrc(g_at, PP * 4), sb + (g_yz ? S32_G : S32_GT), voff_g, so_g);
     e_at += dPX;
     f_at += dPX;
     g_at += dPP;
   };
 
-  // broadcast sources: lane l holds G[ly0 + 2 r + m / 8][lz0 + m % 8] (r = 0..3, m = l % 16) of
-  // the block, G^YZ from G and G^ZY from the transpose (the same position in its block)
+  // broadcast sources: lane l holds G^YZ[ly0 + 2 r + m / 8][lz0 + m % 8] and G^ZY[lz0 + m % 8][ly0 +
+  // 2 r + m / 8] (r = 0..3, m = l % 16); the G^ZY row zz = lz0 + m % 8 lies at granule position
+  // 4 zz + (g ^ ((zz / 2) % 4)) for its column granule g
   const int m = lane & 15;
   const int goff = (ly0 + (m >> 3)) * 16 + lz0 + (m & 7);
+  const int gzz = lz0 + (m & 7);
+  int gmoff[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int yy = ly0 + 2 * r + (m >> 3);
+    gmoff[r] = (gzz * 4 + ((yy >> 2) ^ ((gzz >> 1) & 3))) * 4 + (yy & 3);
+  }
 
   constexpr int D = S32_NS - 1;
   auto next = [](int b) { return b + 1 == S32_NS ? 0 : b + 1; };
@@ -597,7 +608,7 @@ __global__ __launch_bounds__(256) void h32_kernel(int Pp, int Xb, int64_t ldi, i
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       g[r] = sg[goff + 32 * r];
-      gm[r] = sgt[goff + 32 * r];
+      gm[r] = sgt[gmoff[r]];
     }
 #pragma unroll
     for (int p = 0; p < W8 / 2; ++p) {
@@ -691,14 +702,14 @@ int64_t h32_slots_per_xcd() {
 std::vector<uint32_t> h32_tiles(int64_t Pp, int64_t Xb, int64_t slots) { return tiles_for<1>(Pp, Xb, slots); }
 
 hipError_t h_accumulate_f32(int64_t Pp, int64_t Xb, int64_t ldi, int64_t nI, const float* E, const float* F,
-                            const float* G, const float* GT, double* H, const uint32_t* tiles, int64_t ntiles,
-                            int64_t slots, bool fresh, hipStream_t s) {
+                            const float* G, double* H, const uint32_t* tiles, int64_t ntiles, int64_t slots,
+                            bool fresh, hipStream_t s) {
   if (Pp % BY != 0 || Pp <= 0 || Pp > 8192 || Xb % LANES != 0 || Xb > (Pp + LANES - 1) / LANES * LANES || Xb <= 0 ||
       ntiles <= 0 || ntiles > 2147483647LL || nI < 0 || ldi < nI || slots < 1 || ntiles % (8 * slots) != 0)
     return hipErrorInvalidValue;
   const int64_t gen = 8 * slots;
   for (int64_t t0 = 0; t0 < ntiles; t0 += gen) {
-    hipLaunchKernelGGL(h32_kernel, dim3((unsigned)gen), dim3(256), 0, s, (int)Pp, (int)Xb, ldi, nI, E, F, G, GT, H,
+    hipLaunchKernelGGL(h32_kernel, dim3((unsigned)gen), dim3(256), 0, s, (int)Pp, (int)Xb, ldi, nI, E, F, G, H,
                        tiles + t0, (int)((t0 / gen) & 1) | (fresh ? 2 : 0));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

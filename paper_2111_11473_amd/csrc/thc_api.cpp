@@ -113,7 +113,7 @@ struct thc_ctx {
   int64_t nhtiles = 0, hslots = 0, hfilled = 0;  // table length (with empty slots), slots per XCD, tiles
   uint32_t* htiles32 = nullptr;  // tile table of the FP32 H-kernel (mixed precision: 16 x 16 block pairs)
   int64_t nhtiles32 = 0, hslots32 = 0;
-  float *G32 = nullptr, *GT32 = nullptr;  // FP32 G and its transpose (mixed precision), in the FP64 G buffer
+  float* G32 = nullptr;  // FP32 G (mixed precision), in the FP64 G buffer
   int alg1_tile = 64;          // tile edge of the symmetric Alg. 1 product
   double *R1 = nullptr, *I6 = nullptr;
   // Alg. 7
@@ -707,9 +707,8 @@ int plan_and_alloc(thc_ctx* ctx) {
     ctx->htiles32 = ctx->htiles + tiles.size();
     ctx->nhtiles32 = (int64_t)tiles32.size();
     RCHK(h2d(ctx, ctx->htiles32, tiles32.data(), tiles32.size() * sizeof(uint32_t)));
-    // FP32 G and G^T in the two halves of the FP64 G buffer (a residual uses one or the other)
+    // FP32 G in the FP64 G buffer (a residual uses one or the other)
     ctx->G32 = reinterpret_cast<float*>(ctx->Gc);
-    ctx->GT32 = ctx->G32 + ctx->Ic * ctx->Pp * ctx->Pp;
   }
   ctx->diisB.assign((size_t)std::max<int64_t>(ctx->opt.diis_max, 1) * std::max<int64_t>(ctx->opt.diis_max, 1), 0.0);
   return THC_OK;
@@ -1060,18 +1059,14 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
           RCHK(gemm(ctx, ge));
           RCHK(gemm(ctx, gf));
         }
-        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6), stored in 16 x H_GBLK blocks (FP64) or,
-        // with its transpose, in 16 x 16 blocks (FP32, mixed precision)
+        // G_I[Y][Z] = sum_ia y_i^Y y_a^Z B_ia^I   (Alg. 6), stored in 16 x H_GBLK blocks (FP64) or
+        // in 16 x 16 blocks (FP32, mixed precision)
         RCHK(gemm(ctx, mk(ic * o, P, v, ctx->Bq + I0 * ov, v, false, Yv, P, false, ctx->GYc, P)));
         if (ctx->mixed) {
           Gemm gg = batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, nullptr, Pp), ic, 0, o * P, Pp * Pp);
           gg.Cf = ctx->G32;
           gg.cblk = 16;
           RCHK(gemm(ctx, gg));
-          Gemm gt = batched(mk(P, P, o, ctx->GYc, P, true, Yo, P, false, nullptr, Pp), ic, o * P, 0, Pp * Pp);
-          gt.Cf = ctx->GT32;
-          gt.cblk = 16;
-          RCHK(gemm(ctx, gt));
         } else {
           Gemm gg = batched(mk(P, P, o, Yo, P, true, ctx->GYc, P, false, ctx->Gc, Pp), ic, 0, o * P, Pp * Pp);
           gg.cblk = H_GBLK;
@@ -1080,8 +1075,8 @@ int residual_impl(thc_ctx* ctx, const double* T, const double* t1, uint32_t mask
         if (ctx->mixed) {
           Scope sc(ctx, "h_kernel");
           sc.launches = ctx->nhtiles32 / (8 * ctx->hslots32);
-          HIPCHK(h_accumulate_f32(Pp, Xb, ctx->Ic, ic, ctx->Ec32, ctx->Fc32, ctx->G32, ctx->GT32, ctx->Hb,
-                                  ctx->htiles32, ctx->nhtiles32, ctx->hslots32, I0 == 0, s));
+          HIPCHK(h_accumulate_f32(Pp, Xb, ctx->Ic, ic, ctx->Ec32, ctx->Fc32, ctx->G32, ctx->Hb, ctx->htiles32,
+                                  ctx->nhtiles32, ctx->hslots32, I0 == 0, s));
         } else {
           Scope sc(ctx, "h_kernel");
           sc.launches = ctx->nhtiles / (8 * ctx->hslots);  // one dispatch per generation of tiles
