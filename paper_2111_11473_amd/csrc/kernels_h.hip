@@ -500,10 +500,6 @@ __device__ inline void h_row32(float (&acc)[W8], float (&accm)[W8], float ey, fl
         [b4] "n"(B + 4), [b5] "n"(B + 5), [b6] "n"(B + 6), [b7] "n"(B + 7));
 }
 
-__device__ inline float fload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-
 __global__ __launch_bounds__(256) void h32_kernel(int Pp, int Xb, int64_t ldi, int64_t nI, const float* __restrict__ E,
                                                   const float* __restrict__ F, const float* __restrict__ G,
                                                   double* __restrict__ H, const uint32_t* __restrict__ tiles,
