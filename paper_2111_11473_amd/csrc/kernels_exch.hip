@@ -62,8 +62,9 @@ __global__ __launch_bounds__(NT, OB <= 4 ? 3 : 1) void exch_kernel(int64_t o, in
   constexpr int NRX = (OP * BJ) / NT;     // Rx / xo slice elements per thread
   constexpr int NZ = (BI * BJ) / NT;      // z slice elements per thread
   static_assert((OP * BJ) % NT == 0, "whole slices per thread");
-  // row pitches (elements) of the LDS slices
-  constexpr int PR = F32 ? BJ + 4 : BJ, PJ = F32 ? OP + 4 : OP + 1, PZ = F32 ? BI + 4 : BI;
+  // row pitches (elements) of the LDS slices; the transposed stores of xo and z go to rows of an
+  // odd FP64 pitch, so the 16 rows a wave's consecutive lanes write fall on distinct banks
+  constexpr int PR = F32 ? BJ + 4 : BJ, PJ = F32 ? OP + 4 : OP + 1, PZ = F32 ? BI + 4 : BI + 1;
   __shared__ T rx_s[2][OP * PR];  // [k][j]
   __shared__ T xj_s[2][BJ * PJ];  // [j][i]
   __shared__ T z_s[2][BJ * PZ];   // [j][I]
