@@ -90,3 +90,15 @@ def test_memory_plans_of_the_workloads():
     c = synth.CONFIGS["paper"]
     with pytest.raises(thc.ThcError, match="THC_ENOMEM"):
         thc.plan_query(c.o, c.v, c.nL, c.nP, c.nQ, 270e9, synthetic=True, precision=1)
+
+
+def test_mixed_plan_shares_the_fp64_buffers():
+    """The mixed path's FP32 E, F and G live in the FP64 buffers (a residual uses one precision or
+    the other), so its plan walks the same grid-point chunks as the FP64 one; it only adds the
+    FP32 H-kernel's tile table (a few bytes per tile)."""
+    from paper_2111_11473_amd import synth, thc
+    c = synth.CONFIGS["fp64"]
+    p0 = thc.plan_query(c.o, c.v, c.nL, c.nP, c.nQ, 270e9, precision=0)
+    p1 = thc.plan_query(c.o, c.v, c.nL, c.nP, c.nQ, 270e9, precision=1)
+    assert (p1["i_chunk"], p1["x_block"], p1["x7_chunk"]) == (p0["i_chunk"], p0["x_block"], p0["x7_chunk"])
+    assert 0 <= p1["device_bytes"] - p0["device_bytes"] <= 4 * 2 * p0["h_tiles"] + 64 * 1024 * 1024
