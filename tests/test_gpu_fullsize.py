@@ -86,3 +86,31 @@ def test_residual_symmetric_and_blocking_invariant(full):
     d1 = np.abs(a1 - b1).max() / np.abs(a1).max()
     _say("blocking difference", d, d1)
     assert d < 1e-11 and d1 < 1e-11
+
+
+def test_mixed_residual_at_full_size_within_bound(full):
+    """Both mixed-precision modes at the benchmark workload, in the launch configuration the bench
+    times (the FP32 H-kernel over 63 generations of 16 x 16 block pairs per grid-point chunk, four
+    chunks): the projected and singles residuals stay within the mixed bound (5e-5 of the largest
+    element) of the FP64 residual, itself checked above."""
+    import torch
+    thc, cfg, s, dev, ctx, Z0 = full
+    rng = np.random.default_rng(12)
+    R = rng.standard_normal(Z0.shape)
+    Z = Z0 + 0.2 * np.abs(Z0).max() * (R + R.T)
+    t1 = 0.01 * rng.standard_normal((cfg.o, cfg.v))
+    Zd, t1d = torch.from_numpy(Z).to("cuda"), torch.from_numpy(t1).to("cuda")
+    a, a1 = ctx.residual(Zd, t1d)
+    a, a1 = a.cpu().numpy(), a1.cpu().numpy()
+    for prec in (1, 2):
+        _say("mixed residual, precision", prec)
+        c = thc.THC(cfg.o, cfg.v, cfg.nL, cfg.nP, cfg.nQ, precision=prec)
+        c.build_factors(dev["L"], dev["eps"], dev["Xo"], dev["Xv"], dev["xo"], dev["xv"])
+        assert c.plan()["i_chunks"] == ctx.plan()["i_chunks"]
+        b, b1 = c.residual(Zd, t1d)
+        b, b1 = b.cpu().numpy(), b1.cpu().numpy()
+        c.close()
+        d = np.abs(a - b).max() / np.abs(a).max()
+        d1 = np.abs(a1 - b1).max() / np.abs(a1).max()
+        _say("  relative difference", d, d1)
+        assert d < 5e-5 and d1 < 5e-5
