@@ -6,8 +6,9 @@ quantities it computes through the factors, each pinned against the dense oracle
 systems (tests/test_oracle.py):
   - the residual at zero amplitudes is the projected driver M^T M (every other term vanishes);
   - the energy of the MP2 guess from the factors (Coulomb and exchange per Cholesky vector);
-and properties that hold at any size: the residual of a symmetric core is symmetric, and it
-does not depend on the blocking of the Cholesky pass, the grid-point chunk or the X block."""
+and properties that hold at any size: the residual of a symmetric core is symmetric, it does not
+depend on the blocking of the Cholesky pass, the grid-point chunk or the X block, and both
+mixed-precision modes stay within their error bound of the FP64 residual."""
 import numpy as np
 import pytest
 
