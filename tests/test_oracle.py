@@ -8,6 +8,7 @@ import oracle
 from oracle import ccsd
 from paper_2111_11473_amd import synth
 import spinorb_ccsd as so
+from fci_two_electron import two_electron_fci
 
 
 def _random_state(o, v, seed, scale=0.05):
@@ -101,31 +102,6 @@ def test_complete_basis_solve_equals_spin_orbital_ccsd():
     assert np.abs(R2).max() < 1e-9
 
 
-def _two_electron_fci(eps, L):
-    """Singlet full CI of one doubly occupied orbital's two electrons, built from the Cholesky
-    vectors alone: the one-electron operator is the Fock matrix minus the closed-shell mean field
-    of the occupied orbital, the Hamiltonian on spatial pair functions is h x 1 + 1 x h + (pr|qs),
-    restricted to the symmetric (singlet) pairs.  Returns the correlation energy of the state
-    dominated by the reference, and the MP2 energy for scale."""
-    n = eps.size
-    g = np.einsum("Apq,Ars->pqrs", L, L)
-    h = np.diag(eps) - (2.0 * g[:, :, 0, 0] - g[:, 0, 0, :])
-    rows = []
-    for p in range(n):
-        for q in range(p, n):
-            c = np.zeros((n, n))
-            c[p, q] = c[q, p] = 1.0 if p == q else 1.0 / np.sqrt(2.0)
-            rows.append(c.ravel())
-    C = np.array(rows)  # first row: the reference |0 0>
-    H = np.kron(h, np.eye(n)) + np.kron(np.eye(n), h) + g.transpose(0, 2, 1, 3).reshape(n * n, n * n)
-    Hs = C @ H @ C.T
-    w, U = np.linalg.eigh(Hs)
-    k = int(np.argmax(np.abs(U[0])))
-    emp2 = sum((L[:, 0, a] @ L[:, 0, b]) ** 2 / (2 * eps[0] - eps[a] - eps[b])
-               for a in range(1, n) for b in range(1, n))
-    return w[k] - Hs[0, 0], emp2
-
-
 @pytest.mark.parametrize("v,seed,scale", [(4, 5, 1.0), (5, 3, 2.0), (6, 8, 2.0)])
 def test_two_electron_ccsd_is_full_ci(v, seed, scale):
     """CCSD is exact for two electrons: in the complete pair and ERI bases the converged
@@ -136,7 +112,7 @@ def test_two_electron_ccsd_is_full_ci(v, seed, scale):
     eps, L = s["eps"], s["L"] * scale
     r = oracle.solve(eps, L, s["Xo"], s["Xv"], s["xo"], s["xv"], tol=1e-12, tol_e=1e-13, maxit=200)
     assert r.converged
-    e_fci, emp2 = _two_electron_fci(eps, L)
+    e_fci, emp2 = two_electron_fci(eps, L)
     assert abs(r.energy - e_fci) < 1e-11 * max(1.0, abs(e_fci))
     assert abs(e_fci - emp2) > 1e-4
 
