@@ -177,21 +177,24 @@ def test_converged_energy_matches_oracle(thc, singles):
     assert abs(it - r.iterations) <= 2
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2])
 @pytest.mark.parametrize("v,seed", [(5, 3), (6, 8), (12, 6)])
-def test_two_electron_solve_is_full_ci(thc, v, seed):
+def test_two_electron_solve_is_full_ci(thc, v, seed, precision):
     """End to end on the device: one doubly occupied orbital with complete pair and ERI bases
     (nP = nQ = o v), solved by thc_iterate, gives the singlet full-CI correlation energy (CCSD is
     exact for two electrons), from a diagonalization that shares nothing with the oracle or the
-    library; MP2 is 0.02-0.08 Eh away at these systems."""
+    library; MP2 is 0.02-0.08 Eh away at these systems.  The mixed-precision solves (FP32 MFMA,
+    split-BF16) finish with FP64 residuals, so they reach the same energy."""
     cfg = synth.Config("fci", 1, v, 3 * (1 + v), v, v, 30.0, seed)
     s = synth.make_system(cfg)
     Xo, Xv = synth.complete_basis(1, v)
-    _say("two-electron full CI, v", v, "seed", seed)
-    ctx = thc.THC(1, v, cfg.nL, v, v, singles=True, tol_energy=1e-12)
+    _say("two-electron full CI, v", v, "seed", seed, "precision", precision)
+    ctx = thc.THC(1, v, cfg.nL, v, v, singles=True, tol_energy=1e-12, precision=precision)
     ctx.build_factors(_dev(s["L"]), _dev(s["eps"]), _dev(Xo), _dev(Xv), _dev(Xo), _dev(Xv))
     it, rn, ok = ctx.iterate(tol=1e-10, maxit=200)
     e_fci, emp2 = two_electron_fci(s["eps"], s["L"])
-    _say("  iterations", it, "energy", ctx.energy(), "full CI", e_fci, "MP2", emp2)
+    _say("  iterations", it, "of them mixed", sum(ctx.history_precision()), "energy", ctx.energy(), "full CI", e_fci,
+         "MP2", emp2)
     assert ok
     assert abs(ctx.energy() - e_fci) < 1e-10
     assert abs(e_fci - emp2) > 1e-2
