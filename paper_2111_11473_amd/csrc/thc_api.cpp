@@ -1897,8 +1897,9 @@ int thc_iterate(thc_ctx* ctx, double tol, int maxit, int* iters, double* rnorm) 
   ctx->hist_r.clear();
   ctx->hist_t.clear();
   const auto t_start = std::chrono::steady_clock::now();
-  // precision ladder (mixed precision): FP32-MFMA residuals until their norm has dropped 1e4-fold,
-  // is within 10 tol, or stops decreasing; then FP64 residuals, which alone may declare convergence
+  // precision ladder (mixed precision): reduced-precision residuals until their norm has dropped
+  // 1e4-fold, is within 10 tol, stops decreasing, or is predicted below tol for the next iteration;
+  // then FP64 residuals, which alone may declare convergence
   bool mixed_phase = ctx->opt.precision >= 1;
   double rn_first = -1.0, rn_prev = 0.0;
   int mixed_its = 0;
