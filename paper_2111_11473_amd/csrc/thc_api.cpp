@@ -2394,7 +2394,7 @@ int thc_working(thc_ctx* ctx, double* Th, double* sigma_hat) {
 
 int thc_set_guess_network(thc_ctx* ctx, thc_mlp* net) {
   if (!ctx) return THC_EINVAL;
-  if (net && (net->n_in != 10 || net->w != 256 || net->n_out < 1 || net->n_out > 2 || !net->wb)) {
+  if (net && (net->n_in != THC_GUESS_FEATURES || net->w != 256 || net->n_out < 1 || net->n_out > 2 || !net->wb)) {
     ctx->err = "the guess network needs 10 inputs, width 256 and 1 or 2 outputs";
     return THC_EINVAL;
   }
