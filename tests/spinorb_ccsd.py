@@ -138,3 +138,18 @@ def solve(eps, L, o, tol=1e-11, maxit=200):
             return E, t1, t2
         E_old = E
     raise RuntimeError("spin-orbital CCSD did not converge")
+
+
+def mp3_energy(f, anti, nocc):
+    """Third-order Møller–Plesset energy from antisymmetrized spin-orbital integrals and a
+    diagonal Fock matrix, in the standard three-term closed form (Szabo & Ostlund, Modern
+    Quantum Chemistry, Eq. 6.74): particle ladder, hole ladder and ring, each over two MP2
+    denominators."""
+    e = np.diag(f)
+    eo, ev = e[:nocc], e[nocc:]
+    D = eo[:, None, None, None] + eo[None, :, None, None] - ev[None, None, :, None] - ev[None, None, None, :]
+    t = anti[:nocc, :nocc, nocc:, nocc:] / D
+    ladder_p = 0.125 * np.einsum("ijab,abcd,ijcd->", t, anti[nocc:, nocc:, nocc:, nocc:], t)
+    ladder_h = 0.125 * np.einsum("ijab,klij,klab->", t, anti[:nocc, :nocc, :nocc, :nocc], t)
+    ring = np.einsum("ijab,kbcj,ikac->", t, anti[:nocc, nocc:, nocc:, :nocc], t)
+    return ladder_p + ladder_h + ring

@@ -1,6 +1,7 @@
 """Pins of the FP64 oracle against facts that do not come from the oracle itself:
-an independent spin-orbital CCSD, two-electron full CI, the MP2 closed form, the complete-pair-basis limit,
-least-squares identities of the ERI fit, exact invariances and the Galerkin property."""
+an independent spin-orbital CCSD, two-electron full CI, the MP2 and MP3 closed forms, the
+complete-pair-basis limit, least-squares identities of the ERI fit, exact invariances and the
+Galerkin property."""
 import numpy as np
 import pytest
 
@@ -100,6 +101,27 @@ def test_complete_basis_solve_equals_spin_orbital_ccsd():
     z, _ = oracle.eri_fit(L, o, s["xo"], s["xv"])
     R2 = ccsd.doubles_residual(eps, L, r.t1, t2, oracle.eri_thc_dense(s["xo"], s["xv"], z))
     assert np.abs(R2).max() < 1e-9
+
+
+@pytest.mark.parametrize("o,v,seed", [(2, 4, 1), (3, 5, 2), (2, 6, 3)])
+def test_linear_terms_give_the_mp3_energy(o, v, seed):
+    """At t1 = 0 the doubles residual is V + L(t) + Q(t) with L linear and Q quadratic, so its
+    odd part (R(t) - R(-t)) / 2 is L(t) alone.  Without its Fock part (Delta t) and contracted
+    with 2 t - t' at the MP2 amplitudes it is the MP3 energy, which must equal the textbook
+    spin-orbital closed form.  Pins every linear term group (ladders, rings, Eq. 31 and the Fock
+    part: halving any of them misses by 1% or more)."""
+    s = _system(o, v, 3 * (o + v), 4, 4, seed)
+    eps, L = s["eps"], s["L"] * 2.0
+    t = oracle.mp2_amplitudes(eps, L, o)
+    z1 = np.zeros((o, v))
+    eo, ev = eps[:o], eps[o:]
+    delta = -eo[:, None, None, None] - eo[None, :, None, None] + ev[None, None, :, None] + ev[None, None, None, :]
+    lin = 0.5 * (ccsd.doubles_residual(eps, L, z1, t) - ccsd.doubles_residual(eps, L, z1, -t)) - delta * t
+    e3 = np.sum((2 * t - t.transpose(0, 1, 3, 2)) * lin)
+    f, anti, no = so.spin_orbital_system(eps, L, o)
+    e3_ref = so.mp3_energy(f, anti, no)
+    assert abs(e3 - e3_ref) < 1e-12 * abs(e3_ref)
+    assert abs(e3_ref) > 1e-3
 
 
 @pytest.mark.parametrize("v,seed,scale", [(4, 5, 1.0), (5, 3, 2.0), (6, 8, 2.0)])
