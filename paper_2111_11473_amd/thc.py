@@ -185,11 +185,19 @@ def _stream():
 def dgemm(A, B, C_out, transA=False, transB=False, alpha=1.0, beta=0.0):
     """C = alpha op(A) op(B) + beta C on the library's MFMA kernel (2-D or batched 3-D tensors)."""
     lib = load()
+    if not (A.dim() == B.dim() == C_out.dim()) or A.dim() not in (2, 3):
+        raise ValueError("A, B and C must all be 2-D, or all 3-D (a batch)")
     batched = A.dim() == 3
     Am, Bm, Cm = (A, B, C_out) if batched else (A[None], B[None], C_out[None])
     nb = Cm.shape[0]
     M, N = Cm.shape[1], Cm.shape[2]
     K = Am.shape[1] if transA else Am.shape[2]
+    rows_a = Am.shape[2] if transA else Am.shape[1]
+    k_b, cols_b = (Bm.shape[2], Bm.shape[1]) if transB else (Bm.shape[1], Bm.shape[2])
+    if rows_a != M or cols_b != N or k_b != K:
+        raise ValueError(f"op(A) is {rows_a} x {K} and op(B) {k_b} x {cols_b}, C is {M} x {N}")
+    if Am.shape[0] not in (1, nb) or Bm.shape[0] not in (1, nb):
+        raise ValueError("A and B must hold one matrix or as many as C")
     sA = Am.stride(0) if Am.shape[0] > 1 else 0
     sB = Bm.stride(0) if Bm.shape[0] > 1 else 0
     rc = lib.thc_dgemm(int(transA), int(transB), M, N, K, alpha, _ptr(A, name="A"), Am.shape[2], sA, _ptr(B, name="B"),

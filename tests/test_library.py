@@ -51,6 +51,24 @@ def test_binding_refuses_host_tensors():
         thc._ptr(torch.zeros(3, dtype=torch.float64))
 
 
+@pytest.mark.parametrize("a,b,c,tA,tB", [
+    ((4, 5), (6, 7), (4, 7), False, False),     # K of A and B differ
+    ((4, 5), (5, 7), (4, 8), False, False),     # C too wide
+    ((5, 4), (5, 7), (5, 7), True, False),      # op(A) has 4 rows, C 5
+    ((4, 5), (5, 7), (4, 7), False, True),      # op(B) is 7 x 5
+    ((2, 4, 5), (3, 5, 7), (2, 4, 7), False, False),  # B batch neither 1 nor C's
+    ((4, 5), (1, 5, 7), (4, 7), False, False),  # mixed 2-D and 3-D
+])
+def test_dgemm_binding_checks_shapes(a, b, c, tA, tB):
+    """Operand shapes that do not match are refused before any pointer reaches the library (the C
+    entry point takes sizes and leading dimensions only and cannot check buffer lengths)."""
+    import torch
+    from paper_2111_11473_amd import thc
+    z = lambda s: torch.zeros(s, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        thc.dgemm(z(a), z(b), z(c), transA=tA, transB=tB)
+
+
 @pytest.mark.parametrize("field,value", [("o", 0), ("v", -1), ("nL", 0), ("nP", 0), ("nQ", 0),
                                          ("nP", 10 * 40 + 1), ("nQ", 10 * 40 + 1), ("precision", 3),
                                          ("diis_max", 17), ("flags", 1 << 6), ("x_block", -64),
