@@ -1,5 +1,6 @@
 """Host-only checks of the C-ABI library: it is built for gfx950, loads, and exports exactly
-the entry points include/thc.h declares (no GPU call is made)."""
+the entry points include/thc.h declares; the binding and the library refuse bad arguments; the
+working-memory planner's plans (no GPU call is made)."""
 import ctypes
 import os
 import re
@@ -120,3 +121,50 @@ def test_mixed_plan_shares_the_fp64_buffers():
     p1 = thc.plan_query(c.o, c.v, c.nL, c.nP, c.nQ, 270e9, precision=1)
     assert (p1["i_chunk"], p1["x_block"], p1["x7_chunk"]) == (p0["i_chunk"], p0["x_block"], p0["x7_chunk"])
     assert 0 <= p1["device_bytes"] - p0["device_bytes"] <= 4 * 2 * p0["h_tiles"] + 64 * 1024 * 1024
+
+
+def test_planner_properties_over_random_sizes():
+    """The working-memory planner over 600 seeded random problems, budgets from 0.1 to 270 GB,
+    both precisions, caller or synthetic inputs and either Alg. 6 or Alg. 4-5: every plan it
+    returns needs no more than its budget; planning again for exactly the bytes it reported
+    succeeds within them (what a caller's workspace of that size relies on); every block and chunk
+    is within its loop's range; the H-kernel table holds every (Y <= Z) block pair and Z slice of
+    each X tile in whole generations; anything else is THC_ENOMEM."""
+    import random
+    from paper_2111_11473_amd import thc
+    rng = random.Random(7)
+    fitted = 0
+    for _ in range(600):
+        o = rng.choice([1, 2, 5, 10, 30, 50, 80, 120, 200, 350])
+        v = max(1, int(o * rng.uniform(1, 12)))
+        nL = max(1, int((o + v) * rng.uniform(0.5, 4)))
+        nP = max(1, min(o * v, int(rng.uniform(0.2, 25) * o)))
+        nQ = max(1, min(o * v, int(nP * rng.uniform(1, 3))))
+        budget = 10 ** rng.uniform(8, 11.43)
+        kw = dict(synthetic=rng.random() < 0.5, precision=rng.choice([0, 1]),
+                  flags=rng.choice([0, 0, thc.FLAG_QUARTIC, thc.FLAG_QUINTIC]))
+        try:
+            p = thc.plan_query(o, v, nL, nP, nQ, budget, **kw)
+        except thc.ThcError as e:
+            assert e.rc == thc.THC_ENOMEM, e
+            continue
+        fitted += 1
+        case = (o, v, nL, nP, nQ, budget, kw)
+        assert 0 < p["device_bytes"] <= budget, case
+        again = thc.plan_query(o, v, nL, nP, nQ, p["device_bytes"], **kw)
+        assert again["device_bytes"] <= p["device_bytes"], case
+        assert 1 <= p["a_block"] <= nL and p["alg1_tile"] in (64, 128) and 1 <= p["alg1_splits"] <= 16, case
+        assert 1 <= p["x_chunk"] <= nP and 1 <= p["x7_chunk"] <= nP, case
+        assert p["exchange_fused"] == int(o <= 200), case
+        assert p["lvv_resident"] == 1 or kw["synthetic"], case
+        if p["quintic"]:
+            assert kw["flags"] != thc.FLAG_QUARTIC, case
+            assert 1 <= p["q_jchunk"] <= o and 1 <= p["q_pairs"] <= max(o, v), case
+        else:
+            assert kw["flags"] != thc.FLAG_QUINTIC, case
+            p64, nB = -(-nP // 64) * 64, -(-nP // 16)
+            assert p["x_block"] % 64 == 0 and 64 <= p["x_block"] <= p64, case
+            assert 1 <= p["i_chunk"] <= nQ, case
+            assert p["h_tiles"] == nB * (nB + 1) // 2 * 2 * (p["x_block"] // 64), case
+            assert 0 <= p["h_generations"] * 8 * 64 - p["h_tiles"] < 8 * 64, case
+    assert fitted > 300
