@@ -52,6 +52,19 @@ def test_binding_refuses_host_tensors():
         thc._ptr(torch.zeros(3, dtype=torch.float64))
 
 
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """With no built library there is no fallback: loading it raises ImportError naming the build
+    step (in a fresh interpreter, since a loaded library is kept for the process)."""
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2111_11473_amd import thc\n"
+            "try:\n    thc.load(%r)\nexcept ImportError as e:\n    print('ImportError', e)\n") % (
+                ROOT, str(tmp_path / "libthc.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("ImportError") and "build" in r.stdout
+
+
 @pytest.mark.parametrize("a,b,c,tA,tB", [
     ((4, 5), (6, 7), (4, 7), False, False),     # K of A and B differ
     ((4, 5), (5, 7), (4, 8), False, False),     # C too wide
