@@ -348,6 +348,30 @@ def test_mp2_density_of_a_single_pair_amplitude():
     assert abs(Doo[0, 0] + 2 * 0.09) < 1e-15 and abs(Dvv[0, 0] - 2 * 0.09) < 1e-15
 
 
+@pytest.mark.parametrize("o,v,seed", [(3, 5, 2), (2, 7, 4), (4, 4, 9)])
+def test_mp2_density_diagonal_is_the_orbital_energy_derivative(o, v, seed):
+    """At the MP2 amplitudes the unrelaxed density's diagonal is the derivative of the MP2 energy
+    with respect to each orbital energy, D_pp = dE_MP2/d eps_p (the energy is sum V (2V - V') / D
+    and eps_p enters only the denominators).  The energy here is the closed form over the Cholesky
+    integrals, differentiated by central differences; the density is the oracle's, of the
+    least-squares MP2 core in the complete pair basis (where it reproduces the MP2 amplitudes)."""
+    s = _complete(_system(o, v, 3 * (o + v), 4, 4, seed))
+    eps, L = s["eps"], s["L"] * 2.0
+
+    def emp2(e):
+        Lov = L[:, :o, o:]
+        V = np.einsum("Aia,Ajb->iajb", Lov, Lov)
+        eo, ev = e[:o], e[o:]
+        D = eo[:, None, None, None] - ev[None, :, None, None] + eo[None, None, :, None] - ev[None, None, None, :]
+        return np.sum(V * (2 * V - V.transpose(0, 3, 2, 1)) / D)
+
+    Doo, Dvv = oracle.mp2_density(s["Xo"], s["Xv"], oracle.mp2_guess(eps, L, s["Xo"], s["Xv"]))
+    h, unit = 1e-5, np.eye(o + v)
+    grad = np.array([(emp2(eps + h * unit[p]) - emp2(eps - h * unit[p])) / (2 * h) for p in range(o + v)])
+    diag = np.concatenate([np.diag(Doo), np.diag(Dvv)])
+    assert np.abs(diag - grad).max() < 1e-8 * np.abs(grad).max()
+
+
 def _cp_problem(seed, I=5, J=6, K=7, n=3, noise=0.0):
     rng = np.random.default_rng(seed)
     X, Y, Z = rng.standard_normal((I, n)), rng.standard_normal((J, n)), rng.standard_normal((K, n))
