@@ -279,6 +279,35 @@ def test_energy_from_factors_matches_dense_energy():
     assert abs(e - e_ref) < 1e-12 * max(1.0, abs(e_ref))
 
 
+@pytest.mark.parametrize("n,seed", [(5, 1), (7, 2), (10, 3)])
+def test_diis_terminates_on_a_linear_problem(n, seed):
+    """The DIIS extrapolation of the solver (Pulay: the combination of the updated vectors whose
+    coefficients sum to one and minimize the combined error) over Jacobi steps of a linear
+    n-dimensional problem is Anderson acceleration, equivalent to GMRES: with the whole subspace
+    kept it solves the problem exactly after n + 1 residuals, where Jacobi alone is still far off.
+    A wrong sign, constraint or overlap matrix loses the finite termination."""
+    from oracle.thc import _diis_extrapolate
+    rng = np.random.default_rng(seed)
+    D = rng.uniform(1.0, 2.0, n)
+    A = np.diag(D) + 0.35 * rng.standard_normal((n, n)) * np.sqrt(D)[:, None]
+    b = rng.standard_normal(n)
+
+    def residual_after(steps, diis):
+        x, vecs, errs = np.zeros(n), [], []
+        for _ in range(steps):
+            e = -(A @ x - b) / D  # the Jacobi step
+            x = x + e
+            if diis:
+                vecs.append(x.copy())
+                errs.append(e)
+                if len(vecs) >= 2:
+                    x = _diis_extrapolate(vecs, errs)
+        return np.linalg.norm(A @ x - b) / np.linalg.norm(b)
+
+    assert residual_after(n + 1, True) < 1e-12
+    assert residual_after(n + 1, False) > 1e-3
+
+
 def test_diis_drops_oldest_vectors_of_an_ill_conditioned_subspace():
     """DIIS conditioning rule: the oldest vectors go while the error overlap matrix has a
     condition number above 1e12 (two equal errors make it singular); a well-conditioned
