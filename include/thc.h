@@ -12,8 +12,9 @@
  *
  * Conventions
  *  - Every array argument is a DEVICE pointer (memory on the GPU the context was created on),
- *    row-major, FP64, owned by the caller; the library copies what it keeps.  Scalars returned
- *    through pointers (energies, norms, iteration counts) are HOST pointers.
+ *    row-major, FP64 (FP32 where the declaration takes float), owned by the caller; the library
+ *    copies what it keeps.  The few host arrays are marked HOST or "host" at their declaration.
+ *    Scalars returned through pointers (energies, norms, iteration counts) are HOST pointers.
  *  - Sizes: o occupied, v virtual, n = o + v orbitals, nL Cholesky vectors, nP amplitude THC
  *    rank, nQ ERI THC grid points.
  *  - All work is issued on the stream given to thc_create (a hipStream_t, e.g. torch's current
