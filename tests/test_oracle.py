@@ -254,6 +254,22 @@ def test_generator_distributions():
     assert abs(s1["Xo"].var() * cfg.nP - 1) < 0.1
 
 
+def test_learned_set_recipe():
+    """The learned-guess set: 256 systems with o = 30 + (a hash of s) mod 51, v = 9o, nL = 30o,
+    nP = 20o, nQ = 50o and seed 2000 + s; every occupied count of [30, 80] occurs, and both the
+    200 training systems and the 56 held out span the range."""
+    cfgs = [synth.learned_config(s) for s in range(256)]
+    for c in cfgs:
+        assert 30 <= c.o <= 80 and (c.v, c.nL, c.nP, c.nQ) == (9 * c.o, 30 * c.o, 20 * c.o, 50 * c.o)
+        assert c.nP <= c.o * c.v and c.nQ <= c.o * c.v
+    assert [c.seed for c in cfgs] == list(range(2000, 2256))
+    occ = [c.o for c in cfgs]
+    assert set(occ) == set(range(30, 81))
+    assert min(occ[:200]) == 30 and max(occ[:200]) == 80
+    assert min(occ[200:]) <= 35 and max(occ[200:]) >= 75
+    assert occ == [synth.learned_config(s).o for s in range(256)]  # deterministic
+
+
 def test_driver_projection_is_the_zero_amplitude_residual():
     """At t1 = 0, t2 = 0 every term of the dense residual but the driver (ia|jb) vanishes;
     the factorized contraction M^T M must equal the dense residual projected (Eq. 6)."""
