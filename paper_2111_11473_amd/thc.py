@@ -42,6 +42,7 @@ SYMBOLS = ["thc_create", "thc_build_factors", "thc_residual", "thc_residual_term
            "thc_mlp_forward", "thc_mlp_forward_noalloc", "thc_mlp_loss_grad", "thc_mlp_train_step", "thc_mlp_infer", "thc_mlp_last_error",
            "thc_mlp_destroy"]
 GUESS_FEATURES = 10
+MLP_SCRATCH_BYTES = 32 << 20  # the allocation-free forward pass's fixed device array per GPU
 
 
 class Options(C.Structure):

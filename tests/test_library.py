@@ -181,3 +181,47 @@ def test_planner_properties_over_random_sizes():
             assert p["h_tiles"] == nB * (nB + 1) // 2 * 2 * (p["x_block"] // 64), case
             assert 0 <= p["h_generations"] * 8 * 64 - p["h_tiles"] < 8 * 64, case
     assert fitted > 300
+
+
+def test_binding_matches_the_c_header(tmp_path):
+    """The binding's ctypes structures have the C header's layout (every field's offset and size,
+    and each structure's size), and its constants equal the header's #defines -- checked by a C
+    program compiled against include/thc.h as strict C99 (the header is plain C)."""
+    import shutil
+    from paper_2111_11473_amd import thc
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    structs = {"thc_options": thc.Options, "thc_plan_info": thc.PlanInfo, "thc_synth_spec": thc.SynthSpec}
+    names = re.findall(r"^#define (THC_[A-Z_0-9]+)[ \t]+\S", open(HEADER).read(), flags=re.M)
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "thc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("size {cname} %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("field {cname}.{field} %zu %zu\\n", offsetof({cname}, {field}), '
+                         f'sizeof((({cname}*)0)->{field}));')
+    for n in names:
+        lines.append(f'  printf("const {n} %lld\\n", (long long)({n}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    r = subprocess.run([gcc, "-std=c99", "-pedantic", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src),
+                        "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    seen_consts = 0
+    for line in filter(None, out):
+        kind, what, *vals = line.split()
+        if kind == "size":
+            assert int(vals[0]) == ctypes.sizeof(structs[what]), line
+        elif kind == "field":
+            cname, field = what.split(".")
+            desc = getattr(structs[cname], field)
+            assert (int(vals[0]), int(vals[1])) == (desc.offset, desc.size), line
+        else:
+            py = what[4:] if not what.startswith(("THC_O", "THC_E")) else what  # THC_TERM_EQ28 -> TERM_EQ28
+            if hasattr(thc, py):
+                assert getattr(thc, py) == int(vals[0]), line
+                seen_consts += 1
+    assert seen_consts == len(names)
