@@ -225,3 +225,29 @@ def test_binding_matches_the_c_header(tmp_path):
                 assert getattr(thc, py) == int(vals[0]), line
                 seen_consts += 1
     assert seen_consts == len(names)
+
+
+def test_binding_prototypes_match_the_c_header():
+    """Every function of include/thc.h is declared to ctypes with the header's argument list:
+    the same number of arguments, pointers where the header has pointers, and the same integer
+    width and signedness or floating type for each scalar."""
+    import ctypes as C
+    from paper_2111_11473_amd import thc
+    lib = thc.load()
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    scalars = {"int64_t": C.c_int64, "int32_t": C.c_int32, "int": C.c_int, "uint32_t": C.c_uint32,
+               "uint64_t": C.c_uint64, "double": C.c_double, "float": C.c_float, "size_t": C.c_size_t}
+    protos = re.findall(r"\b(?:int|void|const char\s*\*)\s*(thc_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", txt)
+    assert {p[0] for p in protos} == set(_declared())
+    for name, args in protos:
+        params = [a.strip() for a in args.split(",") if a.strip() and a.strip() != "void"]
+        declared = getattr(lib, name).argtypes
+        assert declared is not None and len(declared) == len(params), (name, params, declared)
+        for p, t in zip(params, declared):
+            if "*" in p:
+                assert t in (C.c_void_p, C.c_char_p) or issubclass(t, C._Pointer), (name, p, t)
+            else:
+                ctype = " ".join(p.split()[:-1]).replace("const ", "")
+                want = scalars[ctype]
+                assert C.sizeof(t) == C.sizeof(want) and t(-1).value == want(-1).value, (name, p, t)
+                assert isinstance(t(0).value, float) == isinstance(want(0).value, float), (name, p, t)
