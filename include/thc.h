@@ -325,7 +325,10 @@ int thc_profile_get(thc_ctx* ctx, const char* name, double* total_ms, int64_t* l
 int thc_profile_flops(const thc_ctx* ctx, double* fp64_flops, double* fp32_flops, double* bf16x3_flops);
 
 /* The library's FP64 MFMA GEMM (exposed for testing): C = alpha op(A) op(B) + beta C,
- * row-major, op = transpose when trans* != 0, batched with element strides sA, sB, sC. */
+ * row-major, op = transpose when trans* != 0, batched with element strides sA, sB, sC (0: one
+ * matrix shared by the batch).  Device arrays.  M, N or batch 0: nothing is done.  THC_EINVAL
+ * for negative sizes or strides, a NULL operand, or a leading dimension shorter than its rows
+ * (lda < K, or M when transA; ldb < N, or K when transB; ldc < N). */
 int thc_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
               int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C,
               int64_t ldc, int64_t sC, int64_t batch, void* stream);

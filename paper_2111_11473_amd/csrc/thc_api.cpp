@@ -2334,7 +2334,11 @@ int thc_cp_als(const double* A, int64_t I, int64_t J, int64_t K, int64_t n, cons
 int thc_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
               int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC,
               int64_t batch, void* stream) {
-  if (M < 0 || N < 0 || K < 0 || batch < 0) return THC_EINVAL;
+  if (M < 0 || N < 0 || K < 0 || batch < 0 || sA < 0 || sB < 0 || sC < 0) return THC_EINVAL;
+  if (M == 0 || N == 0 || batch == 0) return THC_OK;  // nothing to compute
+  // every row of op(A), op(B) and C within its leading dimension, and the operands present
+  if (!C || ldc < N || (K > 0 && (!A || !B || lda < (transA ? M : K) || ldb < (transB ? K : N))))
+    return THC_EINVAL;
   Gemm g = batched(mk(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc, alpha, beta), batch, sA, sB, sC);
   if (gemm_f64(g, (hipStream_t)stream) != hipSuccess) return THC_EDEVICE;
   return THC_OK;

@@ -251,3 +251,31 @@ def test_binding_prototypes_match_the_c_header():
                 want = scalars[ctype]
                 assert C.sizeof(t) == C.sizeof(want) and t(-1).value == want(-1).value, (name, p, t)
                 assert isinstance(t(0).value, float) == isinstance(want(0).value, float), (name, p, t)
+
+
+@pytest.mark.parametrize("case", ["lda", "ldb", "ldc", "ldaT", "ldbT", "nullA", "nullB", "nullC", "negK", "negStride"])
+def test_dgemm_entry_point_refuses_bad_arguments(lib, case):
+    """thc_dgemm refuses, before any launch, operands it could not address: a leading dimension
+    shorter than a row of op(A), op(B) or C, a missing operand, negative sizes or strides.  Run only
+    where there is no GPU: the operands are placeholder addresses, so a regression that let one of
+    these calls through must not reach a device."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("placeholder operand addresses are only passed where no GPU exists")
+    from paper_2111_11473_amd import thc
+    f = thc.load().thc_dgemm
+    a = dict(tA=0, tB=0, M=4, N=5, K=6, lda=6, ldb=5, ldc=5, sA=0, sB=0, sC=0, A=1, B=1, C=1)
+    a.update({"lda": dict(lda=5), "ldb": dict(ldb=4), "ldc": dict(ldc=4), "ldaT": dict(tA=1, lda=3),
+              "ldbT": dict(tB=1, ldb=5), "nullA": dict(A=0), "nullB": dict(B=0), "nullC": dict(C=0),
+              "negK": dict(K=-1), "negStride": dict(sC=-1)}[case])
+    p = lambda x: ctypes.c_void_p(0x10000 if x else None)
+    rc = f(a["tA"], a["tB"], a["M"], a["N"], a["K"], 1.0, p(a["A"]), a["lda"], a["sA"], p(a["B"]), a["ldb"],
+           a["sB"], 0.0, p(a["C"]), a["ldc"], a["sC"], 1, None)
+    assert rc == thc.THC_EINVAL
+
+
+def test_dgemm_entry_point_empty_product_is_a_no_op(lib):
+    from paper_2111_11473_amd import thc
+    f = thc.load().thc_dgemm
+    for M, N, nb in ((0, 5, 1), (4, 0, 1), (4, 5, 0)):
+        assert f(0, 0, M, N, 6, 1.0, None, 6, 0, None, 5, 0, 0.0, None, 5, 0, nb, None) == thc.THC_OK
